@@ -1,0 +1,159 @@
+/*
+ * dexel.h -- C ABI of libdexel: exact dilation / erosion of dexel shapes by a
+ * ball on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Chen, Panozzo, Dumas, "Half-Space Power Diagrams and Discrete
+ * Surface Offsets".  A dexel shape is a 2D grid of columns, each holding a
+ * sorted list of disjoint z-intervals (Sec. 3.1, "Dexel Representation").
+ * Dilation by a closed ball of radius r is the set of points within r of the
+ * shape (Sec. 3.1, "Dilation" equation); erosion is the complement of the
+ * dilated complement (Sec. 3.1, "Erosion"); opening and closing chain the two
+ * (Sec. 4, "Topological Cleaning").  The result is computed by the separable
+ * two-stage scheme of Sec. 3.3: an extrusion along x whose pieces carry the
+ * distance to their closest parent, then a dilation along y in which the
+ * pieces are weighted seeds (weight r^2 - dx^2) of a power diagram, then a
+ * per-column interval union.
+ *
+ * Data layout (CSR, all device memory, owned by the caller):
+ *   column id c = y * nx + x (x fastest; a grid row is one contiguous span)
+ *   col_ptr[c] .. col_ptr[c+1]  intervals of column c, col_ptr[0] = 0
+ *   z[2k], z[2k+1]              (z_in, z_out) of interval k, float32
+ * Canonical input (required): per column sorted, finite, z_in <= z_out and
+ * z_out_k < z_in_{k+1} (touching intervals are merged).  Zero-length
+ * intervals are allowed.  `z` must be 8-byte aligned.
+ *
+ * Geometry conventions: columns sit on the integer lattice with unit
+ * spacing; r and z are in the same unit.  The ball is closed (a column at
+ * lateral distance exactly r contributes its intervals unchanged).  Columns
+ * outside the grid contribute nothing to a dilation and impose nothing on an
+ * erosion (only in-grid columns are complemented).  z is unbounded.
+ * Erosion output keeps only intervals of positive length.
+ *
+ * Numerics: every output endpoint is one float32 rounding of a - h or b + h,
+ * where a, b are input endpoints (dilation) or input endpoints / +-inf
+ * (erosion) and h is the float32 rounding of the double square root of
+ * r^2 - d2 (d2 = integer squared lateral distance, r^2 formed exactly in
+ * double).  Overlap tests use exact float32 comparisons, so the output is
+ * the float32 canonical union of those chords, independent of the order or
+ * pruning of the work.
+ *
+ * Ownership: the library never allocates device memory.  Inputs, outputs and
+ * a workspace (size from dexel_workspace_size) are supplied by the caller.
+ * A context owns host-side state only (radius lookup tables, error text).
+ * One host thread per context at a time.
+ *
+ * Asynchrony and errors: host-detectable argument errors are returned before
+ * anything is enqueued.  Everything else runs on `stream` (a hipStream_t, or
+ * NULL for the default stream).  Device-detected conditions are written to
+ * *out->status (a dexel_status) and *out->nseg_out.  Without
+ * DEXEL_FLAG_SYNC the call returns DEXEL_OK meaning "enqueued"; with it, the
+ * call synchronises `stream` and returns the device status.
+ */
+#ifndef DEXEL_H
+#define DEXEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DEXEL_API_VERSION 1
+
+typedef enum {
+    DEXEL_OK = 0,
+    DEXEL_ERR_INVALID = -1,       /* bad argument (null pointer, size, r < 0 or not finite, ...) */
+    DEXEL_ERR_NOT_CANONICAL = -2, /* input failed validation (DEXEL_FLAG_VALIDATE)             */
+    DEXEL_ERR_CAPACITY = -3,      /* output needs more than cap_seg intervals; see nseg_out     */
+    DEXEL_ERR_WORKSPACE = -4,     /* workspace too small; see dexel_workspace_need               */
+    DEXEL_ERR_HIP = -5,           /* a HIP runtime call failed                                   */
+    DEXEL_ERR_UNSUPPORTED = -6    /* outside the supported range (e.g. r > 250)                  */
+} dexel_status;
+
+typedef enum { DEXEL_DILATE = 0, DEXEL_ERODE = 1, DEXEL_OPEN = 2, DEXEL_CLOSE = 3 } dexel_op;
+
+#define DEXEL_FLAG_SYNC 1u     /* synchronise the stream and return the device status   */
+#define DEXEL_FLAG_VALIDATE 2u /* check the input is canonical before computing          */
+
+typedef struct dexel_ctx dexel_ctx;
+
+/* Input grid (device pointers). */
+typedef struct {
+    int32_t nx, ny;         /* grid size, both >= 1                              */
+    int64_t nseg;           /* number of intervals = col_ptr[nx*ny]               */
+    const int64_t* col_ptr; /* [nx*ny + 1]                                        */
+    const float* z;         /* [2*nseg] (z_in, z_out) pairs                       */
+} dexel_grid_view;
+
+/* Output grid (device pointers), same nx, ny as the input. */
+typedef struct {
+    int32_t nx, ny;
+    int64_t cap_seg;   /* capacity of z in intervals                                        */
+    int64_t* col_ptr;  /* [nx*ny + 1], always written when the computation completes        */
+    float* z;          /* [2*cap_seg]; untouched if the result needs more than cap_seg       */
+    int64_t* nseg_out; /* device scalar: exact number of output intervals (also on overflow) */
+    int32_t* status;   /* device scalar: dexel_status of the enqueued work                   */
+} dexel_grid_out;
+
+/* One request of a batch: `op` is a dexel_op. */
+typedef struct {
+    dexel_grid_view in;
+    float r;
+    int32_t op;
+    dexel_grid_out out;
+} dexel_batch_item;
+
+/* Create a context on HIP device `device`.  Returns DEXEL_ERR_INVALID for a
+ * null `ctx`, DEXEL_ERR_HIP if the device cannot be selected. */
+dexel_status dexel_ctx_create(int device, dexel_ctx** ctx);
+void dexel_ctx_destroy(dexel_ctx* ctx);
+
+/* Bytes of workspace needed for one call of dexel_offset on `in` with radius
+ * r and operation op.  `cap_hint` is the capacity, in intervals, of each
+ * internal buffer; 0 picks a default from the input size (2 * nseg +
+ * 2 * nx * ny).  If a call ends with DEXEL_ERR_WORKSPACE, pass the value
+ * reported by dexel_workspace_need as the hint and retry.  Only nx, ny and
+ * nseg of `in` are read (no device access). */
+dexel_status dexel_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, float r, int32_t op,
+                                  int64_t cap_hint, size_t* bytes);
+
+/* After a call completed (stream synchronised), read the capacity hint the
+ * call needed from the workspace header (a small device-to-host copy). */
+dexel_status dexel_workspace_need(dexel_ctx* ctx, const void* ws, int64_t* cap_hint);
+
+/* Dilation by the closed ball of radius r (Sec. 3.1 "Dilation"; computed as
+ * in Sec. 3.3).  `in` and `out` must not alias; ws/ws_bytes from
+ * dexel_workspace_size with op = DEXEL_DILATE. */
+dexel_status dexel_dilate(dexel_ctx* ctx, const dexel_grid_view* in, float r, dexel_grid_out* out,
+                          void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
+/* Erosion: complement, dilate, complement (Sec. 3.1 "Erosion"). */
+dexel_status dexel_erode(dexel_ctx* ctx, const dexel_grid_view* in, float r, dexel_grid_out* out,
+                         void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
+/* Any dexel_op; DEXEL_OPEN = dilate(erode(S)), DEXEL_CLOSE = erode(dilate(S))
+ * (Sec. 4 "Topological Cleaning").  The intermediate stays in the workspace. */
+dexel_status dexel_offset(dexel_ctx* ctx, const dexel_grid_view* in, float r, int32_t op,
+                          dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream,
+                          uint32_t flags);
+
+/* Workspace for dexel_batch_offset over `items` (the largest single-item
+ * need, since items share the workspace in sequence). */
+dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,
+                                        int64_t cap_hint, size_t* bytes);
+
+/* Offset n independent shapes, each with its own radius and op, in one
+ * enqueue on `stream`.  Each item's status/nseg_out are written separately. */
+dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
+                                size_t ws_bytes, void* stream, uint32_t flags);
+
+const char* dexel_status_string(dexel_status s);
+/* Text of the last host-side error of this context ("" if none). */
+const char* dexel_last_error(const dexel_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEXEL_H */

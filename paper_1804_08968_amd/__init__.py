@@ -1,0 +1,126 @@
+"""MI355X dexel offsets: exact dilation / erosion of dexel shapes by a ball.
+
+The computation runs in libdexel.so (HIP kernels for gfx950, C ABI in
+include/dexel.h).  This package is the Python binding: ``binding`` holds
+the thin ctypes wrappers with the C names; ``Engine`` adds buffer
+management (device tensors, workspace reuse, retry on capacity).
+"""
+from __future__ import annotations
+
+import torch
+
+from .binding import (  # noqa: F401
+    DEXEL_CLOSE, DEXEL_DILATE, DEXEL_ERODE, DEXEL_ERR_CAPACITY, DEXEL_ERR_HIP,
+    DEXEL_ERR_INVALID, DEXEL_ERR_NOT_CANONICAL, DEXEL_ERR_UNSUPPORTED, DEXEL_ERR_WORKSPACE,
+    DEXEL_FLAG_SYNC, DEXEL_FLAG_VALIDATE, DEXEL_OK, DEXEL_OPEN, EXPORTED, LIB_PATH, OPS,
+    DexelError, dexel_batch_item, dexel_batch_offset, dexel_batch_workspace_size,
+    dexel_ctx_create, dexel_ctx_destroy, dexel_dilate, dexel_erode, dexel_grid_out,
+    dexel_grid_view, dexel_last_error, dexel_offset, dexel_status_string, dexel_workspace_need,
+    dexel_workspace_size, make_out, make_view,
+)
+
+
+class DeviceGrid:
+    """A dexel grid resident on the GPU (int64 col_ptr, float32 pairs)."""
+
+    def __init__(self, nx: int, ny: int, col_ptr: torch.Tensor, z: torch.Tensor):
+        self.nx, self.ny = int(nx), int(ny)
+        self.col_ptr = col_ptr
+        self.z = z
+
+    @classmethod
+    def from_host(cls, g, device="cuda"):
+        cp = torch.as_tensor(g.col_ptr, dtype=torch.int64).to(device)
+        z = torch.as_tensor(g.z, dtype=torch.float32).reshape(-1)
+        if z.numel() == 0:
+            z = torch.zeros(2, dtype=torch.float32)
+        return cls(g.nx, g.ny, cp, z.to(device))
+
+    @property
+    def nseg(self) -> int:
+        return int(self.col_ptr[-1].item())
+
+    def view(self, nseg: int | None = None):
+        return make_view(self.nx, self.ny, self.col_ptr, self.z,
+                         self.nseg if nseg is None else nseg)
+
+    def to_host(self):
+        n = self.nseg
+        return (self.col_ptr.cpu().numpy(), self.z[: 2 * n].cpu().numpy())
+
+
+class Engine:
+    """Owns a libdexel context and a reusable workspace on one device."""
+
+    def __init__(self, device: int = 0):
+        self.device_index = int(device)
+        self.device = torch.device("cuda", self.device_index)
+        self.ctx = dexel_ctx_create(self.device_index)
+        self._ws = None
+        self._hint = 0
+
+    def close(self):
+        if self.ctx is not None:
+            dexel_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def offset(self, grid: DeviceGrid, r: float, op: str = "dilate", stream=None,
+               out_cap: int | None = None, validate: bool = False, max_tries: int = 8):
+        """Run one op synchronously; returns a new DeviceGrid (retries on
+        workspace or output capacity)."""
+        code = OPS[op]
+        nseg = grid.nseg
+        view = grid.view(nseg)
+        ncols = grid.nx * grid.ny
+        cap = out_cap if out_cap is not None else nseg + ncols + 1024
+        hint = self._hint
+        flags = DEXEL_FLAG_SYNC | (DEXEL_FLAG_VALIDATE if validate else 0)
+        for _ in range(max_tries):
+            nbytes = dexel_workspace_size(self.ctx, view, r, code, hint)
+            ws = self.workspace(nbytes)
+            col = torch.empty(ncols + 1, dtype=torch.int64, device=self.device)
+            z = torch.empty(2 * max(cap, 1), dtype=torch.float32, device=self.device)
+            nout = torch.zeros(1, dtype=torch.int64, device=self.device)
+            status = torch.zeros(1, dtype=torch.int32, device=self.device)
+            out = make_out(grid.nx, grid.ny, col, z, nout, status)
+            st = dexel_offset(self.ctx, view, r, code, out, ws, stream, flags)
+            if st == DEXEL_OK:
+                return DeviceGrid(grid.nx, grid.ny, col, z)
+            if st == DEXEL_ERR_WORKSPACE:
+                need = dexel_workspace_need(self.ctx, ws)
+                if need <= 0:
+                    raise DexelError(st, dexel_last_error(self.ctx))
+                hint = int(need * 1.25) + 1024
+                self._hint = max(self._hint, hint)
+                continue
+            if st == DEXEL_ERR_CAPACITY:
+                cap = int(nout.item()) + 1
+                continue
+            raise DexelError(st, dexel_last_error(self.ctx))
+        raise DexelError(DEXEL_ERR_WORKSPACE, "retries exhausted")
+
+
+_default_engine = None
+
+
+def default_engine() -> Engine:
+    global _default_engine
+    if _default_engine is None:
+        _default_engine = Engine(torch.cuda.current_device())
+    return _default_engine
+
+
+def offset(grid: DeviceGrid, r: float, op: str = "dilate", **kw) -> DeviceGrid:
+    return default_engine().offset(grid, r, op, **kw)

@@ -1,0 +1,834 @@
+// HIP kernels of libdexel for gfx950 (CDNA4, wave64).
+//
+// One dilation pass of a dexel grid by a closed ball of radius r follows the
+// separable scheme of Chen, Panozzo, Dumas, Sec. 3.3: every input interval is
+// extruded along x to the columns within distance R = floor(r) of its own,
+// keeping for each covered z the closest parent only (the extruded piece
+// then carries the weight r^2 - dx^2); the weighted pieces are dilated along
+// y as seeds of a power diagram (their chord at row offset dy has half-width
+// sqrt(r^2 - dx^2 - dy^2)); the chords of each output column are merged.
+//
+// GPU organisation (one lane per output column, 64 columns per workgroup):
+//   K1  row offset   V0(c) = union of the chords of the column's own row
+//                    (dy = 0): the 2D offset of that row at radius r.
+//   K1b neighbour    I(c)  = intersection of V0 over the rows y+-1 .. y+-R.
+//                    Every output column within R rows of c contains I(c).
+//   K2  seeds        closest-parent extrusion pieces of c's row at column c
+//                    (tag t = |dx|), computed by painting the row's columns
+//                    in order of |dx|; a piece is kept only if its chord at
+//                    |dy| = 1 (its largest off-row chord) is not inside I(c):
+//                    a dropped seed's power disk lies inside V0 of every row
+//                    it can reach.  Count pass, scan, fill pass (CSR).
+//   K3  y dilation   out(c) = V0(c) U chords of the kept seeds of the rows
+//                    y+-1 .. y+-R at their power weight r^2 - t^2 - dy^2.
+//   K4  compaction   exclusive scan of the per-column counts, copy to CSR.
+// Erosion complements each in-grid input column on read (closed gaps with
+// -inf/+inf ends) and the result on write.
+//
+// Every candidate chord is [fl(a - H[d2]), fl(b + H[d2])] with H a float
+// table and one rounding per end; the merge is an exact float union.  A
+// skipped candidate is always contained in the union of kept ones, so the
+// result equals the float union of all chords of the ball stencil.
+//
+// Per-lane interval lists live in LDS, interleaved by lane (element i of
+// lane l at i*64 + l) so that lanes touching the same index hit distinct
+// banks.  A list that outgrows its LDS capacity sends its column to a
+// global-memory replay of the same code ("fallback"), sized from an upper
+// bound and carved from the workspace arena.
+#include <hip/hip_runtime.h>
+
+#include "../../include/dexel.h"
+#include "dexel_internal.h"
+
+namespace dexel {
+
+#define DX_INF __builtin_inff()
+
+constexpr int WG = 64;
+constexpr int FALLBACK_BLOCKS = 256;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+struct LV {  // per-lane interval list: element i at p[i * stride]
+    float2* p;
+    int stride;
+    int cap;
+    __device__ __forceinline__ float2 get(int i) const { return p[(int64_t)i * stride]; }
+    __device__ __forceinline__ void set(int i, float2 v) const { p[(int64_t)i * stride] = v; }
+};
+
+__device__ __forceinline__ void set_error(WsHeader* h, int code) {
+    atomicCAS(&h->status, 0, code);
+    atomicExch(&h->abort, 1);
+}
+
+__device__ __forceinline__ void note_need(WsHeader* h, unsigned long long need) {
+    atomicMax(&h->need_cap, need);
+}
+
+// k-th interval of a column (complemented for erosion: closed gaps).
+__device__ __forceinline__ float2 col_item(const float2* z, int64_t b, int n, int k, int erode) {
+    if (!erode) return z[b + k];
+    float lo = (k == 0) ? -DX_INF : z[b + k - 1].y;
+    float hi = (k == n) ? DX_INF : z[b + k].x;
+    return make_float2(lo, hi);
+}
+
+// First index i in [0, n) of a canonical list with U[i].y >= v (n if none).
+__device__ __forceinline__ int lv_lower_hi(const LV& U, int n, float v) {
+    int l = 0, h = n;
+    while (l < h) {
+        int m = (l + h) >> 1;
+        if (U.get(m).y < v) l = m + 1; else h = m;
+    }
+    return l;
+}
+
+// Insert the closed interval [lo, hi] into a canonical list of size n.
+// Returns the new size, or -1 if the list would exceed its capacity (the list
+// is unchanged then).
+__device__ int lv_insert(const LV& U, int n, float lo, float hi) {
+    int i = lv_lower_hi(U, n, lo);
+    if (i == n || U.get(i).x > hi) {
+        if (n >= U.cap) return -1;
+        for (int k = n; k > i; --k) U.set(k, U.get(k - 1));
+        U.set(i, make_float2(lo, hi));
+        return n + 1;
+    }
+    float2 ui = U.get(i);
+    if (ui.x <= lo && hi <= ui.y) return n;
+    // U[i] overlaps or touches; find the last j with U[j].x <= hi
+    int l = i + 1, h = n;
+    while (l < h) {
+        int m = (l + h) >> 1;
+        if (U.get(m).x <= hi) l = m + 1; else h = m;
+    }
+    int j = l - 1;
+    float nlo = fminf(lo, ui.x);
+    float nhi = fmaxf(hi, U.get(j).y);
+    U.set(i, make_float2(nlo, nhi));
+    int sh = j - i;
+    if (sh > 0)
+        for (int k = j + 1; k < n; ++k) U.set(k - sh, U.get(k));
+    return n - sh;
+}
+
+// Is [lo, hi] inside one interval of the canonical global list L[0..n)?
+__device__ __forceinline__ bool in_list(const float2* L, int n, float lo, float hi) {
+    int l = 0, h = n;
+    while (l < h) {
+        int m = (l + h) >> 1;
+        if (L[m].y < hi) l = m + 1; else h = m;
+    }
+    return l < n && L[l].x <= lo;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int* total) {
+    int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Column id -> (x, y).
+__device__ __forceinline__ void col_xy(const OpParams& P, int64_t c, int* x, int* y) {
+    *y = (int)(c / P.nx);
+    *x = (int)(c - (int64_t)(*y) * P.nx);
+}
+
+// Number of (possibly complemented) intervals of input column cc.
+__device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b) {
+    *b = P.col_ptr[cc];
+    return (int)(P.col_ptr[cc + 1] - *b);
+}
+
+// ---------------------------------------------------------------------------
+// per-column computations (same code for LDS and global lists)
+// ---------------------------------------------------------------------------
+
+// K1: V0 = union over |dx| <= R of the chords [a - H[dx^2], b + H[dx^2]] of
+// the row's columns x + dx, nearest columns first (largest chords first, so
+// most later chords are found inside the list and skipped).
+__device__ int k1_column(const OpParams& P, int64_t c, const LV& U) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int64_t row = (int64_t)y * P.nx;
+    int n = 0;
+    for (int t = 0; t <= P.R; ++t) {
+        const float h = P.H[t * t];
+        for (int s = 0; s < (t ? 2 : 1); ++s) {
+            const int xx = s ? x + t : x - t;
+            if (xx < 0 || xx >= P.nx) continue;
+            int64_t b;
+            const int m = col_len(P, row + xx, &b);
+            const int cnt = P.erode ? m + 1 : m;
+            for (int k = 0; k < cnt; ++k) {
+                float2 iv = col_item(P.z, b, m, k, P.erode);
+                n = lv_insert(U, n, iv.x - h, iv.y + h);
+                if (n < 0) return -1;
+            }
+        }
+    }
+    return n;
+}
+
+__device__ int64_t k1_bound(const OpParams& P, int64_t c) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int64_t row = (int64_t)y * P.nx;
+    int x0 = max(0, x - P.R), x1 = min(P.nx - 1, x + P.R);
+    return (P.col_ptr[row + x1 + 1] - P.col_ptr[row + x0]) + (int64_t)(x1 - x0 + 1) + 1;
+}
+
+// K1b: I = intersection of V0 over the in-grid rows y+-1 .. y+-R (the whole
+// line if there are none).  Two lists, result in *res (0 or 1).
+__device__ int k1b_column(const OpParams& P, int64_t c, const LV& L0, const LV& L1, int* res) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    L0.set(0, make_float2(-DX_INF, DX_INF));
+    int n = 1, cur = 0;
+    for (int dy = 1; dy <= P.R && n > 0; ++dy) {
+        for (int s = 0; s < 2 && n > 0; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            const float2* J = P.A + P.offA[cc];
+            const int m = P.cntA[cc];
+            const LV& S = cur ? L1 : L0;
+            const LV& D = cur ? L0 : L1;
+            int i = 0, j = 0, k = 0;
+            while (i < n && j < m) {
+                float2 a = S.get(i), bb = J[j];
+                float lo = fmaxf(a.x, bb.x), hi = fminf(a.y, bb.y);
+                if (lo < hi) {
+                    if (k >= D.cap) return -1;
+                    D.set(k++, make_float2(lo, hi));
+                }
+                if (a.y < bb.y) ++i; else ++j;
+            }
+            n = k;
+            cur ^= 1;
+        }
+    }
+    *res = cur;
+    return n;
+}
+
+__device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    int64_t b = 2;
+    for (int dy = 1; dy <= P.R; ++dy)
+        for (int s = 0; s < 2; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            b += P.cntA[(int64_t)yy * P.nx + x];
+        }
+    return b;
+}
+
+// K2: closest-parent extrusion pieces of row y at column x (tags t = |dx|),
+// painted in order of t: the pieces of tag t are the parts of the columns
+// x-t and x+t not covered by the columns nearer to x.  Only pieces whose
+// chord at |dy| = 1 pokes out of I(c) are kept.  A column whose whole chord
+// is inside I(c) is not added to the cover list either: the pieces it would
+// hide are then kept whole, which adds valid seeds and changes nothing.
+// fill == false: returns the number of kept pieces; fill == true: also
+// writes them at dst.
+template <bool FILL>
+__device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst, uint8_t* dtag) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int64_t row = (int64_t)y * P.nx;
+    const float2* Ip = P.I + P.offI[c];
+    const int ni = P.cntI[c];
+    int n = 0, np = 0;
+    for (int t = 0; t <= P.R; ++t) {
+        const int d2 = t * t + 1;
+        if (d2 > P.d2max) break;
+        const float h1 = P.H[d2];
+        for (int s = 0; s < (t ? 2 : 1); ++s) {
+            const int xx = s ? x + t : x - t;
+            if (xx < 0 || xx >= P.nx) continue;
+            int64_t b;
+            const int m = col_len(P, row + xx, &b);
+            const int cnt = P.erode ? m + 1 : m;
+            for (int k = 0; k < cnt; ++k) {
+                const float2 sg = col_item(P.z, b, m, k, P.erode);
+                const float a = sg.x, e = sg.y;
+                if (in_list(Ip, ni, a - h1, e + h1)) continue;
+                // parts of [a, e] not covered by U (closures)
+                int idx = lv_lower_hi(U, n, a);
+                float p = a;
+                bool done = false;
+                while (idx < n) {
+                    const float2 u = U.get(idx);
+                    if (u.x > e) break;
+                    if (u.x > p) {
+                        if (!in_list(Ip, ni, p - h1, u.x + h1)) {
+                            if (FILL) { dst[np] = make_float2(p, u.x); dtag[np] = (uint8_t)t; }
+                            ++np;
+                        }
+                    }
+                    if (u.y >= e) { done = true; break; }
+                    p = fmaxf(p, u.y);
+                    ++idx;
+                }
+                if (!done && (p < e || a == e)) {
+                    if (!in_list(Ip, ni, p - h1, e + h1)) {
+                        if (FILL) { dst[np] = make_float2(p, e); dtag[np] = (uint8_t)t; }
+                        ++np;
+                    }
+                }
+                n = lv_insert(U, n, a, e);
+                if (n < 0) return -1;
+            }
+        }
+    }
+    return np;
+}
+
+// K3: V0(c) plus the chords of the kept seeds of rows y+-dy at weight
+// r^2 - t^2 - dy^2, nearest rows first.
+__device__ int k3_column(const OpParams& P, int64_t c, const LV& U) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int n0 = P.cntA[c];
+    if (n0 > U.cap) return -1;
+    const float2* V = P.A + P.offA[c];
+    for (int i = 0; i < n0; ++i) U.set(i, V[i]);
+    int n = n0;
+    for (int dy = 1; dy <= P.R; ++dy) {
+        const int dy2 = dy * dy;
+        for (int s = 0; s < 2; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            const int64_t pb = P.offB[cc], pe = P.offB[cc + 1];
+            for (int64_t j = pb; j < pe; ++j) {
+                const int t = P.tagB[j];
+                const int d2 = t * t + dy2;
+                if (d2 > P.d2max) continue;
+                const float h = P.H[d2];
+                const float2 pc = P.B[j];
+                n = lv_insert(U, n, pc.x - h, pc.y + h);
+                if (n < 0) return -1;
+            }
+        }
+    }
+    return n;
+}
+
+__device__ int64_t k3_bound(const OpParams& P, int64_t c) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    int64_t b = (int64_t)P.cntA[c] + 1;
+    for (int dy = 1; dy <= P.R; ++dy)
+        for (int s = 0; s < 2; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            b += P.offB[cc + 1] - P.offB[cc];
+        }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// emission into bump-allocated per-column lists
+// ---------------------------------------------------------------------------
+
+// Write list U (or its complement's closures, dropping the unbounded ends)
+// of every valid lane.  Wave-cooperative: one atomic per wave.
+__device__ void emit_wave(const OpParams& P, int64_t c, bool valid, const LV& U, int n,
+                          int complement, unsigned long long* bump, int64_t* off, int32_t* cnt,
+                          float2* dst) {
+    const int outn = valid ? (complement ? (n > 0 ? n - 1 : 0) : n) : 0;
+    int tot;
+    const int pre = wave_excl_scan(outn, &tot);
+    unsigned long long base = 0;
+    if ((threadIdx.x & 63) == 0 && tot > 0) base = atomicAdd(bump, (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    const unsigned long long end = base + (unsigned long long)tot;
+    const bool ok = end <= (unsigned long long)P.cap;
+    if (!ok && (threadIdx.x & 63) == 0) {
+        note_need(P.hdr, end);
+        set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+    }
+    if (!valid) return;
+    off[c] = (int64_t)(base + pre);
+    cnt[c] = ok ? outn : 0;
+    if (!ok) return;
+    float2* d = dst + base + pre;
+    if (!complement) {
+        for (int i = 0; i < n; ++i) d[i] = U.get(i);
+    } else {
+        for (int i = 0; i + 1 < n; ++i) d[i] = make_float2(U.get(i).y, U.get(i + 1).x);
+    }
+}
+
+// Single-lane variant for the fallback path.
+__device__ void emit_lane(const OpParams& P, int64_t c, const LV& U, int n, int complement,
+                          unsigned long long* bump, int64_t* off, int32_t* cnt, float2* dst) {
+    const int outn = complement ? (n > 0 ? n - 1 : 0) : n;
+    const unsigned long long base = atomicAdd(bump, (unsigned long long)outn);
+    const unsigned long long end = base + (unsigned long long)outn;
+    off[c] = (int64_t)base;
+    if (end > (unsigned long long)P.cap) {
+        note_need(P.hdr, end);
+        set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        cnt[c] = 0;
+        return;
+    }
+    cnt[c] = outn;
+    float2* d = dst + base;
+    if (!complement) {
+        for (int i = 0; i < n; ++i) d[i] = U.get(i);
+    } else {
+        for (int i = 0; i + 1 < n; ++i) d[i] = make_float2(U.get(i).y, U.get(i + 1).x);
+    }
+}
+
+__device__ __forceinline__ void push_overflow(const OpParams& P, int stage, int64_t c) {
+    const int k = atomicAdd(&P.hdr->novf[stage], 1);
+    P.ovf[(int64_t)stage * P.ncols + k] = (int32_t)c;
+}
+
+// Carve `len` intervals from the arena; nullptr (and a workspace error) if
+// it does not fit.
+__device__ float2* arena_alloc(const OpParams& P, int64_t len) {
+    const unsigned long long base = atomicAdd(&P.hdr->arena, (unsigned long long)len);
+    const unsigned long long end = base + (unsigned long long)len;
+    if (end > (unsigned long long)P.cap) {
+        note_need(P.hdr, end);
+        set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        return nullptr;
+    }
+    return P.arena + base;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int64_t map_block(int64_t nblocks) {
+    // Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
+    // contiguous run of columns so that neighbouring columns (which read the
+    // same input rows) share one L2.
+    const int64_t b = blockIdx.x;
+    const int64_t per = (nblocks + 7) / 8;
+    const int64_t xcd = b & 7, k = b >> 3;
+    const int64_t full = nblocks - (per - 1) * 8;  // XCDs holding `per` blocks
+    int64_t start = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+    return start + k;
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_row_offset(OpParams P) {
+    __shared__ float2 lds[CAP * WG];
+    if (P.hdr->abort) return;
+    const int64_t nb = (P.ncols + WG - 1) / WG;
+    const int64_t c = map_block(nb) * WG + threadIdx.x;
+    bool valid = c < P.ncols;
+    LV U{&lds[threadIdx.x], WG, CAP};
+    int n = valid ? k1_column(P, c, U) : 0;
+    if (n < 0) {
+        push_overflow(P, ST_K1, c);
+        valid = false;
+        n = 0;
+    }
+    emit_wave(P, c, valid, U, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+}
+
+__global__ void __launch_bounds__(WG) k_row_offset_fb(OpParams P) {
+    if (P.hdr->abort) return;
+    const int cnt = P.hdr->novf[ST_K1];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+        const int64_t c = P.ovf[(int64_t)ST_K1 * P.ncols + i];
+        const int64_t bound = k1_bound(P, c);
+        float2* buf = arena_alloc(P, bound);
+        if (!buf) return;
+        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
+        const int n = k1_column(P, c, U);
+        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, U, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+    }
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_neighbour(OpParams P) {
+    __shared__ float2 lds[2 * CAP * WG];
+    if (P.hdr->abort) return;
+    const int64_t nb = (P.ncols + WG - 1) / WG;
+    const int64_t c = map_block(nb) * WG + threadIdx.x;
+    bool valid = c < P.ncols;
+    LV L0{&lds[threadIdx.x], WG, CAP};
+    LV L1{&lds[CAP * WG + threadIdx.x], WG, CAP};
+    int res = 0;
+    int n = valid ? k1b_column(P, c, L0, L1, &res) : 0;
+    if (n < 0) {
+        push_overflow(P, ST_K1B, c);
+        valid = false;
+        n = 0;
+    }
+    emit_wave(P, c, valid, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+}
+
+__global__ void __launch_bounds__(WG) k_neighbour_fb(OpParams P) {
+    if (P.hdr->abort) return;
+    const int cnt = P.hdr->novf[ST_K1B];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+        const int64_t c = P.ovf[(int64_t)ST_K1B * P.ncols + i];
+        const int64_t bound = k1b_bound(P, c);
+        float2* buf = arena_alloc(P, 2 * bound);
+        if (!buf) return;
+        const int cap = (int)min<int64_t>(bound, 0x7fffffff);
+        LV L0{buf, 1, cap}, L1{buf + bound, 1, cap};
+        int res = 0;
+        const int n = k1b_column(P, c, L0, L1, &res);
+        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+    }
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_seeds_count(OpParams P) {
+    __shared__ float2 lds[CAP * WG];
+    if (P.hdr->abort) return;
+    const int64_t nb = (P.ncols + WG - 1) / WG;
+    const int64_t c = map_block(nb) * WG + threadIdx.x;
+    if (c >= P.ncols) return;
+    LV U{&lds[threadIdx.x], WG, CAP};
+    const int np = k2_column<false>(P, c, U, nullptr, nullptr);
+    if (np < 0) {
+        push_overflow(P, ST_K2C, c);
+        P.cntB[c] = 0;
+    } else {
+        P.cntB[c] = np;
+    }
+}
+
+__global__ void __launch_bounds__(WG) k_seeds_count_fb(OpParams P) {
+    if (P.hdr->abort) return;
+    const int cnt = P.hdr->novf[ST_K2C];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+        const int64_t c = P.ovf[(int64_t)ST_K2C * P.ncols + i];
+        const int64_t bound = k1_bound(P, c);
+        float2* buf = arena_alloc(P, bound);
+        if (!buf) return;
+        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
+        const int np = k2_column<false>(P, c, U, nullptr, nullptr);
+        if (np < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
+        P.cntB[c] = np;
+    }
+}
+
+// Checks the scanned seed count against the buffer; all lanes of all blocks
+// read the same total.
+__device__ __forceinline__ bool seeds_fit(const OpParams& P) {
+    const int64_t tot = P.offB[P.ncols];
+    if (tot > P.cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            note_need(P.hdr, (unsigned long long)tot);
+            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        }
+        return false;
+    }
+    return true;
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_seeds_fill(OpParams P) {
+    __shared__ float2 lds[CAP * WG];
+    if (P.hdr->abort || !seeds_fit(P)) return;
+    const int64_t nb = (P.ncols + WG - 1) / WG;
+    const int64_t c = map_block(nb) * WG + threadIdx.x;
+    if (c >= P.ncols) return;
+    LV U{&lds[threadIdx.x], WG, CAP};
+    const int64_t o = P.offB[c];
+    const int np = k2_column<true>(P, c, U, P.B + o, P.tagB + o);
+    if (np < 0) push_overflow(P, ST_K2F, c);
+}
+
+__global__ void __launch_bounds__(WG) k_seeds_fill_fb(OpParams P) {
+    if (P.hdr->abort || !seeds_fit(P)) return;
+    const int cnt = P.hdr->novf[ST_K2F];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+        const int64_t c = P.ovf[(int64_t)ST_K2F * P.ncols + i];
+        const int64_t bound = k1_bound(P, c);
+        float2* buf = arena_alloc(P, bound);
+        if (!buf) return;
+        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
+        const int64_t o = P.offB[c];
+        const int np = k2_column<true>(P, c, U, P.B + o, P.tagB + o);
+        if (np < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
+    }
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_union(OpParams P) {
+    __shared__ float2 lds[CAP * WG];
+    if (P.hdr->abort) return;
+    const int64_t nb = (P.ncols + WG - 1) / WG;
+    const int64_t c = map_block(nb) * WG + threadIdx.x;
+    bool valid = c < P.ncols;
+    LV U{&lds[threadIdx.x], WG, CAP};
+    int n = valid ? k3_column(P, c, U) : 0;
+    if (n < 0) {
+        push_overflow(P, ST_K3, c);
+        valid = false;
+        n = 0;
+    }
+    emit_wave(P, c, valid, U, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+}
+
+__global__ void __launch_bounds__(WG) k_union_fb(OpParams P) {
+    if (P.hdr->abort) return;
+    const int cnt = P.hdr->novf[ST_K3];
+    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+        const int64_t c = P.ovf[(int64_t)ST_K3 * P.ncols + i];
+        const int64_t bound = k3_bound(P, c);
+        float2* buf = arena_alloc(P, bound);
+        if (!buf) return;
+        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
+        const int n = k3_column(P, c, U);
+        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, U, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts into int64 offsets (with the total at [n])
+// ---------------------------------------------------------------------------
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_V = 4;
+constexpr int SCAN_B = SCAN_T * SCAN_V;
+
+__device__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_T; d <<= 1) {
+        int64_t y = (t >= d) ? sh[t - d] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    const int64_t incl = sh[t];
+    *total = sh[SCAN_T - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* cnt, int64_t n, int64_t* bsum) {
+    __shared__ int64_t sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_V; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_V + k;
+        if (i < n) s += cnt[i];
+    }
+    int64_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_bsum(int64_t* bsum, int64_t nb) {
+    __shared__ int64_t sh[SCAN_T];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nb; base += SCAN_T) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nb ? bsum[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_excl_scan(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t* cnt, int64_t n,
+                                                       const int64_t* bsum, int64_t nb, int64_t* off) {
+    __shared__ int64_t sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    int32_t v[SCAN_V];
+    int64_t s = 0;
+    for (int k = 0; k < SCAN_V; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_V + k;
+        v[k] = i < n ? cnt[i] : 0;
+        s += v[k];
+    }
+    int64_t tot;
+    int64_t run = block_excl_scan(s, sh, &tot) + bsum[blockIdx.x];
+    for (int k = 0; k < SCAN_V; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * SCAN_V + k;
+        if (i < n) off[i] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) off[n] = bsum[nb];
+}
+
+static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int64_t* off,
+                              hipStream_t s) {
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, cnt, n, bsum);
+    }
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(SCAN_T), 0, s, bsum, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_T), 0, s, cnt, n,
+                       bsum, nb, off);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// compaction into the output CSR, status
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_copy_out(OpParams P) {
+    if (P.hdr->abort) return;
+    const int64_t tot = P.out_col_ptr[P.ncols];
+    if (tot > P.out_cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (P.out_is_intermediate) {
+                note_need(P.hdr, (unsigned long long)tot);
+                set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+            } else {
+                atomicCAS(&P.hdr->status, 0, DEXEL_ERR_CAPACITY);
+            }
+        }
+        return;
+    }
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= P.ncols) return;
+    const int64_t o = P.out_col_ptr[c];
+    const int n = P.cntC[c];
+    const float2* src = P.C + P.offC[c];
+    for (int i = 0; i < n; ++i) P.out_z[o + i] = src[i];
+}
+
+__global__ void k_init_call(WsHeader* h) {
+    if (threadIdx.x == 0) {
+        h->status = 0;
+        h->abort = 0;
+        h->need_cap = 0;
+        h->nseg_out = -1;
+    }
+    if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
+    if (threadIdx.x == 0) { h->bumpA = h->bumpI = h->bumpC = h->arena = 0; }
+}
+
+__global__ void k_init_op(WsHeader* h) {
+    if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
+    if (threadIdx.x == 0) { h->bumpA = h->bumpI = h->bumpC = h->arena = 0; }
+}
+
+// Input sanity that prevents out-of-range reads: col_ptr[0] = 0,
+// nondecreasing, col_ptr[ncols] = nseg (when known).  Always run.
+__global__ void __launch_bounds__(256) k_check_colptr(OpParams P) {
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c > P.ncols) return;
+    const int64_t v = P.col_ptr[c];
+    bool bad = false;
+    if (c == 0 && v != 0) bad = true;
+    if (c < P.ncols && P.col_ptr[c + 1] < v) bad = true;
+    if (c == P.ncols && P.nseg >= 0 && v != P.nseg) bad = true;
+    if (v < 0 || (P.nseg >= 0 && v > P.nseg)) bad = true;
+    if (bad) set_error(P.hdr, DEXEL_ERR_NOT_CANONICAL);
+}
+
+// Full canonical-form check of the intervals (DEXEL_FLAG_VALIDATE).
+__global__ void __launch_bounds__(256) k_validate(OpParams P) {
+    if (P.hdr->abort) return;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= P.ncols) return;
+    const int64_t b = P.col_ptr[c], e = P.col_ptr[c + 1];
+    float prev = -DX_INF;
+    bool first = true, bad = false;
+    for (int64_t i = b; i < e; ++i) {
+        const float2 v = P.z[i];
+        if (!(v.x == v.x) || !(v.y == v.y) || isinf(v.x) || isinf(v.y) || v.x > v.y) bad = true;
+        if (!first && !(v.x > prev)) bad = true;
+        prev = v.y;
+        first = false;
+    }
+    if (bad) set_error(P.hdr, DEXEL_ERR_NOT_CANONICAL);
+}
+
+__global__ void k_finish(WsHeader* h, const int64_t* out_col_ptr, int64_t ncols, int64_t* nseg_out,
+                         int32_t* status) {
+    if (threadIdx.x != 0) return;
+    const int st = h->status;
+    int64_t n = -1;
+    if (st == 0 || st == DEXEL_ERR_CAPACITY) n = out_col_ptr[ncols];
+    h->nseg_out = n;
+    if (nseg_out) *nseg_out = n;
+    if (status) *status = st;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_init_call(WsHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(64), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_op(WsHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_op, dim3(1), dim3(64), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_colptr(const OpParams& p, hipStream_t s) {
+    const int64_t nb = (p.ncols + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_check_colptr, dim3((unsigned)nb), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const OpParams& p, hipStream_t s) {
+    const int64_t nb = (p.ncols + 255) / 256;
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)nb), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+constexpr int CAP_K1 = 32;
+constexpr int CAP_K1B = 16;
+constexpr int CAP_K2 = 48;
+constexpr int CAP_K3 = 32;
+
+hipError_t launch_offset_pass(const OpParams& p, hipStream_t s) {
+    const unsigned nb = (unsigned)((p.ncols + WG - 1) / WG);
+    const dim3 g(nb), b(WG), gf(FALLBACK_BLOCKS);
+    hipLaunchKernelGGL(k_row_offset<CAP_K1>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_neighbour<CAP_K1B>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_neighbour_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_count<CAP_K2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_count_fb, gf, b, 0, s, p);
+    hipError_t e = scan_counts(p.cntB, p.ncols, p.bsum, p.offB, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_seeds_fill<CAP_K2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_fill_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_union<CAP_K3>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_union_fb, gf, b, 0, s, p);
+    e = scan_counts(p.cntC, p.ncols, p.bsum, p.out_col_ptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_copy_out, dim3((unsigned)((p.ncols + 255) / 256)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(WsHeader* hdr, const int64_t* out_col_ptr, int64_t ncols,
+                         int64_t* nseg_out, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, hdr, out_col_ptr, ncols, nseg_out,
+                       status);
+    return hipGetLastError();
+}
+
+}  // namespace dexel
