@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of exact dexel offsets on one MI355X.
+
+Default workload: closing (dilation then erosion, r = 16) of a 2048 x 2048
+gyroid lattice (period 64, walls about 3 voxels thick, height 2048; about 51
+intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
+method's own scalability experiments.  One step = one closing of the whole
+grid, input resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--no-cpu-baseline]
+
+value   = input intervals offset per second (intervals of the input grid per
+          operation, summed over the step's operations, divided by the step
+          time measured between device synchronisations).
+roofline: the dominant kernel's algorithmic bytes per launch divided by its
+          average duration (HIP events on the library's stream inside the
+          timed region), against the 8 TB/s HBM peak.
+cpu_baseline: the float64 brute-force oracle on the host cores, timed on a
+          bounded sample of output columns of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c3": dict(desc="closing r=16 of a 2048x2048 gyroid lattice (period 64, wall ~3 voxels, "
+                    "height 2048)", ops=[("close", 16.0)]),
+    "c2": dict(desc="dilation and erosion at r in {2, 8, 32} of a 512x512 soup of 1350 "
+                    "spheres/boxes (sizes U[4,64], height 512)",
+               ops=[(op, r) for r in (2.0, 8.0, 32.0) for op in ("dilate", "erode")]),
+    "c1": dict(desc="dilation r=3 of a 64x64 union of 8 spheres (R in U[4,12])",
+               ops=[("dilate", 3.0)]),
+}
+
+
+def make_grid(name):
+    from synth import gen
+    if name == "c3":
+        return gen.gyroid_grid(0)
+    if name == "c2":
+        return gen.primitives_grid(0)
+    if name == "c1":
+        return gen.spheres_grid(0)
+    raise KeyError(name)
+
+
+def kernel_bytes(stage, ncols, n_in, st):
+    """Algorithmic bytes of one launch of a profiled kernel: every array it
+    must read or write once (CSR offsets 8 B per column, counts 4 B,
+    intervals 8 B, seed tags 1 B)."""
+    v0, iv, seeds, res = st["row_offset"], st["neighbour"], st["seeds"], st["result"]
+    inp = 8 * (ncols + 1) + 8 * n_in
+    lst_v0 = 12 * ncols + 8 * v0
+    lst_i = 12 * ncols + 8 * iv
+    return {
+        "row_offset": inp + lst_v0,
+        "neighbour": lst_v0 + lst_i,
+        "seeds_count": inp + lst_i + 4 * ncols,
+        "seeds_fill": inp + lst_i + 8 * (ncols + 1) + 9 * seeds,
+        "y_union": lst_v0 + 8 * (ncols + 1) + 9 * seeds + 12 * ncols + 8 * res,
+        "compact": 4 * ncols + 8 * (ncols + 1) + 12 * ncols + 16 * res,
+    }.get(stage)
+
+
+def pass_list(op):
+    return {"dilate": ["dilate"], "erode": ["erode"], "close": ["dilate", "erode"],
+            "open": ["erode", "dilate"]}[op]
+
+
+def cpu_baseline(grid, ops, budget_s=20.0):
+    """Time the float64 oracle on a square tile of output columns."""
+    import oracle
+    op, r = ops[0]
+    n = 4
+    best = None
+    cores = oracle.num_threads()
+    while True:
+        x0 = max(0, grid.nx // 2 - n // 2)
+        y0 = max(0, grid.ny // 2 - n // 2)
+        xs = np.arange(x0, min(grid.nx, x0 + n))
+        ys = np.arange(y0, min(grid.ny, y0 + n))
+        cols = (ys[:, None] * grid.nx + xs[None, :]).ravel()
+        t0 = time.perf_counter()
+        if op in ("dilate", "erode"):
+            oracle.offset_columns(grid, r, op, "f64", cols=cols)
+        else:
+            oracle.region_chain(grid, r, op, cols, "f64")
+        dt = time.perf_counter() - t0
+        best = (cols.size, dt, n)
+        if dt * 4 > budget_s or cols.size >= grid.nx * grid.ny:
+            break
+        n *= 2
+    ncols_s, dt, n = best
+    per_col = grid.nseg / float(grid.nx * grid.ny)
+    segs = ncols_s * per_col
+    return {"value": segs / dt, "unit": "input segments/s", "cores": cores, "kind": "oracle",
+            "sample": f"{op} r={r} on a {n}x{n} tile of output columns ({ncols_s} columns, "
+                      f"{segs:.0f} input-interval equivalents at {per_col:.2f} per column), "
+                      f"{dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the offset of one "
+              "grid is not split across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1804_08968_amd as dx
+
+    wl = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    grid = make_grid(args.workload)
+    print(f"[bench] workload {args.workload}: {grid.nx}x{grid.ny}, {grid.nseg} intervals "
+          f"(generated in {time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    eng = dx.Engine(0)
+    dg = dx.DeviceGrid.from_host(grid)
+    ncols = grid.nx * grid.ny
+
+    # per-pass sizes for the algorithmic-byte model (outside the timed region)
+    pass_stats = []
+    for op, r in wl["ops"]:
+        cur = dg
+        for p in pass_list(op):
+            plan = dx.Plan(eng, cur, r, p)
+            plan.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+            st = dx.dexel_workspace_stats(eng.ctx, eng.workspace(plan.ws_bytes))
+            pass_stats.append((cur.nseg, st))
+            cur = plan.result()
+    plans = [dx.Plan(eng, dg, r, op) for op, r in wl["ops"]]
+    print(f"[bench] plans ready ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        for p in plans:
+            p.enqueue()
+    torch.cuda.synchronize()
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        for p in plans:
+            p.enqueue()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    dx.dexel_profile_enable(eng.ctx, False)
+    prof_ms, passes = dx.dexel_profile_read(eng.ctx, reset=True)
+    for p in plans:
+        if p.status() != 0:
+            raise RuntimeError(f"device status {p.status()} for {p.op}")
+
+    ms_per_step = (t_end - t_start) * 1000.0 / args.steps
+    n_in_step = sum(p.nseg_in for p in plans)
+    value = n_in_step / (ms_per_step / 1000.0)
+
+    # dominant kernel over the timed region
+    stages = dx.PROFILE_STAGES
+    per_step = {s: prof_ms[i] / args.steps for i, s in enumerate(stages)}
+    dom = max(per_step, key=per_step.get)
+    dom_launches_per_step = len(pass_stats)
+    dom_ms = per_step[dom] / dom_launches_per_step
+    tot_bytes = 0
+    for n_in, st in pass_stats:
+        b = kernel_bytes(dom, ncols, n_in, st)
+        tot_bytes += b if b is not None else 0
+    bytes_per_launch = tot_bytes / max(1, len(pass_stats))
+    achieved = bytes_per_launch / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": dx.PROFILE_KERNELS[stages.index(dom)],
+                "kernel_ms": round(dom_ms, 4), "bytes_per_launch": int(bytes_per_launch)}
+
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": value,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "grid": f"{grid.nx}x{grid.ny}",
+                   "nseg_in": grid.nseg, "ops": [f"{op} r={r}" for op, r in wl["ops"]],
+                   "nseg_out": [p.nseg_out for p in plans]},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "pass_sizes": [dict(st, nseg_in=n) for n, st in pass_stats],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(grid, wl["ops"], args.cpu_budget)
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
+if __name__ == "__main__":
+    main()

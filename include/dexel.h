@@ -148,6 +148,26 @@ dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_b
 dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
                                 size_t ws_bytes, void* stream, uint32_t flags);
 
+/* Profiling.  When enabled, every pass of every later call records HIP
+ * events on its stream around each of its DEXEL_NPROF launch groups: row
+ * offset, its global-memory replay, neighbour intersection, its replay, seed
+ * count, (unused), seed-count scan, seed fill, (unused), y dilation with
+ * per-column union, its replay, result scan, compaction copy.
+ * dexel_profile_read waits for the recorded events and returns the
+ * accumulated milliseconds per group and the number of passes (a dilation or
+ * erosion is one pass, open/close two); reset != 0 clears the accumulators. */
+#define DEXEL_NPROF 13
+dexel_status dexel_profile_enable(dexel_ctx* ctx, int on);
+dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset);
+
+/* Sizes recorded by the last pass of the last completed call in `ws`
+ * (stream synchronised; small device-to-host copy): stats[0] row-offset
+ * intervals, [1] neighbour-intersection intervals, [2] kept extrusion seeds,
+ * [3] result intervals of the pass, [4] overflow-arena intervals used,
+ * [5] columns replayed from global memory, [6] capacity hint needed,
+ * [7] output intervals of the call (-1 if it failed). */
+dexel_status dexel_workspace_stats(dexel_ctx* ctx, const void* ws, int64_t* stats);
+
 const char* dexel_status_string(dexel_status s);
 /* Text of the last host-side error of this context ("" if none). */
 const char* dexel_last_error(const dexel_ctx* ctx);

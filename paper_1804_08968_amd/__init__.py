@@ -15,8 +15,9 @@ from .binding import (  # noqa: F401
     DEXEL_FLAG_SYNC, DEXEL_FLAG_VALIDATE, DEXEL_OK, DEXEL_OPEN, EXPORTED, LIB_PATH, OPS,
     DexelError, dexel_batch_item, dexel_batch_offset, dexel_batch_workspace_size,
     dexel_ctx_create, dexel_ctx_destroy, dexel_dilate, dexel_erode, dexel_grid_out,
-    dexel_grid_view, dexel_last_error, dexel_offset, dexel_status_string, dexel_workspace_need,
-    dexel_workspace_size, make_out, make_view,
+    dexel_grid_view, dexel_last_error, dexel_offset, dexel_profile_enable, dexel_profile_read,
+    dexel_status_string, dexel_workspace_need, dexel_workspace_size, dexel_workspace_stats,
+    make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES,
 )
 
 
@@ -102,7 +103,8 @@ class Engine:
                 need = dexel_workspace_need(self.ctx, ws)
                 if need <= 0:
                     raise DexelError(st, dexel_last_error(self.ctx))
-                hint = int(need * 1.25) + 1024
+                base = hint if hint > 0 else nseg + 2 * ncols + 1024
+                hint = max(int(need * 1.25) + 1024, 2 * base)
                 self._hint = max(self._hint, hint)
                 continue
             if st == DEXEL_ERR_CAPACITY:
@@ -110,6 +112,45 @@ class Engine:
                 continue
             raise DexelError(st, dexel_last_error(self.ctx))
         raise DexelError(DEXEL_ERR_WORKSPACE, "retries exhausted")
+
+
+class Plan:
+    """A pre-sized offset call for repeated asynchronous enqueues.
+
+    Construction runs the op once synchronously (learning the workspace and
+    output sizes), then keeps the output buffers and the call arguments.
+    ``enqueue`` issues the call on a stream without synchronising;
+    ``status()`` reads the device status of the last call.
+    """
+
+    def __init__(self, engine: "Engine", grid: DeviceGrid, r: float, op: str):
+        self.engine, self.grid, self.r, self.op = engine, grid, float(r), op
+        self.code = OPS[op]
+        res = engine.offset(grid, r, op)
+        self.nseg_out = res.nseg
+        self.nseg_in = grid.nseg
+        self.view = grid.view(self.nseg_in)
+        ncols = grid.nx * grid.ny
+        dev = engine.device
+        self.col = torch.empty(ncols + 1, dtype=torch.int64, device=dev)
+        self.z = torch.empty(2 * max(self.nseg_out, 1), dtype=torch.float32, device=dev)
+        self.nout = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status_t = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.out = make_out(grid.nx, grid.ny, self.col, self.z, self.nout, self.status_t)
+        self.ws_bytes = dexel_workspace_size(engine.ctx, self.view, self.r, self.code, engine._hint)
+        engine.workspace(self.ws_bytes)
+
+    def enqueue(self, stream=None, flags: int = 0) -> None:
+        ws = self.engine.workspace(self.ws_bytes)
+        st = dexel_offset(self.engine.ctx, self.view, self.r, self.code, self.out, ws, stream, flags)
+        if st != DEXEL_OK:
+            raise DexelError(st, dexel_last_error(self.engine.ctx))
+
+    def status(self) -> int:
+        return int(self.status_t.item())
+
+    def result(self) -> DeviceGrid:
+        return DeviceGrid(self.grid.nx, self.grid.ny, self.col, self.z)
 
 
 _default_engine = None

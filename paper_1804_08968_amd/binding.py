@@ -73,6 +73,12 @@ lib.dexel_batch_workspace_size.restype = c_int
 lib.dexel_batch_offset.argtypes = [c_void_p, c_int32, _P(dexel_batch_item), c_void_p, c_size_t,
                                    c_void_p, c_uint32]
 lib.dexel_batch_offset.restype = c_int
+lib.dexel_profile_enable.argtypes = [c_void_p, c_int]
+lib.dexel_profile_enable.restype = c_int
+lib.dexel_profile_read.argtypes = [c_void_p, _P(ctypes.c_double), _P(c_int64), c_int]
+lib.dexel_profile_read.restype = c_int
+lib.dexel_workspace_stats.argtypes = [c_void_p, c_void_p, _P(c_int64)]
+lib.dexel_workspace_stats.restype = c_int
 lib.dexel_status_string.argtypes = [c_int]
 lib.dexel_status_string.restype = ctypes.c_char_p
 lib.dexel_last_error.argtypes = [c_void_p]
@@ -80,8 +86,17 @@ lib.dexel_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_workspace_need", "dexel_dilate", "dexel_erode", "dexel_offset",
-            "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_status_string",
+            "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_profile_enable",
+            "dexel_profile_read", "dexel_workspace_stats", "dexel_status_string",
             "dexel_last_error"]
+NPROF = 13
+PROFILE_STAGES = ["row_offset", "row_offset_replay", "neighbour", "neighbour_replay",
+                  "seeds_count", "unused5", "seeds_scan", "seeds_fill",
+                  "unused8", "y_union", "y_union_replay", "result_scan", "compact"]
+# main HIP kernel of each profiled group (as rocprofv3 names it)
+PROFILE_KERNELS = ["k_row_offset", "k_row_offset_fb", "k_neighbour", "k_neighbour_fb",
+                   "k_seeds_count", "-", "k_scan", "k_seeds_fill",
+                   "-", "k_union", "k_union_fb", "k_scan", "k_copy_out"]
 
 
 class DexelError(RuntimeError):
@@ -176,3 +191,28 @@ def dexel_batch_offset(ctx, items, ws: torch.Tensor, stream=None, flags: int = 0
     arr = (dexel_batch_item * len(items))(*items)
     return lib.dexel_batch_offset(ctx, len(items), arr, _ptr(ws), int(ws.numel()),
                                   _stream_ptr(stream), int(flags))
+
+
+def dexel_profile_enable(ctx, on: bool = True) -> None:
+    st = lib.dexel_profile_enable(ctx, 1 if on else 0)
+    if st != DEXEL_OK:
+        raise DexelError(st)
+
+
+def dexel_profile_read(ctx, reset: bool = False):
+    """Returns (ms per stage as a list, number of passes)."""
+    ms = (ctypes.c_double * NPROF)()
+    n = c_int64()
+    st = lib.dexel_profile_read(ctx, ms, ctypes.byref(n), 1 if reset else 0)
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    return list(ms), int(n.value)
+
+
+def dexel_workspace_stats(ctx, ws: torch.Tensor) -> dict:
+    v = (c_int64 * 8)()
+    st = lib.dexel_workspace_stats(ctx, _ptr(ws), v)
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    keys = ["row_offset", "neighbour", "seeds", "result", "arena", "replayed", "need", "nseg_out"]
+    return dict(zip(keys, list(v)))

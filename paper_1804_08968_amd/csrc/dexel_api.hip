@@ -21,6 +21,13 @@ struct dexel_ctx {
     // table is immutable once built, so an asynchronous upload from it can
     // never observe a later call's table.
     std::map<uint32_t, float*> luts;
+    // Optional per-stage timing: HIP events recorded on the call's stream at
+    // the stage boundaries of every pass, read back by dexel_profile_read.
+    bool profile = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::vector<hipEvent_t>> pending;
+    double acc[dexel::NPROF] = {0};
+    int64_t passes = 0;
 };
 
 namespace {
@@ -238,7 +245,23 @@ dexel_status enqueue_op(dexel_ctx* ctx, const dexel_grid_view* in, float r, int 
             HIP_TRY(dexel::launch_check_colptr(p, s));
             if (flags & DEXEL_FLAG_VALIDATE) HIP_TRY(dexel::launch_validate(p, s));
         }
-        HIP_TRY(dexel::launch_offset_pass(p, s));
+        hipEvent_t* ev = nullptr;
+        if (ctx->profile) {
+            std::vector<hipEvent_t> group;
+            for (int i = 0; i <= dexel::NPROF; ++i) {
+                hipEvent_t e;
+                if (!ctx->pool.empty()) {
+                    e = ctx->pool.back();
+                    ctx->pool.pop_back();
+                } else {
+                    HIP_TRY(hipEventCreate(&e));
+                }
+                group.push_back(e);
+            }
+            ctx->pending.push_back(group);
+            ev = ctx->pending.back().data();
+        }
+        HIP_TRY(dexel::launch_offset_pass(p, s, ev));
     }
     HIP_TRY(dexel::launch_finish(p.hdr, out->col_ptr, ncols, out->nseg_out, out->status, s));
     return DEXEL_OK;
@@ -274,6 +297,9 @@ dexel_status dexel_ctx_create(int device, dexel_ctx** ctx) {
 
 void dexel_ctx_destroy(dexel_ctx* ctx) {
     if (!ctx) return;
+    for (auto& g : ctx->pending)
+        for (hipEvent_t e : g) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
     for (auto& kv : ctx->luts) (void)hipHostFree(kv.second);
     delete ctx;
 }
@@ -377,6 +403,53 @@ dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_ite
             if (st != 0) return (dexel_status)st;
         }
     }
+    return DEXEL_OK;
+}
+
+dexel_status dexel_profile_enable(dexel_ctx* ctx, int on) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    ctx->profile = on != 0;
+    return DEXEL_OK;
+}
+
+dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    for (auto& g : ctx->pending) {
+        HIP_TRY(hipEventSynchronize(g.back()));
+        for (int i = 0; i < dexel::NPROF; ++i) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, g[i], g[i + 1]));
+            ctx->acc[i] += t;
+        }
+        ctx->passes += 1;
+        for (hipEvent_t e : g) ctx->pool.push_back(e);
+    }
+    ctx->pending.clear();
+    if (ms)
+        for (int i = 0; i < dexel::NPROF; ++i) ms[i] = ctx->acc[i];
+    if (passes) *passes = ctx->passes;
+    if (reset) {
+        for (int i = 0; i < dexel::NPROF; ++i) ctx->acc[i] = 0;
+        ctx->passes = 0;
+    }
+    return DEXEL_OK;
+}
+
+dexel_status dexel_workspace_stats(dexel_ctx* ctx, const void* ws, int64_t* stats) {
+    if (!ctx || !ws || !stats) return DEXEL_ERR_INVALID;
+    WsHeader h;
+    hipError_t e = hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(ctx, DEXEL_ERR_HIP, hipGetErrorString(e));
+    int64_t novf = 0;
+    for (int i = 0; i < dexel::NSTAGE; ++i) novf += h.novf[i];
+    stats[0] = (int64_t)h.bumpA;
+    stats[1] = (int64_t)h.bumpI;
+    stats[2] = h.nseeds;
+    stats[3] = (int64_t)h.bumpC;
+    stats[4] = (int64_t)h.arena;
+    stats[5] = novf;
+    stats[6] = (int64_t)h.need_cap;
+    stats[7] = h.nseg_out;
     return DEXEL_OK;
 }
 

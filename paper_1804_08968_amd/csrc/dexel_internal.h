@@ -19,7 +19,8 @@ struct WsHeader {
     unsigned long long arena;       // bump allocator of the overflow arena
     int64_t nseg_out;
     int32_t novf[8];                // columns whose per-lane list overflowed LDS, per stage
-    int64_t reserved[3];
+    int64_t nseeds;                 // kept extrusion seeds of the last pass
+    int64_t reserved[2];
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
@@ -59,7 +60,13 @@ hipError_t launch_init_call(WsHeader* hdr, hipStream_t s);
 hipError_t launch_init_op(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_colptr(const OpParams& p, hipStream_t s);
 hipError_t launch_validate(const OpParams& p, hipStream_t s);
-hipError_t launch_offset_pass(const OpParams& p, hipStream_t s);
+// Profiled intervals of one pass, one per launch group: row offset, its
+// replay, neighbour intersection, its replay, seed count, its replay, seed
+// scan, seed fill, its replay, y dilation + union, its replay, result scan,
+// compaction copy.
+constexpr int NPROF = 13;
+// ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
+hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_finish(WsHeader* hdr, const int64_t* out_col_ptr, int64_t ncols,
                          int64_t* nseg_out, int32_t* status, hipStream_t s);
 

@@ -115,6 +115,62 @@ __device__ int lv_insert(const LV& U, int n, float lo, float hi) {
     return n - sh;
 }
 
+// lv_insert for candidates arriving in non-decreasing order of start: the
+// insertion point is found by walking forward from *hint (the position the
+// previous candidate landed at) instead of a binary search.
+__device__ int lv_insert_fwd(const LV& U, int n, float lo, float hi, int* hint) {
+    int i = *hint;
+    while (i < n && U.get(i).y < lo) ++i;
+    *hint = i;
+    if (i == n || U.get(i).x > hi) {
+        if (n >= U.cap) return -1;
+        for (int k = n; k > i; --k) U.set(k, U.get(k - 1));
+        U.set(i, make_float2(lo, hi));
+        return n + 1;
+    }
+    float2 ui = U.get(i);
+    if (ui.x <= lo && hi <= ui.y) return n;
+    int j = i;
+    while (j + 1 < n && U.get(j + 1).x <= hi) ++j;
+    U.set(i, make_float2(fminf(lo, ui.x), fmaxf(hi, U.get(j).y)));
+    int sh = j - i;
+    if (sh > 0)
+        for (int k = j + 1; k < n; ++k) U.set(k - sh, U.get(k));
+    return n - sh;
+}
+
+// Insert the chords [a - h, b + h] of column items k0 .. k1-1 (starts
+// non-decreasing).  Returns the new size or -1 on overflow.
+__device__ int insert_chords(const OpParams& P, const LV& U, int n, int64_t b, int m, int k0,
+                             int k1, float h) {
+    int hint = 0;
+    for (int k = k0; k < k1; ++k) {
+        const float2 iv = col_item(P.z, b, m, k, P.erode);
+        n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
+        if (n < 0) return -1;
+    }
+    return n;
+}
+
+// Add the chords of one column to the union U.  Within a column the chord
+// starts and the chord ends are both non-decreasing (disjoint sorted
+// intervals, one half-width), so when U is a single interval [L, R] only a
+// leading run of chords starting below L and a trailing run ending above R
+// can change it; the chords between them lie inside [L, R].
+__device__ int add_column_chords(const OpParams& P, const LV& U, int n, int64_t b, int m, float h) {
+    const int cnt = P.erode ? m + 1 : m;
+    if (cnt == 0) return n;
+    if (n != 1) return insert_chords(P, U, n, b, m, 0, cnt, h);
+    const float2 u = U.get(0);
+    int k0 = 0;
+    while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
+    int k1 = cnt;
+    while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
+    n = insert_chords(P, U, n, b, m, 0, k0, h);
+    if (n < 0) return -1;
+    return insert_chords(P, U, n, b, m, k1, cnt, h);
+}
+
 // Is [lo, hi] inside one interval of the canonical global list L[0..n)?
 __device__ __forceinline__ bool in_list(const float2* L, int n, float lo, float hi) {
     int l = 0, h = n;
@@ -168,12 +224,8 @@ __device__ int k1_column(const OpParams& P, int64_t c, const LV& U) {
             if (xx < 0 || xx >= P.nx) continue;
             int64_t b;
             const int m = col_len(P, row + xx, &b);
-            const int cnt = P.erode ? m + 1 : m;
-            for (int k = 0; k < cnt; ++k) {
-                float2 iv = col_item(P.z, b, m, k, P.erode);
-                n = lv_insert(U, n, iv.x - h, iv.y + h);
-                if (n < 0) return -1;
-            }
+            n = add_column_chords(P, U, n, b, m, h);
+            if (n < 0) return -1;
         }
     }
     return n;
@@ -238,10 +290,43 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
 // painted in order of t: the pieces of tag t are the parts of the columns
 // x-t and x+t not covered by the columns nearer to x.  Only pieces whose
 // chord at |dy| = 1 pokes out of I(c) are kept.  A column whose whole chord
-// is inside I(c) is not added to the cover list either: the pieces it would
-// hide are then kept whole, which adds valid seeds and changes nothing.
-// fill == false: returns the number of kept pieces; fill == true: also
-// writes them at dst.
+// is inside I(c) is not added to the cover list, and the cover list simply
+// stops growing when its LDS capacity is reached: either way the pieces it
+// would hide are then kept whole, which adds valid seeds and changes
+// nothing in the result.  FILL == false: returns the number of kept pieces;
+// FILL == true: also writes them at dst.
+template <bool FILL>
+__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, const LV& U, int* n, float a,
+                                           float e, float h1, int t, int* np, float2* dst,
+                                           uint8_t* dtag) {
+    if (in_list(Ip, ni, a - h1, e + h1)) return;
+    // parts of [a, e] not covered by U (closures)
+    int idx = lv_lower_hi(U, *n, a);
+    float p = a;
+    bool done = false;
+    while (idx < *n) {
+        const float2 u = U.get(idx);
+        if (u.x > e) break;
+        if (u.x > p) {
+            if (!in_list(Ip, ni, p - h1, u.x + h1)) {
+                if (FILL) { dst[*np] = make_float2(p, u.x); dtag[*np] = (uint8_t)t; }
+                ++*np;
+            }
+        }
+        if (u.y >= e) { done = true; break; }
+        p = fmaxf(p, u.y);
+        ++idx;
+    }
+    if (!done && (p < e || a == e)) {
+        if (!in_list(Ip, ni, p - h1, e + h1)) {
+            if (FILL) { dst[*np] = make_float2(p, e); dtag[*np] = (uint8_t)t; }
+            ++*np;
+        }
+    }
+    const int nn = lv_insert(U, *n, a, e);
+    if (nn >= 0) *n = nn;
+}
+
 template <bool FILL>
 __device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst, uint8_t* dtag) {
     int x, y;
@@ -249,6 +334,7 @@ __device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst,
     const int64_t row = (int64_t)y * P.nx;
     const float2* Ip = P.I + P.offI[c];
     const int ni = P.cntI[c];
+    const float2 i0 = ni == 1 ? Ip[0] : make_float2(0.f, 0.f);
     int n = 0, np = 0;
     for (int t = 0; t <= P.R; ++t) {
         const int d2 = t * t + 1;
@@ -260,35 +346,23 @@ __device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst,
             int64_t b;
             const int m = col_len(P, row + xx, &b);
             const int cnt = P.erode ? m + 1 : m;
-            for (int k = 0; k < cnt; ++k) {
+            int k0 = cnt, k1 = cnt;
+            if (ni == 1) {
+                // Only a leading run of chords starting below I and a trailing
+                // run ending above it can poke out (starts and ends of one
+                // column's chords are both non-decreasing).
+                k0 = 0;
+                while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h1 < i0.x) ++k0;
+                k1 = cnt;
+                while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h1 > i0.y) --k1;
+            }
+            for (int k = 0; k < k0; ++k) {
                 const float2 sg = col_item(P.z, b, m, k, P.erode);
-                const float a = sg.x, e = sg.y;
-                if (in_list(Ip, ni, a - h1, e + h1)) continue;
-                // parts of [a, e] not covered by U (closures)
-                int idx = lv_lower_hi(U, n, a);
-                float p = a;
-                bool done = false;
-                while (idx < n) {
-                    const float2 u = U.get(idx);
-                    if (u.x > e) break;
-                    if (u.x > p) {
-                        if (!in_list(Ip, ni, p - h1, u.x + h1)) {
-                            if (FILL) { dst[np] = make_float2(p, u.x); dtag[np] = (uint8_t)t; }
-                            ++np;
-                        }
-                    }
-                    if (u.y >= e) { done = true; break; }
-                    p = fmaxf(p, u.y);
-                    ++idx;
-                }
-                if (!done && (p < e || a == e)) {
-                    if (!in_list(Ip, ni, p - h1, e + h1)) {
-                        if (FILL) { dst[np] = make_float2(p, e); dtag[np] = (uint8_t)t; }
-                        ++np;
-                    }
-                }
-                n = lv_insert(U, n, a, e);
-                if (n < 0) return -1;
+                k2_segment<FILL>(Ip, ni, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag);
+            }
+            for (int k = k1; k < cnt; ++k) {
+                const float2 sg = col_item(P.z, b, m, k, P.erode);
+                k2_segment<FILL>(Ip, ni, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag);
             }
         }
     }
@@ -305,6 +379,9 @@ __device__ int k3_column(const OpParams& P, int64_t c, const LV& U) {
     const float2* V = P.A + P.offA[c];
     for (int i = 0; i < n0; ++i) U.set(i, V[i]);
     int n = n0;
+    // While the union is one interval, keep it in registers: most seed
+    // chords land inside it and are dropped after two compares.
+    float2 u0 = n == 1 ? U.get(0) : make_float2(0.f, 0.f);
     for (int dy = 1; dy <= P.R; ++dy) {
         const int dy2 = dy * dy;
         for (int s = 0; s < 2; ++s) {
@@ -318,8 +395,11 @@ __device__ int k3_column(const OpParams& P, int64_t c, const LV& U) {
                 if (d2 > P.d2max) continue;
                 const float h = P.H[d2];
                 const float2 pc = P.B[j];
-                n = lv_insert(U, n, pc.x - h, pc.y + h);
+                const float lo = pc.x - h, hi = pc.y + h;
+                if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
+                n = lv_insert(U, n, lo, hi);
                 if (n < 0) return -1;
+                if (n == 1) u0 = U.get(0);
             }
         }
     }
@@ -401,7 +481,8 @@ __device__ __forceinline__ void push_overflow(const OpParams& P, int stage, int6
 }
 
 // Carve `len` intervals from the arena; nullptr (and a workspace error) if
-// it does not fit.
+// it does not fit.  The counter advances either way, so after a failed call
+// it holds the arena size every replayed column together would need.
 __device__ float2* arena_alloc(const OpParams& P, int64_t len) {
     const unsigned long long base = atomicAdd(&P.hdr->arena, (unsigned long long)len);
     const unsigned long long end = base + (unsigned long long)len;
@@ -453,7 +534,7 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(OpParams P) {
         const int64_t c = P.ovf[(int64_t)ST_K1 * P.ncols + i];
         const int64_t bound = k1_bound(P, c);
         float2* buf = arena_alloc(P, bound);
-        if (!buf) return;
+        if (!buf) continue;  // keep counting the arena demand
         LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k1_column(P, c, U);
         if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
@@ -487,7 +568,7 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(OpParams P) {
         const int64_t c = P.ovf[(int64_t)ST_K1B * P.ncols + i];
         const int64_t bound = k1b_bound(P, c);
         float2* buf = arena_alloc(P, 2 * bound);
-        if (!buf) return;
+        if (!buf) continue;  // keep counting the arena demand
         const int cap = (int)min<int64_t>(bound, 0x7fffffff);
         LV L0{buf, 1, cap}, L1{buf + bound, 1, cap};
         int res = 0;
@@ -505,28 +586,7 @@ __global__ void __launch_bounds__(WG) k_seeds_count(OpParams P) {
     const int64_t c = map_block(nb) * WG + threadIdx.x;
     if (c >= P.ncols) return;
     LV U{&lds[threadIdx.x], WG, CAP};
-    const int np = k2_column<false>(P, c, U, nullptr, nullptr);
-    if (np < 0) {
-        push_overflow(P, ST_K2C, c);
-        P.cntB[c] = 0;
-    } else {
-        P.cntB[c] = np;
-    }
-}
-
-__global__ void __launch_bounds__(WG) k_seeds_count_fb(OpParams P) {
-    if (P.hdr->abort) return;
-    const int cnt = P.hdr->novf[ST_K2C];
-    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t c = P.ovf[(int64_t)ST_K2C * P.ncols + i];
-        const int64_t bound = k1_bound(P, c);
-        float2* buf = arena_alloc(P, bound);
-        if (!buf) return;
-        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
-        const int np = k2_column<false>(P, c, U, nullptr, nullptr);
-        if (np < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
-        P.cntB[c] = np;
-    }
+    P.cntB[c] = k2_column<false>(P, c, U, nullptr, nullptr);
 }
 
 // Checks the scanned seed count against the buffer; all lanes of all blocks
@@ -547,28 +607,13 @@ template <int CAP>
 __global__ void __launch_bounds__(WG) k_seeds_fill(OpParams P) {
     __shared__ float2 lds[CAP * WG];
     if (P.hdr->abort || !seeds_fit(P)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.hdr->nseeds = P.offB[P.ncols];
     const int64_t nb = (P.ncols + WG - 1) / WG;
     const int64_t c = map_block(nb) * WG + threadIdx.x;
     if (c >= P.ncols) return;
     LV U{&lds[threadIdx.x], WG, CAP};
     const int64_t o = P.offB[c];
-    const int np = k2_column<true>(P, c, U, P.B + o, P.tagB + o);
-    if (np < 0) push_overflow(P, ST_K2F, c);
-}
-
-__global__ void __launch_bounds__(WG) k_seeds_fill_fb(OpParams P) {
-    if (P.hdr->abort || !seeds_fit(P)) return;
-    const int cnt = P.hdr->novf[ST_K2F];
-    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t c = P.ovf[(int64_t)ST_K2F * P.ncols + i];
-        const int64_t bound = k1_bound(P, c);
-        float2* buf = arena_alloc(P, bound);
-        if (!buf) return;
-        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
-        const int64_t o = P.offB[c];
-        const int np = k2_column<true>(P, c, U, P.B + o, P.tagB + o);
-        if (np < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
-    }
+    k2_column<true>(P, c, U, P.B + o, P.tagB + o);
 }
 
 template <int CAP>
@@ -595,7 +640,7 @@ __global__ void __launch_bounds__(WG) k_union_fb(OpParams P) {
         const int64_t c = P.ovf[(int64_t)ST_K3 * P.ncols + i];
         const int64_t bound = k3_bound(P, c);
         float2* buf = arena_alloc(P, bound);
-        if (!buf) return;
+        if (!buf) continue;  // keep counting the arena demand
         LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k3_column(P, c, U);
         if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
@@ -798,29 +843,45 @@ hipError_t launch_validate(const OpParams& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-constexpr int CAP_K1 = 32;
-constexpr int CAP_K1B = 16;
+constexpr int CAP_K1 = 64;
+constexpr int CAP_K1B = 32;
 constexpr int CAP_K2 = 48;
-constexpr int CAP_K3 = 32;
+constexpr int CAP_K3 = 64;
 
-hipError_t launch_offset_pass(const OpParams& p, hipStream_t s) {
+hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev) {
     const unsigned nb = (unsigned)((p.ncols + WG - 1) / WG);
     const dim3 g(nb), b(WG), gf(FALLBACK_BLOCKS);
+    hipError_t e = hipSuccess;
+#define DX_MARK(i) \
+    if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) return e
+    DX_MARK(0);
     hipLaunchKernelGGL(k_row_offset<CAP_K1>, g, b, 0, s, p);
+    DX_MARK(1);
     hipLaunchKernelGGL(k_row_offset_fb, gf, b, 0, s, p);
+    DX_MARK(2);
     hipLaunchKernelGGL(k_neighbour<CAP_K1B>, g, b, 0, s, p);
+    DX_MARK(3);
     hipLaunchKernelGGL(k_neighbour_fb, gf, b, 0, s, p);
+    DX_MARK(4);
     hipLaunchKernelGGL(k_seeds_count<CAP_K2>, g, b, 0, s, p);
-    hipLaunchKernelGGL(k_seeds_count_fb, gf, b, 0, s, p);
-    hipError_t e = scan_counts(p.cntB, p.ncols, p.bsum, p.offB, s);
+    DX_MARK(5);
+    DX_MARK(6);
+    e = scan_counts(p.cntB, p.ncols, p.bsum, p.offB, s);
     if (e != hipSuccess) return e;
+    DX_MARK(7);
     hipLaunchKernelGGL(k_seeds_fill<CAP_K2>, g, b, 0, s, p);
-    hipLaunchKernelGGL(k_seeds_fill_fb, gf, b, 0, s, p);
+    DX_MARK(8);
+    DX_MARK(9);
     hipLaunchKernelGGL(k_union<CAP_K3>, g, b, 0, s, p);
+    DX_MARK(10);
     hipLaunchKernelGGL(k_union_fb, gf, b, 0, s, p);
+    DX_MARK(11);
     e = scan_counts(p.cntC, p.ncols, p.bsum, p.out_col_ptr, s);
     if (e != hipSuccess) return e;
+    DX_MARK(12);
     hipLaunchKernelGGL(k_copy_out, dim3((unsigned)((p.ncols + 255) / 256)), dim3(256), 0, s, p);
+    DX_MARK(13);
+#undef DX_MARK
     return hipGetLastError();
 }
 

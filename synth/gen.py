@@ -11,6 +11,8 @@ Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64).
 from __future__ import annotations
 
 import math
+import multiprocessing
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -82,10 +84,7 @@ def canonical_csr(cols: np.ndarray, lo: np.ndarray, hi: np.ndarray, ncols: int):
     start[1:] = klo[1:] > run[:-1]
     gidx = np.flatnonzero(start)
     glo = lo32[gidx]
-    ghi_key = np.maximum.reduceat(khi, gidx)
-    # recover the float of the group maximum: find it as the max of hi32 per group
     ghi = np.maximum.reduceat(hi32, gidx)
-    del ghi_key
     gcol = cols[gidx]
     counts = np.bincount(gcol, minlength=ncols).astype(np.int64)
     col_ptr = np.zeros(ncols + 1, np.int64)
@@ -194,9 +193,73 @@ def primitives_grid(seed: int, n: int = 512, count: int = 1350, smin: float = 4.
                                    "size_range": [smin, smax]})
 
 
+def _gyroid_rows(args):
+    """Canonical CSR of gyroid rows [yb, ye) (worker for gyroid_grid)."""
+    n, H, period, t, ph, yb, ye = args
+    k = 2.0 * math.pi / period
+    nper = int(math.ceil(H / period)) + 4
+    xs = np.arange(n, dtype=np.float64)
+    X, Y = np.meshgrid(xs + 0.5 + ph[0], np.arange(yb, ye, dtype=np.float64) + 0.5 + ph[1])
+    X, Y = X.ravel(), Y.ravel()
+    cid = np.arange((ye - yb) * n, dtype=np.int64)
+    A = np.sin(k * X) * np.cos(k * Y)
+    sy, cx = np.sin(k * Y), np.cos(k * X)
+    M = np.sqrt(sy * sy + cx * cx)
+    theta = np.arctan2(cx, sy)
+    flat = M < 1e-12
+    Ms = np.where(flat, 1.0, M)
+    ulo = np.maximum(-1.0, (-t - A) / Ms)
+    uhi = np.minimum(1.0, (t - A) / Ms)
+    some = (ulo <= uhi) & ~flat
+    full_flat = flat & (np.abs(A) <= t)
+    alpha = np.arccos(np.clip(uhi, -1.0, 1.0))
+    beta = np.arccos(np.clip(ulo, -1.0, 1.0))
+    lo_clip = uhi >= 1.0   # alpha == 0: arcs centred at 2 pi m
+    hi_clip = ulo <= -1.0  # beta == pi: arcs centred at 2 pi m + pi
+    # phi = k (z + ph_z) - theta ; z = (phi + theta) / k - ph_z
+    phi0 = k * ph[2] - theta
+    m0 = np.floor(phi0 / (2 * math.pi)) - 2
+    ms = m0[:, None] + np.arange(nper + 2)[None, :]
+    base = 2 * math.pi * ms
+    a_, b_ = alpha[:, None], beta[:, None]
+    full = (some & lo_clip & hi_clip) | full_flat
+    c1 = some & lo_clip & ~hi_clip
+    c2 = some & hi_clip & ~lo_clip
+    c3 = some & ~lo_clip & ~hi_clip
+    segs = [(c1, base - b_, base + b_), (c2, base + a_, base + 2 * math.pi - a_),
+            (c3, base + a_, base + b_), (c3, base + 2 * math.pi - b_, base + 2 * math.pi - a_)]
+    th = theta[:, None]
+    cols_all, lo_all, hi_all = [], [], []
+    for mask, plo, phi_hi in segs:
+        if not mask.any():
+            continue
+        zl = (plo[mask] + th[mask]) / k - ph[2]
+        zh = (phi_hi[mask] + th[mask]) / k - ph[2]
+        cc = np.broadcast_to(cid[mask][:, None], zl.shape)
+        zl = np.maximum(zl, 0.0)
+        zh = np.minimum(zh, H)
+        keep = zl < zh
+        cols_all.append(cc[keep])
+        lo_all.append(zl[keep])
+        hi_all.append(zh[keep])
+    if full.any():
+        cols_all.append(cid[full])
+        lo_all.append(np.zeros(int(full.sum())))
+        hi_all.append(np.full(int(full.sum()), H))
+    if cols_all:
+        cols = np.concatenate(cols_all)
+        lo = np.concatenate(lo_all)
+        hi = np.concatenate(hi_all)
+    else:
+        cols = np.zeros(0, np.int64)
+        lo = hi = np.zeros(0)
+    col_ptr, z = canonical_csr(cols, lo, hi, (ye - yb) * n)
+    return np.diff(col_ptr).astype(np.int32), z
+
+
 def gyroid_grid(seed: int, n: int = 2048, height: float | None = None,
                 period: float = 64.0, t: float = 0.225,
-                rows: tuple[int, int] | None = None) -> DexelGrid:
+                rows: tuple[int, int] | None = None, workers: int | None = None) -> DexelGrid:
     """Thin-walled gyroid lattice {|f| <= t}, f = sin kX cos kY + sin kY cos kZ
     + sin kZ cos kX, k = 2 pi / period, with seeded phase shifts, sliced in
     closed form along each z-ray and clipped to z in [0, height].
@@ -205,76 +268,32 @@ def gyroid_grid(seed: int, n: int = 2048, height: float | None = None,
     M = sqrt(sin^2 kY + cos^2 kX), theta = atan2(cos kX, sin kY).
     ``rows`` restricts generation to y in [rows[0], rows[1]) (same values as
     the full grid there; the returned grid then has ny = rows[1] - rows[0]).
+    Rows are generated in independent chunks (in parallel for large grids).
     """
     rng = np.random.default_rng(seed)
     ph = rng.uniform(0.0, period, size=3)
     H = float(n if height is None else height)
-    k = 2.0 * math.pi / period
     y0, y1 = (0, n) if rows is None else rows
-    nyl = y1 - y0
-    nper = int(math.ceil(H / period)) + 4
-    cols_all, lo_all, hi_all = [], [], []
-    chunk = max(1, (1 << 19) // max(1, n))  # rows per chunk
-    xs = np.arange(n, dtype=np.float64)
-    for yb in range(y0, y1, chunk):
-        ye = min(y1, yb + chunk)
-        X, Y = np.meshgrid(xs + 0.5 + ph[0], np.arange(yb, ye, dtype=np.float64) + 0.5 + ph[1])
-        X, Y = X.ravel(), Y.ravel()
-        cid = ((np.arange(yb, ye)[:, None] - y0) * n + np.arange(n)[None, :]).ravel()
-        A = np.sin(k * X) * np.cos(k * Y)
-        sy, cx = np.sin(k * Y), np.cos(k * X)
-        M = np.sqrt(sy * sy + cx * cx)
-        theta = np.arctan2(cx, sy)
-        flat = M < 1e-12
-        Ms = np.where(flat, 1.0, M)
-        ulo = np.maximum(-1.0, (-t - A) / Ms)
-        uhi = np.minimum(1.0, (t - A) / Ms)
-        some = (ulo <= uhi) & ~flat
-        full_flat = flat & (np.abs(A) <= t)
-        alpha = np.arccos(np.clip(uhi, -1.0, 1.0))
-        beta = np.arccos(np.clip(ulo, -1.0, 1.0))
-        lo_clip = uhi >= 1.0   # alpha == 0: intervals centred at 2 pi m
-        hi_clip = ulo <= -1.0  # beta == pi: intervals centred at 2 pi m + pi
-        # phi = k (z + ph_z) - theta ; z = (phi + theta) / k - ph_z
-        phi0 = k * ph[2] - theta
-        m0 = np.floor(phi0 / (2 * math.pi)) - 2
-        ms = m0[:, None] + np.arange(nper + 2)[None, :]
-        base = 2 * math.pi * ms
-        a_, b_ = alpha[:, None], beta[:, None]
-        segs = []
-        # case alpha==0 & beta==pi -> full column
-        full = (some & lo_clip & hi_clip) | full_flat
-        # case alpha == 0, beta < pi
-        c1 = some & lo_clip & ~hi_clip
-        segs.append((c1, base - b_, base + b_))
-        # case beta == pi, alpha > 0
-        c2 = some & hi_clip & ~lo_clip
-        segs.append((c2, base + a_, base + 2 * math.pi - a_))
-        # generic case: two arcs per period
-        c3 = some & ~lo_clip & ~hi_clip
-        segs.append((c3, base + a_, base + b_))
-        segs.append((c3, base + 2 * math.pi - b_, base + 2 * math.pi - a_))
-        th = theta[:, None]
-        for mask, plo, phi_hi in segs:
-            if not mask.any():
-                continue
-            zl = (plo[mask] + th[mask]) / k - ph[2]
-            zh = (phi_hi[mask] + th[mask]) / k - ph[2]
-            cc = np.broadcast_to(cid[mask][:, None], zl.shape)
-            zl = np.maximum(zl, 0.0)
-            zh = np.minimum(zh, H)
-            keep = zl < zh
-            cols_all.append(cc[keep])
-            lo_all.append(zl[keep])
-            hi_all.append(zh[keep])
-        if full.any():
-            cols_all.append(cid[full])
-            lo_all.append(np.zeros(int(full.sum())))
-            hi_all.append(np.full(int(full.sum()), H))
-    parts = (cols_all, lo_all, hi_all)
-    return _assemble(n, nyl, parts, {"generator": "gyroid", "seed": seed, "n": n,
-                                     "height": H, "period": period, "wall_t": t,
-                                     "phase": ph.tolist(), "rows": [y0, y1]})
+    chunk = max(1, (1 << 18) // max(1, n))
+    jobs = [(n, H, period, t, ph, yb, min(y1, yb + chunk)) for yb in range(y0, y1, chunk)]
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if len(jobs) >= 8 else 1
+    if workers > 1:
+        ctx = multiprocessing.get_context("fork")
+        with ctx.Pool(workers) as pool:
+            parts = pool.map(_gyroid_rows, jobs)
+    else:
+        parts = [_gyroid_rows(j) for j in jobs]
+    counts = np.concatenate([p[0] for p in parts]).astype(np.int64)
+    col_ptr = np.zeros(counts.size + 1, np.int64)
+    np.cumsum(counts, out=col_ptr[1:])
+    z = np.concatenate([p[1] for p in parts]) if parts else np.zeros(0, np.float32)
+    g = DexelGrid(n, y1 - y0, col_ptr, z, {"generator": "gyroid", "seed": seed, "n": n,
+                                           "height": H, "period": period, "wall_t": t,
+                                           "phase": ph.tolist(), "rows": [y0, y1]})
+    g.meta.update(g.stats())
+    g.meta["generator_version"] = GENERATOR_VERSION
+    return g
 
 
 # ---------------------------------------------------------------------------
