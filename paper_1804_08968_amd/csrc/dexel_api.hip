@@ -57,7 +57,7 @@ void radius_params(float r, int* R, int* d2max) {
 
 // Workspace layout for one call.
 struct Layout {
-    size_t hdr, lut, offA, cntA, A, offI, cntI, I, offB, cntB, B, tagB, offC, cntC, C, ovf, arena,
+    size_t hdr, lut, offA, cntA, A, offI, cntI, I, offB, cntB, B, tagB, hullB, offC, cntC, C, ovf, arena,
         bsum, mid_ptr, mid_z, total;
 };
 
@@ -82,6 +82,7 @@ Layout make_layout(int64_t ncols, int64_t cap, int d2max, bool chain) {
     L.cntB = take(4 * nc);
     L.B = take(8 * cp);
     L.tagB = take(cp);
+    L.hullB = take(8 * nc);
     L.offC = take(8 * nc);
     L.cntC = take(4 * nc);
     L.C = take(8 * cp);
@@ -165,6 +166,7 @@ OpParams base_params(const Layout& L, char* ws, int64_t ncols, int64_t cap) {
     p.cntB = (int32_t*)(ws + L.cntB);
     p.B = (float2*)(ws + L.B);
     p.tagB = (uint8_t*)(ws + L.tagB);
+    p.hullB = (float2*)(ws + L.hullB);
     p.offC = (int64_t*)(ws + L.offC);
     p.cntC = (int32_t*)(ws + L.cntC);
     p.C = (float2*)(ws + L.C);

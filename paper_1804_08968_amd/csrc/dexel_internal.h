@@ -45,6 +45,7 @@ struct OpParams {
     int64_t* offI; int32_t* cntI; float2* I;
     // B: per-column extrusion seeds (closest-parent pieces) kept for the y pass, CSR
     int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB;
+    float2* hullB;            // per column: hull of the kept seeds' chords at |dy| = 1
     // C: per-column result (complemented for erosion)
     int64_t* offC; int32_t* cntC; float2* C;
     int32_t* ovf;             // [NSTAGE * ncols] overflow column lists

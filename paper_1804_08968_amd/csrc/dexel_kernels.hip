@@ -46,6 +46,7 @@ namespace dexel {
 
 constexpr int WG = 64;
 constexpr int FALLBACK_BLOCKS = 256;
+constexpr int CAP_FB = 160;  // LDS list capacity of the replay kernels' first tier
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -144,7 +145,19 @@ __device__ int lv_insert_fwd(const LV& U, int n, float lo, float hi, int* hint) 
 __device__ int insert_chords(const OpParams& P, const LV& U, int n, int64_t b, int m, int k0,
                              int k1, float h) {
     int hint = 0;
-    for (int k = k0; k < k1; ++k) {
+    int k = k0;
+    if (!P.erode) {
+        // four loads in flight per lane before the dependent list updates
+        for (; k + 4 <= k1; k += 4) {
+            const float2 c0 = P.z[b + k], c1 = P.z[b + k + 1];
+            const float2 c2 = P.z[b + k + 2], c3 = P.z[b + k + 3];
+            if ((n = lv_insert_fwd(U, n, c0.x - h, c0.y + h, &hint)) < 0) return -1;
+            if ((n = lv_insert_fwd(U, n, c1.x - h, c1.y + h, &hint)) < 0) return -1;
+            if ((n = lv_insert_fwd(U, n, c2.x - h, c2.y + h, &hint)) < 0) return -1;
+            if ((n = lv_insert_fwd(U, n, c3.x - h, c3.y + h, &hint)) < 0) return -1;
+        }
+    }
+    for (; k < k1; ++k) {
         const float2 iv = col_item(P.z, b, m, k, P.erode);
         n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
         if (n < 0) return -1;
@@ -295,11 +308,29 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
 // would hide are then kept whole, which adds valid seeds and changes
 // nothing in the result.  FILL == false: returns the number of kept pieces;
 // FILL == true: also writes them at dst.
+// Is [lo, hi] inside I(c)?  A one-interval I is tested from registers.
+__device__ __forceinline__ bool in_I(const float2* Ip, int ni, float2 i0, float lo, float hi) {
+    if (ni == 1) return i0.x <= lo && hi <= i0.y;
+    return in_list(Ip, ni, lo, hi);
+}
+
 template <bool FILL>
-__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, const LV& U, int* n, float a,
-                                           float e, float h1, int t, int* np, float2* dst,
-                                           uint8_t* dtag) {
-    if (in_list(Ip, ni, a - h1, e + h1)) return;
+__device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, int* np, float2* dst,
+                                        uint8_t* dtag, float2* hull) {
+    if (FILL) {
+        dst[*np] = make_float2(p, q);
+        dtag[*np] = (uint8_t)t;
+        hull->x = fminf(hull->x, p - h1);
+        hull->y = fmaxf(hull->y, q + h1);
+    }
+    ++*np;
+}
+
+template <bool FILL>
+__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, float2 i0, const LV& U, int* n,
+                                           float a, float e, float h1, int t, int* np,
+                                           float2* dst, uint8_t* dtag, float2* hull) {
+    if (in_I(Ip, ni, i0, a - h1, e + h1)) return;
     // parts of [a, e] not covered by U (closures)
     int idx = lv_lower_hi(U, *n, a);
     float p = a;
@@ -308,27 +339,22 @@ __device__ __forceinline__ void k2_segment(const float2* Ip, int ni, const LV& U
         const float2 u = U.get(idx);
         if (u.x > e) break;
         if (u.x > p) {
-            if (!in_list(Ip, ni, p - h1, u.x + h1)) {
-                if (FILL) { dst[*np] = make_float2(p, u.x); dtag[*np] = (uint8_t)t; }
-                ++*np;
-            }
+            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit<FILL>(p, u.x, h1, t, np, dst, dtag, hull);
         }
         if (u.y >= e) { done = true; break; }
         p = fmaxf(p, u.y);
         ++idx;
     }
     if (!done && (p < e || a == e)) {
-        if (!in_list(Ip, ni, p - h1, e + h1)) {
-            if (FILL) { dst[*np] = make_float2(p, e); dtag[*np] = (uint8_t)t; }
-            ++*np;
-        }
+        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit<FILL>(p, e, h1, t, np, dst, dtag, hull);
     }
     const int nn = lv_insert(U, *n, a, e);
     if (nn >= 0) *n = nn;
 }
 
 template <bool FILL>
-__device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst, uint8_t* dtag) {
+__device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst, uint8_t* dtag,
+                         float2* hull) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -346,23 +372,45 @@ __device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst,
             int64_t b;
             const int m = col_len(P, row + xx, &b);
             const int cnt = P.erode ? m + 1 : m;
-            int k0 = cnt, k1 = cnt;
-            if (ni == 1) {
-                // Only a leading run of chords starting below I and a trailing
-                // run ending above it can poke out (starts and ends of one
-                // column's chords are both non-decreasing).
-                k0 = 0;
-                while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h1 < i0.x) ++k0;
-                k1 = cnt;
-                while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h1 > i0.y) --k1;
+            // Chords that can poke out of I: for each gap of I (the two
+            // unbounded ends included) the chords meeting it form one run,
+            // because a column's chord starts and chord ends are both
+            // non-decreasing.  Short columns are simply scanned whole.
+            if (ni == 0 || cnt <= 8) {
+                for (int k = 0; k < cnt; ++k) {
+                    const float2 sg = col_item(P.z, b, m, k, P.erode);
+                    k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
+                }
+                continue;
             }
-            for (int k = 0; k < k0; ++k) {
+            const float ilo = ni == 1 ? i0.x : Ip[0].x;
+            const float ihi = ni == 1 ? i0.y : Ip[ni - 1].y;
+            int k = 0;
+            for (; k < cnt; ++k) {  // gap below I
                 const float2 sg = col_item(P.z, b, m, k, P.erode);
-                k2_segment<FILL>(Ip, ni, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag);
+                if (!(sg.x - h1 < ilo)) break;
+                k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
             }
-            for (int k = k1; k < cnt; ++k) {
+            int next = k;
+            for (int g = 1; g < ni; ++g) {  // interior gaps (I[g-1].y, I[g].x)
+                const float glo = Ip[g - 1].y, ghi = Ip[g].x;
+                int l = next, hh = cnt;  // first chord with end > glo
+                while (l < hh) {
+                    const int mid = (l + hh) >> 1;
+                    if (col_item(P.z, b, m, mid, P.erode).y + h1 > glo) hh = mid; else l = mid + 1;
+                }
+                for (k = l; k < cnt; ++k) {
+                    const float2 sg = col_item(P.z, b, m, k, P.erode);
+                    if (!(sg.x - h1 < ghi)) break;
+                    k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
+                }
+                next = max(next, k);
+            }
+            int k1 = cnt;  // gap above I
+            while (k1 > next && col_item(P.z, b, m, k1 - 1, P.erode).y + h1 > ihi) --k1;
+            for (k = k1; k < cnt; ++k) {
                 const float2 sg = col_item(P.z, b, m, k, P.erode);
-                k2_segment<FILL>(Ip, ni, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag);
+                k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
             }
         }
     }
@@ -388,6 +436,16 @@ __device__ int k3_column(const OpParams& P, int64_t c, const LV& U) {
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
             const int64_t cc = (int64_t)yy * P.nx + x;
+            // Every chord of this seed column at |dy| >= 1 lies inside its hull
+            // at |dy| = 1; skip the column when the hull is inside the union.
+            const float2 hb = P.hullB[cc];
+            if (hb.x > hb.y) continue;
+            if (n == 1) {
+                if (u0.x <= hb.x && hb.y <= u0.y) continue;
+            } else {
+                const int i = lv_lower_hi(U, n, hb.y);
+                if (i < n && U.get(i).x <= hb.x) continue;
+            }
             const int64_t pb = P.offB[cc], pe = P.offB[cc + 1];
             for (int64_t j = pb; j < pe; ++j) {
                 const int t = P.tagB[j];
@@ -528,10 +586,19 @@ __global__ void __launch_bounds__(WG) k_row_offset(OpParams P) {
 }
 
 __global__ void __launch_bounds__(WG) k_row_offset_fb(OpParams P) {
+    __shared__ float2 lds[CAP_FB * WG];
     if (P.hdr->abort) return;
     const int cnt = P.hdr->novf[ST_K1];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
         const int64_t c = P.ovf[(int64_t)ST_K1 * P.ncols + i];
+        {
+            LV L{&lds[threadIdx.x], WG, CAP_FB};
+            const int n = k1_column(P, c, L);
+            if (n >= 0) {
+                emit_lane(P, c, L, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+                continue;
+            }
+        }
         const int64_t bound = k1_bound(P, c);
         float2* buf = arena_alloc(P, bound);
         if (!buf) continue;  // keep counting the arena demand
@@ -562,10 +629,21 @@ __global__ void __launch_bounds__(WG) k_neighbour(OpParams P) {
 }
 
 __global__ void __launch_bounds__(WG) k_neighbour_fb(OpParams P) {
+    __shared__ float2 lds[CAP_FB * WG];
     if (P.hdr->abort) return;
     const int cnt = P.hdr->novf[ST_K1B];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
         const int64_t c = P.ovf[(int64_t)ST_K1B * P.ncols + i];
+        {
+            LV L0{&lds[threadIdx.x], WG, CAP_FB / 2};
+            LV L1{&lds[(CAP_FB / 2) * WG + threadIdx.x], WG, CAP_FB / 2};
+            int res = 0;
+            const int n = k1b_column(P, c, L0, L1, &res);
+            if (n >= 0) {
+                emit_lane(P, c, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+                continue;
+            }
+        }
         const int64_t bound = k1b_bound(P, c);
         float2* buf = arena_alloc(P, 2 * bound);
         if (!buf) continue;  // keep counting the arena demand
@@ -586,7 +664,7 @@ __global__ void __launch_bounds__(WG) k_seeds_count(OpParams P) {
     const int64_t c = map_block(nb) * WG + threadIdx.x;
     if (c >= P.ncols) return;
     LV U{&lds[threadIdx.x], WG, CAP};
-    P.cntB[c] = k2_column<false>(P, c, U, nullptr, nullptr);
+    P.cntB[c] = k2_column<false>(P, c, U, nullptr, nullptr, nullptr);
 }
 
 // Checks the scanned seed count against the buffer; all lanes of all blocks
@@ -613,7 +691,9 @@ __global__ void __launch_bounds__(WG) k_seeds_fill(OpParams P) {
     if (c >= P.ncols) return;
     LV U{&lds[threadIdx.x], WG, CAP};
     const int64_t o = P.offB[c];
-    k2_column<true>(P, c, U, P.B + o, P.tagB + o);
+    float2 hull = make_float2(DX_INF, -DX_INF);
+    k2_column<true>(P, c, U, P.B + o, P.tagB + o, &hull);
+    P.hullB[c] = hull;
 }
 
 template <int CAP>
@@ -634,10 +714,19 @@ __global__ void __launch_bounds__(WG) k_union(OpParams P) {
 }
 
 __global__ void __launch_bounds__(WG) k_union_fb(OpParams P) {
+    __shared__ float2 lds[CAP_FB * WG];
     if (P.hdr->abort) return;
     const int cnt = P.hdr->novf[ST_K3];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
         const int64_t c = P.ovf[(int64_t)ST_K3 * P.ncols + i];
+        {
+            LV L{&lds[threadIdx.x], WG, CAP_FB};
+            const int n = k3_column(P, c, L);
+            if (n >= 0) {
+                emit_lane(P, c, L, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+                continue;
+            }
+        }
         const int64_t bound = k3_bound(P, c);
         float2* buf = arena_alloc(P, bound);
         if (!buf) continue;  // keep counting the arena demand
@@ -843,10 +932,10 @@ hipError_t launch_validate(const OpParams& p, hipStream_t s) {
     return hipGetLastError();
 }
 
-constexpr int CAP_K1 = 64;
+constexpr int CAP_K1 = 40;
 constexpr int CAP_K1B = 32;
 constexpr int CAP_K2 = 48;
-constexpr int CAP_K3 = 64;
+constexpr int CAP_K3 = 32;
 
 hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev) {
     const unsigned nb = (unsigned)((p.ncols + WG - 1) / WG);
