@@ -153,6 +153,53 @@ class Plan:
         return DeviceGrid(self.grid.nx, self.grid.ny, self.col, self.z)
 
 
+def _items(grids, radii, ops, outs):
+    arr = []
+    for g, r, op, o in zip(grids, radii, ops, outs):
+        it = dexel_batch_item()
+        it.in_ = g.view()
+        it.r = float(r)
+        it.op = OPS[op]
+        it.out = make_out(g.nx, g.ny, o[0], o[1], o[2], o[3])
+        arr.append(it)
+    return arr
+
+
+def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: int = 8):
+    """Offset many shapes in one enqueue (dexel_batch_offset); returns a list
+    of DeviceGrids.  Retries with a larger workspace or larger outputs."""
+    grids = list(grids)
+    radii = [float(r) for r in radii]
+    ops = list(ops)
+    dev = engine.device
+    caps = [g.nseg + g.nx * g.ny + 1024 for g in grids]
+    hint = engine._hint
+    for _ in range(max_tries):
+        outs = [(torch.empty(g.nx * g.ny + 1, dtype=torch.int64, device=dev),
+                 torch.empty(2 * max(c, 1), dtype=torch.float32, device=dev),
+                 torch.zeros(1, dtype=torch.int64, device=dev),
+                 torch.zeros(1, dtype=torch.int32, device=dev)) for g, c in zip(grids, caps)]
+        items = _items(grids, radii, ops, outs)
+        nbytes = dexel_batch_workspace_size(engine.ctx, items, hint)
+        ws = engine.workspace(nbytes)
+        st = dexel_batch_offset(engine.ctx, items, ws, stream, DEXEL_FLAG_SYNC)
+        if st == DEXEL_OK:
+            return [DeviceGrid(g.nx, g.ny, o[0], o[1]) for g, o in zip(grids, outs)]
+        if st == DEXEL_ERR_WORKSPACE:
+            need = dexel_workspace_need(engine.ctx, ws)
+            base = hint if hint > 0 else sum(caps)
+            hint = max(int(need * 1.25) + 1024, 2 * base)
+            engine._hint = max(engine._hint, hint)
+            continue
+        if st == DEXEL_ERR_CAPACITY:
+            for i, o in enumerate(outs):
+                if int(o[3].item()) == DEXEL_ERR_CAPACITY:
+                    caps[i] = int(o[2].item()) + 1
+            continue
+        raise DexelError(st, dexel_last_error(engine.ctx))
+    raise DexelError(DEXEL_ERR_WORKSPACE, "retries exhausted")
+
+
 _default_engine = None
 
 

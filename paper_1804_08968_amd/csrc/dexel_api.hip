@@ -55,13 +55,26 @@ void radius_params(float r, int* R, int* d2max) {
     *d2max = (int)std::floor(rd * rd);
 }
 
-// Workspace layout for one call.
+// Workspace layout of one call (a batch of items; a single op is a batch of one).
 struct Layout {
-    size_t hdr, lut, offA, cntA, A, offI, cntI, I, offB, cntB, B, tagB, hullB, offC, cntC, C, ovf, arena,
-        bsum, mid_ptr, mid_z, total;
+    size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
+    size_t offA, cntA, offI, cntI, offB, cntB, hullB, offC, cntC, scanC;
+    size_t A, I, B, tagB, C, ovf, arena, bsum, mid_ptr, mid_z, total;
+    int64_t gcols1, gcols2, gmax, mid_cols;
+    std::vector<size_t> lut_off;  // per item: byte offset of its radius table
 };
 
-Layout make_layout(int64_t ncols, int64_t cap, int d2max, bool chain) {
+struct ItemInfo {
+    int64_t ncols;
+    int R, d2max;
+    bool chain;
+};
+
+int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
+
+bool is_chain(int op) { return op == DEXEL_OPEN || op == DEXEL_CLOSE; }
+
+Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -69,30 +82,47 @@ Layout make_layout(int64_t ncols, int64_t cap, int d2max, bool chain) {
         o = align_up(o + bytes);
         return at;
     };
-    const size_t nc = (size_t)ncols, cp = (size_t)cap;
+    const size_t n = items.size();
+    L.gcols1 = L.gcols2 = L.mid_cols = 0;
+    for (const auto& it : items) {
+        L.gcols1 += pad64(it.ncols);
+        if (it.chain) {
+            L.gcols2 += pad64(it.ncols);
+            L.mid_cols += it.ncols + 1;
+        }
+    }
+    L.gmax = L.gcols1 > L.gcols2 ? L.gcols1 : L.gcols2;
+    const size_t g = (size_t)L.gmax, cp = (size_t)cap;
     L.hdr = take(256);
-    L.lut = take(sizeof(float) * (size_t)(d2max + 1));
-    L.offA = take(8 * nc);
-    L.cntA = take(4 * nc);
+    L.shape_status = take(4 * n);
+    L.zbase = take(8 * n);
+    L.shapes1 = take(sizeof(dexel::Shape) * n);
+    L.shapes2 = take(sizeof(dexel::Shape) * n);
+    L.sbase1 = take(8 * (n + 1));
+    L.sbase2 = take(8 * (n + 1));
+    L.lut_off.resize(n);
+    for (size_t i = 0; i < n; ++i) L.lut_off[i] = take(sizeof(float) * (size_t)(items[i].d2max + 1));
+    L.luts = n ? L.lut_off[0] : o;
+    L.offA = take(8 * g);
+    L.cntA = take(4 * g);
+    L.offI = take(8 * g);
+    L.cntI = take(4 * g);
+    L.offB = take(8 * (g + 1));
+    L.cntB = take(4 * g);
+    L.hullB = take(8 * g);
+    L.offC = take(8 * g);
+    L.cntC = take(4 * g);
+    L.scanC = take(8 * (g + 1));
     L.A = take(8 * cp);
-    L.offI = take(8 * nc);
-    L.cntI = take(4 * nc);
     L.I = take(8 * cp);
-    L.offB = take(8 * (nc + 1));
-    L.cntB = take(4 * nc);
     L.B = take(8 * cp);
     L.tagB = take(cp);
-    L.hullB = take(8 * nc);
-    L.offC = take(8 * nc);
-    L.cntC = take(4 * nc);
     L.C = take(8 * cp);
-    L.ovf = take(4 * nc * dexel::NSTAGE);
+    L.ovf = take(4 * g * dexel::NSTAGE);
     L.arena = take(8 * cp);
-    L.bsum = take(8 * ((nc + 1023) / 1024 + 2));
-    if (chain) {
-        L.mid_ptr = take(8 * (nc + 1));
-        L.mid_z = take(8 * cp);
-    }
+    L.bsum = take(8 * ((g + 1023) / 1024 + 2));
+    L.mid_ptr = take(8 * (size_t)L.mid_cols);
+    L.mid_z = take(L.gcols2 ? 8 * cp : 0);
     L.total = o;
     return L;
 }
@@ -102,11 +132,11 @@ int64_t default_cap(const dexel_grid_view* in) {
     return in->nseg + 2 * ncols + 1024;
 }
 
-bool is_chain(int op) { return op == DEXEL_OPEN || op == DEXEL_CLOSE; }
-
 dexel_status check_view(dexel_ctx* ctx, const dexel_grid_view* in) {
     if (!in) return fail(ctx, DEXEL_ERR_INVALID, "null input view");
     if (in->nx <= 0 || in->ny <= 0) return fail(ctx, DEXEL_ERR_INVALID, "nx and ny must be >= 1");
+    if ((int64_t)in->nx * in->ny >= ((int64_t)1 << 31) - 64)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "nx * ny must be below 2^31");
     if (in->nseg < 0) return fail(ctx, DEXEL_ERR_INVALID, "nseg must be >= 0");
     if (!in->col_ptr) return fail(ctx, DEXEL_ERR_INVALID, "null input col_ptr");
     if (in->nseg > 0 && !in->z) return fail(ctx, DEXEL_ERR_INVALID, "null input z");
@@ -150,32 +180,6 @@ float* lut_for(dexel_ctx* ctx, float r, int d2max) {
     return h;
 }
 
-OpParams base_params(const Layout& L, char* ws, int64_t ncols, int64_t cap) {
-    OpParams p{};
-    p.ncols = ncols;
-    p.hdr = (WsHeader*)(ws + L.hdr);
-    p.H = (const float*)(ws + L.lut);
-    p.cap = cap;
-    p.offA = (int64_t*)(ws + L.offA);
-    p.cntA = (int32_t*)(ws + L.cntA);
-    p.A = (float2*)(ws + L.A);
-    p.offI = (int64_t*)(ws + L.offI);
-    p.cntI = (int32_t*)(ws + L.cntI);
-    p.I = (float2*)(ws + L.I);
-    p.offB = (int64_t*)(ws + L.offB);
-    p.cntB = (int32_t*)(ws + L.cntB);
-    p.B = (float2*)(ws + L.B);
-    p.tagB = (uint8_t*)(ws + L.tagB);
-    p.hullB = (float2*)(ws + L.hullB);
-    p.offC = (int64_t*)(ws + L.offC);
-    p.cntC = (int32_t*)(ws + L.cntC);
-    p.C = (float2*)(ws + L.C);
-    p.ovf = (int32_t*)(ws + L.ovf);
-    p.arena = (float2*)(ws + L.arena);
-    p.bsum = (int64_t*)(ws + L.bsum);
-    return p;
-}
-
 #define HIP_TRY(expr)                                                                    \
     do {                                                                                 \
         hipError_t e_ = (expr);                                                          \
@@ -183,70 +187,180 @@ OpParams base_params(const Layout& L, char* ws, int64_t ncols, int64_t cap) {
             return fail(ctx, DEXEL_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
     } while (0)
 
-// Enqueue one operation (any dexel_op) into an already checked workspace.
-dexel_status enqueue_op(dexel_ctx* ctx, const dexel_grid_view* in, float r, int op,
-                        dexel_grid_out* out, void* ws, size_t ws_bytes, hipStream_t s,
-                        uint32_t flags, int64_t cap_hint) {
-    const int64_t ncols = (int64_t)in->nx * in->ny;
-    const int64_t cap = cap_hint > 0 ? cap_hint : default_cap(in);
-    int R, d2max;
-    radius_params(r, &R, &d2max);
-    const bool chain = is_chain(op);
-    const Layout L = make_layout(ncols, cap, d2max, chain);
+dexel_status check_items(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,
+                         std::vector<ItemInfo>* info, bool outputs) {
+    if (n < 0 || (n > 0 && !items)) return fail(ctx, DEXEL_ERR_INVALID, "bad item list");
+    info->clear();
+    for (int32_t i = 0; i < n; ++i) {
+        const dexel_batch_item& it = items[i];
+        dexel_status st;
+        if (outputs) {
+            if ((st = check_view(ctx, &it.in)) != DEXEL_OK) return st;
+        } else {
+            if (it.in.nx <= 0 || it.in.ny <= 0 || it.in.nseg < 0)
+                return fail(ctx, DEXEL_ERR_INVALID, "bad grid size");
+        }
+        if ((st = check_radius(ctx, it.r)) != DEXEL_OK) return st;
+        if (it.op < DEXEL_DILATE || it.op > DEXEL_CLOSE) return fail(ctx, DEXEL_ERR_INVALID, "unknown op");
+        if (outputs && (st = check_out(ctx, &it.in, &it.out)) != DEXEL_OK) return st;
+        ItemInfo ii;
+        ii.ncols = (int64_t)it.in.nx * it.in.ny;
+        radius_params(it.r, &ii.R, &ii.d2max);
+        ii.chain = is_chain(it.op);
+        info->push_back(ii);
+    }
+    return DEXEL_OK;
+}
+
+int64_t batch_default_cap(int32_t n, const dexel_batch_item* items) {
+    int64_t c = 1024;
+    for (int32_t i = 0; i < n; ++i) c += default_cap(&items[i].in) - 1024;
+    return c;
+}
+
+// Largest internal capacity whose layout fits in ws_bytes (0 if none).
+int64_t cap_for_bytes(const std::vector<ItemInfo>& info, size_t ws_bytes) {
+    int64_t lo = 1, hi = 1;
+    if (make_layout(info, lo).total > ws_bytes) return 0;
+    while (make_layout(info, hi).total <= ws_bytes && hi < ((int64_t)1 << 40)) hi *= 2;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(info, mid).total <= ws_bytes) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Enqueue a batch (already argument-checked) into a workspace of ws_bytes.
+dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,
+                           const std::vector<ItemInfo>& info, void* ws, size_t ws_bytes,
+                           hipStream_t s, uint32_t flags) {
+    if (n == 0) return DEXEL_OK;
     if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
     if (((uintptr_t)ws) % kAlign != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
-    if (ws_bytes < L.total) return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than dexel_workspace_size");
+    const int64_t cap = cap_for_bytes(info, ws_bytes);
+    if (cap <= 0) return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than the minimum layout");
+    const Layout L = make_layout(info, cap);
     char* w = (char*)ws;
-    float* lut = lut_for(ctx, r, d2max);
-    if (!lut) return fail(ctx, DEXEL_ERR_HIP, "cannot allocate pinned lookup table");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DEXEL_ERR_HIP, "hipSetDevice failed");
 
-    OpParams p = base_params(L, w, ncols, cap);
-    p.nx = in->nx;
-    p.ny = in->ny;
-    p.R = R;
-    p.d2max = d2max;
-
-    HIP_TRY(dexel::launch_init_call(p.hdr, s));
-    HIP_TRY(hipMemcpyAsync(w + L.lut, lut, sizeof(float) * (size_t)(d2max + 1), hipMemcpyHostToDevice, s));
-
-    // stage list: (erode?, source, destination)
-    int ops[2] = {0, 0};
-    int nops = 1;
-    switch (op) {
-        case DEXEL_DILATE: ops[0] = 0; break;
-        case DEXEL_ERODE: ops[0] = 1; break;
-        case DEXEL_OPEN: ops[0] = 1; ops[1] = 0; nops = 2; break;
-        case DEXEL_CLOSE: ops[0] = 0; ops[1] = 1; nops = 2; break;
-        default: return fail(ctx, DEXEL_ERR_INVALID, "unknown op");
+    std::vector<dexel::Shape> sh1, sh2;
+    std::vector<int64_t> base1, base2;
+    int64_t g1 = 0, g2 = 0, mid = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const dexel_batch_item& it = items[i];
+        const ItemInfo& ii = info[i];
+        float* lut = lut_for(ctx, it.r, ii.d2max);
+        if (!lut) return fail(ctx, DEXEL_ERR_HIP, "cannot allocate pinned lookup table");
+        const int ops[2] = {it.op == DEXEL_ERODE || it.op == DEXEL_OPEN ? 1 : 0,
+                            it.op == DEXEL_CLOSE ? 1 : 0};
+        auto fill = [&](dexel::Shape& S, int64_t gbase) {
+            std::memset(&S, 0, sizeof(S));
+            S.nx = it.in.nx;
+            S.ny = it.in.ny;
+            S.ncols = ii.ncols;
+            S.gbase = gbase;
+            S.R = ii.R;
+            S.d2max = ii.d2max;
+            S.index = i;
+            S.H = (const float*)(w + L.lut_off[i]);
+            S.offA = (int64_t*)(w + L.offA) + gbase;
+            S.cntA = (int32_t*)(w + L.cntA) + gbase;
+            S.offI = (int64_t*)(w + L.offI) + gbase;
+            S.cntI = (int32_t*)(w + L.cntI) + gbase;
+            S.offB = (int64_t*)(w + L.offB) + gbase;
+            S.cntB = (int32_t*)(w + L.cntB) + gbase;
+            S.hullB = (float2*)(w + L.hullB) + gbase;
+            S.offC = (int64_t*)(w + L.offC) + gbase;
+            S.cntC = (int32_t*)(w + L.cntC) + gbase;
+            S.scanC = (int64_t*)(w + L.scanC) + gbase;
+        };
+        dexel::Shape a;
+        fill(a, g1);
+        a.col_ptr = it.in.col_ptr;
+        a.z = (const float2*)it.in.z;
+        a.nseg = it.in.nseg;
+        a.erode = ops[0];
+        if (ii.chain) {
+            int64_t* mptr = (int64_t*)(w + L.mid_ptr) + mid;
+            a.out_col_ptr = mptr;
+            a.out_z = (float2*)(w + L.mid_z);
+            a.out_zoff = a.scanC;  // the shape's base in the pass's result scan
+            a.out_cap = cap;
+            a.out_is_intermediate = 1;
+            dexel::Shape b;
+            fill(b, g2);
+            b.col_ptr = mptr;
+            b.z = (const float2*)(w + L.mid_z);
+            b.zoff = (const int64_t*)(w + L.zbase) + i;
+            b.nseg = -1;
+            b.erode = ops[1];
+            b.out_col_ptr = it.out.col_ptr;
+            b.out_z = (float2*)it.out.z;
+            b.out_cap = it.out.cap_seg;
+            b.last_pass = 1;
+            b.out_nseg = it.out.nseg_out;
+            b.out_status = it.out.status;
+            sh2.push_back(b);
+            base2.push_back(g2);
+            g2 += pad64(ii.ncols);
+            mid += ii.ncols + 1;
+        } else {
+            a.out_col_ptr = it.out.col_ptr;
+            a.out_z = (float2*)it.out.z;
+            a.out_cap = it.out.cap_seg;
+            a.last_pass = 1;
+            a.out_nseg = it.out.nseg_out;
+            a.out_status = it.out.status;
+        }
+        sh1.push_back(a);
+        base1.push_back(g1);
+        g1 += pad64(ii.ncols);
     }
-    for (int k = 0; k < nops; ++k) {
-        const bool first = (k == 0), last = (k == nops - 1);
-        p.erode = ops[k];
-        if (first) {
-            p.col_ptr = in->col_ptr;
-            p.z = (const float2*)in->z;
-            p.nseg = in->nseg;
-        } else {
-            p.col_ptr = (const int64_t*)(w + L.mid_ptr);
-            p.z = (const float2*)(w + L.mid_z);
-            p.nseg = -1;
-        }
-        if (last) {
-            p.out_col_ptr = out->col_ptr;
-            p.out_z = (float2*)out->z;
-            p.out_cap = out->cap_seg;
-            p.out_is_intermediate = 0;
-        } else {
-            p.out_col_ptr = (int64_t*)(w + L.mid_ptr);
-            p.out_z = (float2*)(w + L.mid_z);
-            p.out_cap = cap;
-            p.out_is_intermediate = 1;
-        }
-        if (!first) HIP_TRY(dexel::launch_init_op(p.hdr, s));
-        if (first) {
-            HIP_TRY(dexel::launch_check_colptr(p, s));
-            if (flags & DEXEL_FLAG_VALIDATE) HIP_TRY(dexel::launch_validate(p, s));
-        }
+    base1.push_back(g1);
+    base2.push_back(g2);
+
+    auto make_pass = [&](size_t shapes_off, size_t sbase_off, int nsh, int64_t gcols) {
+        dexel::Pass q{};
+        q.shapes = (const dexel::Shape*)(w + shapes_off);
+        q.sbase = (const int64_t*)(w + sbase_off);
+        q.nshapes = nsh;
+        q.gcols = gcols;
+        q.hdr = (WsHeader*)(w + L.hdr);
+        q.shape_status = (int32_t*)(w + L.shape_status);
+        q.cap = cap;
+        q.A = (float2*)(w + L.A);
+        q.I = (float2*)(w + L.I);
+        q.B = (float2*)(w + L.B);
+        q.tagB = (uint8_t*)(w + L.tagB);
+        q.C = (float2*)(w + L.C);
+        q.cntB_g = (int32_t*)(w + L.cntB);
+        q.offB_g = (int64_t*)(w + L.offB);
+        q.cntC_g = (int32_t*)(w + L.cntC);
+        q.scanC_g = (int64_t*)(w + L.scanC);
+        q.ovf = (int32_t*)(w + L.ovf);
+        q.arena = (float2*)(w + L.arena);
+        q.bsum = (int64_t*)(w + L.bsum);
+        return q;
+    };
+    const dexel::Pass p1 = make_pass(L.shapes1, L.sbase1, (int)sh1.size(), g1);
+    const dexel::Pass p2 = make_pass(L.shapes2, L.sbase2, (int)sh2.size(), g2);
+    int64_t* zbase = (int64_t*)(w + L.zbase);
+
+    HIP_TRY(dexel::launch_init_call(p1.hdr, p1.shape_status, n, s));
+    for (int32_t i = 0; i < n; ++i) {
+        float* lut = lut_for(ctx, items[i].r, info[i].d2max);
+        HIP_TRY(hipMemcpyAsync(w + L.lut_off[i], lut, sizeof(float) * (size_t)(info[i].d2max + 1),
+                               hipMemcpyHostToDevice, s));
+    }
+    HIP_TRY(dexel::launch_put_shapes((dexel::Shape*)(w + L.shapes1), sh1.data(), (int)sh1.size(), s));
+    HIP_TRY(dexel::launch_put_i64((int64_t*)(w + L.sbase1), base1.data(), (int)base1.size(), s));
+    if (!sh2.empty()) {
+        HIP_TRY(dexel::launch_put_shapes((dexel::Shape*)(w + L.shapes2), sh2.data(), (int)sh2.size(), s));
+        HIP_TRY(dexel::launch_put_i64((int64_t*)(w + L.sbase2), base2.data(), (int)base2.size(), s));
+    }
+    HIP_TRY(dexel::launch_check_input(p1, (flags & DEXEL_FLAG_VALIDATE) ? 1 : 0, s));
+
+    auto run_pass = [&](const dexel::Pass& q) -> dexel_status {
         hipEvent_t* ev = nullptr;
         if (ctx->profile) {
             std::vector<hipEvent_t> group;
@@ -263,22 +377,33 @@ dexel_status enqueue_op(dexel_ctx* ctx, const dexel_grid_view* in, float r, int 
             ctx->pending.push_back(group);
             ev = ctx->pending.back().data();
         }
-        HIP_TRY(dexel::launch_offset_pass(p, s, ev));
+        HIP_TRY(dexel::launch_pass(q, s, ev));
+        HIP_TRY(dexel::launch_finish(q, zbase, s));
+        return DEXEL_OK;
+    };
+    dexel_status st = run_pass(p1);
+    if (st != DEXEL_OK) return st;
+    if (!sh2.empty()) {
+        HIP_TRY(dexel::launch_init_pass(p2.hdr, s));
+        st = run_pass(p2);
+        if (st != DEXEL_OK) return st;
     }
-    HIP_TRY(dexel::launch_finish(p.hdr, out->col_ptr, ncols, out->nseg_out, out->status, s));
     return DEXEL_OK;
 }
 
-dexel_status sync_status(dexel_ctx* ctx, hipStream_t s, const int32_t* dstatus) {
+dexel_status sync_status(dexel_ctx* ctx, hipStream_t s, int32_t n, const dexel_batch_item* items) {
     HIP_TRY(hipStreamSynchronize(s));
-    int32_t st = 0;
-    HIP_TRY(hipMemcpy(&st, dstatus, sizeof(st), hipMemcpyDeviceToHost));
-    if (st != 0) {
-        char buf[96];
-        std::snprintf(buf, sizeof(buf), "device status %d", st);
-        ctx->err = buf;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t st = 0;
+        HIP_TRY(hipMemcpy(&st, items[i].out.status, sizeof(st), hipMemcpyDeviceToHost));
+        if (st != 0) {
+            char buf[96];
+            std::snprintf(buf, sizeof(buf), "device status %d (item %d)", st, (int)i);
+            ctx->err = buf;
+            return (dexel_status)st;
+        }
     }
-    return (dexel_status)st;
+    return DEXEL_OK;
 }
 
 }  // namespace
@@ -310,15 +435,11 @@ dexel_status dexel_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, flo
                                   int64_t cap_hint, size_t* bytes) {
     if (!ctx || !bytes) return DEXEL_ERR_INVALID;
     if (!in) return fail(ctx, DEXEL_ERR_INVALID, "null input view");
-    if (in->nx <= 0 || in->ny <= 0 || in->nseg < 0) return fail(ctx, DEXEL_ERR_INVALID, "bad grid size");
-    dexel_status st = check_radius(ctx, r);
-    if (st != DEXEL_OK) return st;
-    if (op < DEXEL_DILATE || op > DEXEL_CLOSE) return fail(ctx, DEXEL_ERR_INVALID, "unknown op");
-    int R, d2max;
-    radius_params(r, &R, &d2max);
-    const int64_t cap = cap_hint > 0 ? cap_hint : default_cap(in);
-    *bytes = make_layout((int64_t)in->nx * in->ny, cap, d2max, is_chain(op)).total;
-    return DEXEL_OK;
+    dexel_batch_item it{};
+    it.in = *in;
+    it.r = r;
+    it.op = op;
+    return dexel_batch_workspace_size(ctx, 1, &it, cap_hint, bytes);
 }
 
 dexel_status dexel_workspace_need(dexel_ctx* ctx, const void* ws, int64_t* cap_hint) {
@@ -334,31 +455,13 @@ dexel_status dexel_offset(dexel_ctx* ctx, const dexel_grid_view* in, float r, in
                           dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream,
                           uint32_t flags) {
     if (!ctx) return DEXEL_ERR_INVALID;
-    ctx->err.clear();
-    dexel_status st = check_view(ctx, in);
-    if (st != DEXEL_OK) return st;
-    if ((st = check_radius(ctx, r)) != DEXEL_OK) return st;
-    if ((st = check_out(ctx, in, out)) != DEXEL_OK) return st;
-    if (op < DEXEL_DILATE || op > DEXEL_CLOSE) return fail(ctx, DEXEL_ERR_INVALID, "unknown op");
-    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DEXEL_ERR_HIP, "hipSetDevice failed");
-    // The internal buffers get the largest capacity whose layout fits in
-    // ws_bytes (at least what dexel_workspace_size was asked for).
-    const int64_t ncols = (int64_t)in->nx * in->ny;
-    int R, d2max;
-    radius_params(r, &R, &d2max);
-    int64_t lo = 1, hi = 1;
-    while (make_layout(ncols, hi, d2max, is_chain(op)).total <= ws_bytes && hi < ((int64_t)1 << 40)) hi *= 2;
-    if (make_layout(ncols, lo, d2max, is_chain(op)).total > ws_bytes)
-        return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than the minimum layout");
-    while (hi - lo > 1) {
-        int64_t mid = lo + (hi - lo) / 2;
-        if (make_layout(ncols, mid, d2max, is_chain(op)).total <= ws_bytes) lo = mid; else hi = mid;
-    }
-    hipStream_t s = (hipStream_t)stream;
-    st = enqueue_op(ctx, in, r, op, out, ws, ws_bytes, s, flags, lo);
-    if (st != DEXEL_OK) return st;
-    if (flags & DEXEL_FLAG_SYNC) return sync_status(ctx, s, out->status);
-    return DEXEL_OK;
+    if (!in || !out) return fail(ctx, DEXEL_ERR_INVALID, "null input or output");
+    dexel_batch_item it{};
+    it.in = *in;
+    it.r = r;
+    it.op = op;
+    it.out = *out;
+    return dexel_batch_offset(ctx, 1, &it, ws, ws_bytes, stream, flags);
 }
 
 dexel_status dexel_dilate(dexel_ctx* ctx, const dexel_grid_view* in, float r, dexel_grid_out* out,
@@ -373,38 +476,26 @@ dexel_status dexel_erode(dexel_ctx* ctx, const dexel_grid_view* in, float r, dex
 
 dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,
                                         int64_t cap_hint, size_t* bytes) {
-    if (!ctx || !bytes || n < 0 || (n > 0 && !items)) return DEXEL_ERR_INVALID;
-    size_t best = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        size_t b = 0;
-        dexel_status st = dexel_workspace_size(ctx, &items[i].in, items[i].r, items[i].op, cap_hint, &b);
-        if (st != DEXEL_OK) return st;
-        if (b > best) best = b;
-    }
-    *bytes = best;
+    if (!ctx || !bytes) return DEXEL_ERR_INVALID;
+    std::vector<ItemInfo> info;
+    dexel_status st = check_items(ctx, n, items, &info, false);
+    if (st != DEXEL_OK) return st;
+    const int64_t cap = cap_hint > 0 ? cap_hint : batch_default_cap(n, items);
+    *bytes = make_layout(info, cap).total;
     return DEXEL_OK;
 }
 
 dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
                                 size_t ws_bytes, void* stream, uint32_t flags) {
-    if (!ctx || n < 0 || (n > 0 && !items)) return DEXEL_ERR_INVALID;
+    if (!ctx) return DEXEL_ERR_INVALID;
     ctx->err.clear();
-    for (int32_t i = 0; i < n; ++i) {
-        const dexel_batch_item& it = items[i];
-        dexel_grid_out o = it.out;
-        dexel_status st = dexel_offset(ctx, &it.in, it.r, it.op, &o, ws, ws_bytes, stream,
-                                       flags & ~DEXEL_FLAG_SYNC);
-        if (st != DEXEL_OK) return st;
-    }
-    if (flags & DEXEL_FLAG_SYNC) {
-        hipStream_t s = (hipStream_t)stream;
-        HIP_TRY(hipStreamSynchronize(s));
-        for (int32_t i = 0; i < n; ++i) {
-            int32_t st = 0;
-            HIP_TRY(hipMemcpy(&st, items[i].out.status, sizeof(st), hipMemcpyDeviceToHost));
-            if (st != 0) return (dexel_status)st;
-        }
-    }
+    std::vector<ItemInfo> info;
+    dexel_status st = check_items(ctx, n, items, &info, true);
+    if (st != DEXEL_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, flags);
+    if (st != DEXEL_OK) return st;
+    if (flags & DEXEL_FLAG_SYNC) return sync_status(ctx, s, n, items);
     return DEXEL_OK;
 }
 

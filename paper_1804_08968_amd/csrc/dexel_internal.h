@@ -7,10 +7,10 @@
 namespace dexel {
 
 // Device-side header at the start of every workspace.  Reset by k_init_call
-// at the start of a call and (bump counters only) by k_init_op before each
-// operation of a chain.
+// at the start of a call and (bump counters only) by k_init_pass before the
+// second pass of a chain.
 struct WsHeader {
-    int32_t status;                 // dexel_status, first error wins
+    int32_t status;                 // dexel_status, first error wins (workspace-wide errors)
     int32_t abort;                  // nonzero: the remaining kernels of the call exit at once
     unsigned long long need_cap;    // largest internal-buffer size (intervals) the call needed
     unsigned long long bumpA;       // bump allocators of the per-column lists
@@ -24,51 +24,111 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
-enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K2C = 2, ST_K2F = 3, ST_K3 = 4, NSTAGE = 5 };
+enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K3 = 2, NSTAGE = 3 };
 
-// Everything one dilation (or erosion) pass reads and writes.
-struct OpParams {
+// One shape of one pass, in device memory.  Per-column arrays are already
+// offset to the shape's first global column, so kernels index them with the
+// shape-local column id.
+struct Shape {
     int32_t nx, ny;
     int64_t ncols;
+    int64_t gbase;            // first global column of the shape in this pass (multiple of 64)
     const int64_t* col_ptr;   // input CSR
     const float2* z;
+    const int64_t* zoff;      // if set, the input pairs start at z + *zoff (chained pass input)
     int64_t nseg;             // input interval count (-1: unknown on the host)
     int32_t erode;            // complement on read and on write
     int32_t R;                // floor(r)
-    int32_t d2max;            // floor(r^2): integer squared distances d2 <= d2max are in the ball
+    int32_t d2max;            // floor(r^2)
+    int32_t index;            // item index (status slot)
     const float* H;           // H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..d2max
+    int64_t* offA; int32_t* cntA;
+    int64_t* offI; int32_t* cntI;
+    int64_t* offB; int32_t* cntB; float2* hullB;
+    int64_t* offC; int32_t* cntC;
+    int64_t* scanC;           // global exclusive scan of the result counts
+    // output
+    int64_t* out_col_ptr;
+    float2* out_z;
+    const int64_t* out_zoff;  // if set, results are written at out_z + *out_zoff
+    int64_t out_cap;
+    int32_t out_is_intermediate;
+    int32_t last_pass;        // write the caller's nseg_out / status after this pass
+    int64_t* out_nseg;
+    int32_t* out_status;
+};
+
+// Kernel argument of every per-pass kernel.
+struct Pass {
+    const Shape* shapes;      // [nshapes]
+    const int64_t* sbase;     // [nshapes + 1] first global column of each shape; sbase[n] = gcols
+    int32_t nshapes;
+    int32_t pad;
+    int64_t gcols;            // padded global column count of the pass
     WsHeader* hdr;
+    int32_t* shape_status;    // [items] per-item status (output capacity)
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
-    // A: per-column row offset V0 (2D dilation of the column's own row at radius r)
+    float2* A;
+    float2* I;
+    float2* B;
+    uint8_t* tagB;
+    float2* C;
+    int32_t* cntB_g;          // global views of the per-column arrays (for the scans)
+    int64_t* offB_g;
+    int32_t* cntC_g;
+    int64_t* scanC_g;
+    int32_t* ovf;             // [NSTAGE * gcols] overflow column lists (global ids)
+    float2* arena;
+    int64_t* bsum;
+};
+
+// Per-column view used by the algorithms: one shape's fields plus the
+// shared buffers.
+struct OpParams {
+    int32_t nx, ny;
+    int64_t ncols;
+    const int64_t* col_ptr;
+    const float2* z;
+    int32_t erode;
+    int32_t R;
+    int32_t d2max;
+    const float* H;
+    WsHeader* hdr;
+    int64_t cap;
     int64_t* offA; int32_t* cntA; float2* A;
-    // I: per-column intersection of V0 over the rows within R (excluding the own row)
     int64_t* offI; int32_t* cntI; float2* I;
-    // B: per-column extrusion seeds (closest-parent pieces) kept for the y pass, CSR
-    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB;
-    float2* hullB;            // per column: hull of the kept seeds' chords at |dy| = 1
-    // C: per-column result (complemented for erosion)
+    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float2* hullB;
     int64_t* offC; int32_t* cntC; float2* C;
-    int32_t* ovf;             // [NSTAGE * ncols] overflow column lists
-    float2* arena;            // global lists for overflow columns
-    int64_t* bsum;            // scan scratch
-    // output CSR
-    int64_t* out_col_ptr; float2* out_z; int64_t out_cap;
-    int32_t out_is_intermediate;   // 1: output overflow is a workspace error, not a capacity error
+    float2* arena;
+};
+
+// Descriptor upload through kernel arguments (no host buffer outlives the call).
+constexpr int DESC_CHUNK = 12;
+struct ShapeChunk {
+    Shape s[DESC_CHUNK];
+    int32_t n;
+    int32_t first;
+};
+constexpr int I64_CHUNK = 256;
+struct I64Chunk {
+    int64_t v[I64_CHUNK];
+    int32_t n;
+    int32_t first;
 };
 
 // Launchers (dexel_kernels.hip).  All enqueue on `s`, none synchronises.
-hipError_t launch_init_call(WsHeader* hdr, hipStream_t s);
-hipError_t launch_init_op(WsHeader* hdr, hipStream_t s);
-hipError_t launch_check_colptr(const OpParams& p, hipStream_t s);
-hipError_t launch_validate(const OpParams& p, hipStream_t s);
+hipError_t launch_put_shapes(Shape* dst, const Shape* host, int n, hipStream_t s);
+hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t s);
+hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s);
+hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
+hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
 // Profiled intervals of one pass, one per launch group: row offset, its
-// replay, neighbour intersection, its replay, seed count, its replay, seed
-// scan, seed fill, its replay, y dilation + union, its replay, result scan,
+// replay, neighbour intersection, its replay, seed count, (unused), seed
+// scan, seed fill, (unused), y dilation + union, its replay, result scan,
 // compaction copy.
 constexpr int NPROF = 13;
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
-hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev);
-hipError_t launch_finish(WsHeader* hdr, const int64_t* out_col_ptr, int64_t ncols,
-                         int64_t* nseg_out, int32_t* status, hipStream_t s);
+hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev);
+hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s);
 
 }  // namespace dexel

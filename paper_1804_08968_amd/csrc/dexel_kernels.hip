@@ -533,11 +533,6 @@ __device__ void emit_lane(const OpParams& P, int64_t c, const LV& U, int n, int 
     }
 }
 
-__device__ __forceinline__ void push_overflow(const OpParams& P, int stage, int64_t c) {
-    const int k = atomicAdd(&P.hdr->novf[stage], 1);
-    P.ovf[(int64_t)stage * P.ncols + k] = (int32_t)c;
-}
-
 // Carve `len` intervals from the arena; nullptr (and a workspace error) if
 // it does not fit.  The counter advances either way, so after a failed call
 // it holds the arena size every replayed column together would need.
@@ -553,8 +548,44 @@ __device__ float2* arena_alloc(const OpParams& P, int64_t len) {
 }
 
 // ---------------------------------------------------------------------------
-// kernels
+// passes over many shapes: shape lookup and per-shape views
 // ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void push_overflow(const Pass& Q, int stage, int64_t g) {
+    const int k = atomicAdd(&Q.hdr->novf[stage], 1);
+    Q.ovf[(int64_t)stage * Q.gcols + k] = (int32_t)g;
+}
+
+// Shape holding global column g (the last s with sbase[s] <= g).
+__device__ __forceinline__ int find_shape(const Pass& Q, int64_t g) {
+    int l = 0, h = Q.nshapes;
+    while (h - l > 1) {
+        const int m = (l + h) >> 1;
+        if (Q.sbase[m] <= g) l = m; else h = m;
+    }
+    return l;
+}
+
+__device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
+    OpParams p;
+    p.nx = S.nx;
+    p.ny = S.ny;
+    p.ncols = S.ncols;
+    p.col_ptr = S.col_ptr;
+    p.z = S.zoff ? S.z + *S.zoff : S.z;
+    p.erode = S.erode;
+    p.R = S.R;
+    p.d2max = S.d2max;
+    p.H = S.H;
+    p.hdr = Q.hdr;
+    p.cap = Q.cap;
+    p.offA = S.offA; p.cntA = S.cntA; p.A = Q.A;
+    p.offI = S.offI; p.cntI = S.cntI; p.I = Q.I;
+    p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B; p.tagB = Q.tagB; p.hullB = S.hullB;
+    p.offC = S.offC; p.cntC = S.cntC; p.C = Q.C;
+    p.arena = Q.arena;
+    return p;
+}
 
 __device__ __forceinline__ int64_t map_block(int64_t nblocks) {
     // Blocks are dispatched round-robin over the 8 XCDs; give every XCD a
@@ -568,34 +599,59 @@ __device__ __forceinline__ int64_t map_block(int64_t nblocks) {
     return start + k;
 }
 
+// Wave-uniform placement of a fast-path block: its first global column, the
+// shape, and this lane's shape-local column.
+struct Place {
+    int64_t g0;
+    int s;
+    int64_t c;
+    bool valid;
+};
+
+__device__ __forceinline__ Place place_block(const Pass& Q) {
+    Place pl;
+    pl.g0 = map_block(Q.gcols / WG) * WG;
+    pl.s = find_shape(Q, pl.g0);
+    pl.c = pl.g0 - Q.sbase[pl.s] + threadIdx.x;
+    pl.valid = pl.c < Q.shapes[pl.s].ncols;
+    return pl;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_row_offset(OpParams P) {
+__global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     __shared__ float2 lds[CAP * WG];
-    if (P.hdr->abort) return;
-    const int64_t nb = (P.ncols + WG - 1) / WG;
-    const int64_t c = map_block(nb) * WG + threadIdx.x;
-    bool valid = c < P.ncols;
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
+    bool valid = pl.valid;
     LV U{&lds[threadIdx.x], WG, CAP};
-    int n = valid ? k1_column(P, c, U) : 0;
+    int n = valid ? k1_column(P, pl.c, U) : 0;
     if (n < 0) {
-        push_overflow(P, ST_K1, c);
+        push_overflow(Q, ST_K1, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
     }
-    emit_wave(P, c, valid, U, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+    emit_wave(P, pl.c, valid, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
 }
 
-__global__ void __launch_bounds__(WG) k_row_offset_fb(OpParams P) {
+__global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     __shared__ float2 lds[CAP_FB * WG];
-    if (P.hdr->abort) return;
-    const int cnt = P.hdr->novf[ST_K1];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K1];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t c = P.ovf[(int64_t)ST_K1 * P.ncols + i];
+        const int64_t g = Q.ovf[(int64_t)ST_K1 * Q.gcols + i];
+        const int s = find_shape(Q, g);
+        const OpParams P = make_op(Q, Q.shapes[s]);
+        const int64_t c = g - Q.sbase[s];
         {
             LV L{&lds[threadIdx.x], WG, CAP_FB};
             const int n = k1_column(P, c, L);
             if (n >= 0) {
-                emit_lane(P, c, L, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+                emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
                 continue;
             }
         }
@@ -604,43 +660,46 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(OpParams P) {
         if (!buf) continue;  // keep counting the arena demand
         LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k1_column(P, c, U);
-        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, U, n, 0, &P.hdr->bumpA, P.offA, P.cntA, P.A);
+        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
     }
 }
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_neighbour(OpParams P) {
+__global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     __shared__ float2 lds[2 * CAP * WG];
-    if (P.hdr->abort) return;
-    const int64_t nb = (P.ncols + WG - 1) / WG;
-    const int64_t c = map_block(nb) * WG + threadIdx.x;
-    bool valid = c < P.ncols;
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
+    bool valid = pl.valid;
     LV L0{&lds[threadIdx.x], WG, CAP};
     LV L1{&lds[CAP * WG + threadIdx.x], WG, CAP};
     int res = 0;
-    int n = valid ? k1b_column(P, c, L0, L1, &res) : 0;
+    int n = valid ? k1b_column(P, pl.c, L0, L1, &res) : 0;
     if (n < 0) {
-        push_overflow(P, ST_K1B, c);
+        push_overflow(Q, ST_K1B, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
     }
-    emit_wave(P, c, valid, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+    emit_wave(P, pl.c, valid, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
 }
 
-__global__ void __launch_bounds__(WG) k_neighbour_fb(OpParams P) {
+__global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
     __shared__ float2 lds[CAP_FB * WG];
-    if (P.hdr->abort) return;
-    const int cnt = P.hdr->novf[ST_K1B];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K1B];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t c = P.ovf[(int64_t)ST_K1B * P.ncols + i];
+        const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + i];
+        const int s = find_shape(Q, g);
+        const OpParams P = make_op(Q, Q.shapes[s]);
+        const int64_t c = g - Q.sbase[s];
         {
             LV L0{&lds[threadIdx.x], WG, CAP_FB / 2};
             LV L1{&lds[(CAP_FB / 2) * WG + threadIdx.x], WG, CAP_FB / 2};
             int res = 0;
             const int n = k1b_column(P, c, L0, L1, &res);
             if (n >= 0) {
-                emit_lane(P, c, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+                emit_lane(P, c, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
                 continue;
             }
         }
@@ -651,30 +710,33 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(OpParams P) {
         LV L0{buf, 1, cap}, L1{buf + bound, 1, cap};
         int res = 0;
         const int n = k1b_column(P, c, L0, L1, &res);
-        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, res ? L1 : L0, n, 0, &P.hdr->bumpI, P.offI, P.cntI, P.I);
+        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
     }
 }
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_seeds_count(OpParams P) {
+__global__ void __launch_bounds__(WG) k_seeds_count(Pass Q) {
     __shared__ float2 lds[CAP * WG];
-    if (P.hdr->abort) return;
-    const int64_t nb = (P.ncols + WG - 1) / WG;
-    const int64_t c = map_block(nb) * WG + threadIdx.x;
-    if (c >= P.ncols) return;
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    if (!pl.valid) {
+        Q.cntB_g[pl.g0 + threadIdx.x] = 0;  // padding column
+        return;
+    }
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
     LV U{&lds[threadIdx.x], WG, CAP};
-    P.cntB[c] = k2_column<false>(P, c, U, nullptr, nullptr, nullptr);
+    P.cntB[pl.c] = k2_column<false>(P, pl.c, U, nullptr, nullptr, nullptr);
 }
 
 // Checks the scanned seed count against the buffer; all lanes of all blocks
 // read the same total.
-__device__ __forceinline__ bool seeds_fit(const OpParams& P) {
-    const int64_t tot = P.offB[P.ncols];
-    if (tot > P.cap) {
+__device__ __forceinline__ bool seeds_fit(const Pass& Q) {
+    const int64_t tot = Q.offB_g[Q.gcols];
+    if (tot > Q.cap) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            note_need(P.hdr, (unsigned long long)tot);
-            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+            note_need(Q.hdr, (unsigned long long)tot);
+            set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
         }
         return false;
     }
@@ -682,48 +744,52 @@ __device__ __forceinline__ bool seeds_fit(const OpParams& P) {
 }
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_seeds_fill(OpParams P) {
+__global__ void __launch_bounds__(WG) k_seeds_fill(Pass Q) {
     __shared__ float2 lds[CAP * WG];
-    if (P.hdr->abort || !seeds_fit(P)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.hdr->nseeds = P.offB[P.ncols];
-    const int64_t nb = (P.ncols + WG - 1) / WG;
-    const int64_t c = map_block(nb) * WG + threadIdx.x;
-    if (c >= P.ncols) return;
+    if (Q.hdr->abort || !seeds_fit(Q)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) Q.hdr->nseeds = Q.offB_g[Q.gcols];
+    const Place pl = place_block(Q);
+    if (!pl.valid) return;
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
     LV U{&lds[threadIdx.x], WG, CAP};
-    const int64_t o = P.offB[c];
+    const int64_t o = P.offB[pl.c];
     float2 hull = make_float2(DX_INF, -DX_INF);
-    k2_column<true>(P, c, U, P.B + o, P.tagB + o, &hull);
-    P.hullB[c] = hull;
+    k2_column<true>(P, pl.c, U, P.B + o, P.tagB + o, &hull);
+    P.hullB[pl.c] = hull;
 }
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_union(OpParams P) {
+__global__ void __launch_bounds__(WG) k_union(Pass Q) {
     __shared__ float2 lds[CAP * WG];
-    if (P.hdr->abort) return;
-    const int64_t nb = (P.ncols + WG - 1) / WG;
-    const int64_t c = map_block(nb) * WG + threadIdx.x;
-    bool valid = c < P.ncols;
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
+    if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
+    bool valid = pl.valid;
     LV U{&lds[threadIdx.x], WG, CAP};
-    int n = valid ? k3_column(P, c, U) : 0;
+    int n = valid ? k3_column(P, pl.c, U) : 0;
     if (n < 0) {
-        push_overflow(P, ST_K3, c);
+        push_overflow(Q, ST_K3, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
     }
-    emit_wave(P, c, valid, U, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+    emit_wave(P, pl.c, valid, U, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
 }
 
-__global__ void __launch_bounds__(WG) k_union_fb(OpParams P) {
+__global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
     __shared__ float2 lds[CAP_FB * WG];
-    if (P.hdr->abort) return;
-    const int cnt = P.hdr->novf[ST_K3];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K3];
     for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t c = P.ovf[(int64_t)ST_K3 * P.ncols + i];
+        const int64_t g = Q.ovf[(int64_t)ST_K3 * Q.gcols + i];
+        const int s = find_shape(Q, g);
+        const OpParams P = make_op(Q, Q.shapes[s]);
+        const int64_t c = g - Q.sbase[s];
         {
             LV L{&lds[threadIdx.x], WG, CAP_FB};
             const int n = k3_column(P, c, L);
             if (n >= 0) {
-                emit_lane(P, c, L, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+                emit_lane(P, c, L, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
                 continue;
             }
         }
@@ -732,8 +798,8 @@ __global__ void __launch_bounds__(WG) k_union_fb(OpParams P) {
         if (!buf) continue;  // keep counting the arena demand
         LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k3_column(P, c, U);
-        if (n < 0) { set_error(P.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, U, n, P.erode, &P.hdr->bumpC, P.offC, P.cntC, P.C);
+        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
+        emit_lane(P, c, U, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
     }
 }
 
@@ -761,8 +827,10 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
     return incl - v;
 }
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* cnt, int64_t n, int64_t* bsum) {
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* cnt, int64_t n, int64_t* bsum,
+                                                        const WsHeader* hdr) {
     __shared__ int64_t sh[SCAN_T];
+    if (hdr->abort) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_B;
     int64_t s = 0;
     for (int k = 0; k < SCAN_V; ++k) {
@@ -774,8 +842,9 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(const int32_t* cnt, int6
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(SCAN_T) k_scan_bsum(int64_t* bsum, int64_t nb) {
+__global__ void __launch_bounds__(SCAN_T) k_scan_bsum(int64_t* bsum, int64_t nb, const WsHeader* hdr) {
     __shared__ int64_t sh[SCAN_T];
+    if (hdr->abort) return;
     int64_t carry = 0;
     for (int64_t base = 0; base < nb; base += SCAN_T) {
         const int64_t i = base + threadIdx.x;
@@ -789,8 +858,10 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_bsum(int64_t* bsum, int64_t nb)
 }
 
 __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t* cnt, int64_t n,
-                                                       const int64_t* bsum, int64_t nb, int64_t* off) {
+                                                       const int64_t* bsum, int64_t nb, int64_t* off,
+                                                       const WsHeader* hdr) {
     __shared__ int64_t sh[SCAN_T];
+    if (hdr->abort) return;
     const int64_t base = (int64_t)blockIdx.x * SCAN_B;
     int32_t v[SCAN_V];
     int64_t s = 0;
@@ -810,14 +881,14 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int32_t* cnt, int64
 }
 
 static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int64_t* off,
-                              hipStream_t s) {
+                              const WsHeader* hdr, hipStream_t s) {
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, cnt, n, bsum);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_T), 0, s, cnt, n, bsum, hdr);
     }
-    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(SCAN_T), 0, s, bsum, nb);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(SCAN_T), 0, s, bsum, nb, hdr);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_T), 0, s, cnt, n,
-                       bsum, nb, off);
+                       bsum, nb, off, hdr);
     return hipGetLastError();
 }
 
@@ -825,110 +896,148 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
 // compaction into the output CSR, status
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_copy_out(OpParams P) {
-    if (P.hdr->abort) return;
-    const int64_t tot = P.out_col_ptr[P.ncols];
-    if (tot > P.out_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            if (P.out_is_intermediate) {
-                note_need(P.hdr, (unsigned long long)tot);
-                set_error(P.hdr, DEXEL_ERR_WORKSPACE);
-            } else {
-                atomicCAS(&P.hdr->status, 0, DEXEL_ERR_CAPACITY);
-            }
+// One wave per 64 global columns (waves never straddle shapes).  Writes the
+// shape's output column pointers always and its intervals when they fit.
+__global__ void __launch_bounds__(WG) k_copy_out(Pass Q) {
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    const Shape& S = Q.shapes[pl.s];
+    const int64_t base = S.scanC[0];
+    const int64_t total = S.scanC[S.ncols] - base;
+    const int64_t zb = S.out_zoff ? *S.out_zoff : 0;
+    const bool fits = zb + total <= S.out_cap;
+    if (!fits && pl.c == 0) {
+        if (S.out_is_intermediate) {
+            note_need(Q.hdr, (unsigned long long)(zb + total));
+            set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+        } else {
+            atomicCAS(&Q.shape_status[S.index], 0, DEXEL_ERR_CAPACITY);
         }
-        return;
     }
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= P.ncols) return;
-    const int64_t o = P.out_col_ptr[c];
-    const int n = P.cntC[c];
-    const float2* src = P.C + P.offC[c];
-    for (int i = 0; i < n; ++i) P.out_z[o + i] = src[i];
+    if (!pl.valid) return;
+    const int64_t o = S.scanC[pl.c] - base;
+    S.out_col_ptr[pl.c] = o;
+    if (pl.c == S.ncols - 1) S.out_col_ptr[S.ncols] = total;
+    if (!fits) return;
+    const int n = S.cntC[pl.c];
+    const float2* src = Q.C + S.offC[pl.c];
+    float2* dst = S.out_z + zb + o;
+    for (int i = 0; i < n; ++i) dst[i] = src[i];
 }
 
-__global__ void k_init_call(WsHeader* h) {
+__global__ void k_init_call(WsHeader* h, int32_t* shape_status, int nitems) {
     if (threadIdx.x == 0) {
         h->status = 0;
         h->abort = 0;
         h->need_cap = 0;
         h->nseg_out = -1;
+        h->nseeds = 0;
+        h->bumpA = h->bumpI = h->bumpC = h->arena = 0;
     }
     if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
-    if (threadIdx.x == 0) { h->bumpA = h->bumpI = h->bumpC = h->arena = 0; }
+    for (int i = threadIdx.x; i < nitems; i += blockDim.x) shape_status[i] = 0;
 }
 
-__global__ void k_init_op(WsHeader* h) {
+__global__ void k_init_pass(WsHeader* h) {
     if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
     if (threadIdx.x == 0) { h->bumpA = h->bumpI = h->bumpC = h->arena = 0; }
 }
 
-// Input sanity that prevents out-of-range reads: col_ptr[0] = 0,
-// nondecreasing, col_ptr[ncols] = nseg (when known).  Always run.
-__global__ void __launch_bounds__(256) k_check_colptr(OpParams P) {
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c > P.ncols) return;
-    const int64_t v = P.col_ptr[c];
+__global__ void k_put_shapes(Shape* dst, ShapeChunk ch) {
+    const int i = threadIdx.x;
+    if (i < ch.n) dst[ch.first + i] = ch.s[i];
+}
+
+__global__ void k_put_i64(int64_t* dst, I64Chunk ch) {
+    for (int i = threadIdx.x; i < ch.n; i += blockDim.x) dst[ch.first + i] = ch.v[i];
+}
+
+// Input checks of the first pass.  Always: col_ptr[0] = 0, nondecreasing,
+// col_ptr[ncols] = nseg (reads past the arrays are impossible afterwards).
+// With `validate`: every interval finite, z_in <= z_out, strictly separated.
+__global__ void __launch_bounds__(WG) k_check_input(Pass Q, int validate) {
+    const Place pl = place_block(Q);
+    if (!pl.valid) return;
+    const Shape& S = Q.shapes[pl.s];
+    const int64_t c = pl.c;
+    const int64_t v = S.col_ptr[c], w = S.col_ptr[c + 1];
     bool bad = false;
     if (c == 0 && v != 0) bad = true;
-    if (c < P.ncols && P.col_ptr[c + 1] < v) bad = true;
-    if (c == P.ncols && P.nseg >= 0 && v != P.nseg) bad = true;
-    if (v < 0 || (P.nseg >= 0 && v > P.nseg)) bad = true;
-    if (bad) set_error(P.hdr, DEXEL_ERR_NOT_CANONICAL);
-}
-
-// Full canonical-form check of the intervals (DEXEL_FLAG_VALIDATE).
-__global__ void __launch_bounds__(256) k_validate(OpParams P) {
-    if (P.hdr->abort) return;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= P.ncols) return;
-    const int64_t b = P.col_ptr[c], e = P.col_ptr[c + 1];
-    float prev = -DX_INF;
-    bool first = true, bad = false;
-    for (int64_t i = b; i < e; ++i) {
-        const float2 v = P.z[i];
-        if (!(v.x == v.x) || !(v.y == v.y) || isinf(v.x) || isinf(v.y) || v.x > v.y) bad = true;
-        if (!first && !(v.x > prev)) bad = true;
-        prev = v.y;
-        first = false;
+    if (w < v || v < 0) bad = true;
+    if (S.nseg >= 0 && w > S.nseg) bad = true;
+    if (c == S.ncols - 1 && S.nseg >= 0 && w != S.nseg) bad = true;
+    if (!bad && validate) {
+        float prev = -DX_INF;
+        for (int64_t i = v; i < w; ++i) {
+            const float2 iv = S.z[i];
+            if (!(iv.x == iv.x) || !(iv.y == iv.y) || isinf(iv.x) || isinf(iv.y) || iv.x > iv.y)
+                bad = true;
+            if (i > v && !(iv.x > prev)) bad = true;
+            prev = iv.y;
+        }
     }
-    if (bad) set_error(P.hdr, DEXEL_ERR_NOT_CANONICAL);
+    if (bad) set_error(Q.hdr, DEXEL_ERR_NOT_CANONICAL);
 }
 
-__global__ void k_finish(WsHeader* h, const int64_t* out_col_ptr, int64_t ncols, int64_t* nseg_out,
-                         int32_t* status) {
-    if (threadIdx.x != 0) return;
-    const int st = h->status;
+// Per shape: after its last pass write the caller's status and count; after
+// an intermediate pass record where its result starts in the chain buffer.
+__global__ void k_finish(Pass Q, int64_t* zbase) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= Q.nshapes) return;
+    const Shape& S = Q.shapes[s];
+    const int hst = Q.hdr->status;
+    const int st = hst ? hst : Q.shape_status[S.index];
     int64_t n = -1;
-    if (st == 0 || st == DEXEL_ERR_CAPACITY) n = out_col_ptr[ncols];
-    h->nseg_out = n;
-    if (nseg_out) *nseg_out = n;
-    if (status) *status = st;
+    if (st == 0 || st == DEXEL_ERR_CAPACITY) n = S.scanC[S.ncols] - S.scanC[0];
+    if (S.out_is_intermediate) {
+        if (!hst) zbase[S.index] = S.scanC[0];
+        return;
+    }
+    if (s == 0) Q.hdr->nseg_out = n;
+    if (S.last_pass) {
+        if (S.out_nseg) *S.out_nseg = n;
+        if (S.out_status) *S.out_status = st;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_init_call(WsHeader* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(64), 0, s, hdr);
+hipError_t launch_put_shapes(Shape* dst, const Shape* host, int n, hipStream_t s) {
+    for (int first = 0; first < n; first += DESC_CHUNK) {
+        ShapeChunk ch;
+        ch.n = n - first < DESC_CHUNK ? n - first : DESC_CHUNK;
+        ch.first = first;
+        for (int i = 0; i < ch.n; ++i) ch.s[i] = host[first + i];
+        hipLaunchKernelGGL(k_put_shapes, dim3(1), dim3(64), 0, s, dst, ch);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_init_op(WsHeader* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_op, dim3(1), dim3(64), 0, s, hdr);
+hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t s) {
+    for (int first = 0; first < n; first += I64_CHUNK) {
+        I64Chunk ch;
+        ch.n = n - first < I64_CHUNK ? n - first : I64_CHUNK;
+        ch.first = first;
+        for (int i = 0; i < ch.n; ++i) ch.v[i] = host[first + i];
+        hipLaunchKernelGGL(k_put_i64, dim3(1), dim3(256), 0, s, dst, ch);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_check_colptr(const OpParams& p, hipStream_t s) {
-    const int64_t nb = (p.ncols + 1 + 255) / 256;
-    hipLaunchKernelGGL(k_check_colptr, dim3((unsigned)nb), dim3(256), 0, s, p);
+hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, hdr, shape_status, nitems);
     return hipGetLastError();
 }
 
-hipError_t launch_validate(const OpParams& p, hipStream_t s) {
-    const int64_t nb = (p.ncols + 255) / 256;
-    hipLaunchKernelGGL(k_validate, dim3((unsigned)nb), dim3(256), 0, s, p);
+hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_pass, dim3(1), dim3(64), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_input, dim3((unsigned)(p.gcols / WG)), dim3(WG), 0, s, p, validate);
     return hipGetLastError();
 }
 
@@ -937,8 +1046,8 @@ constexpr int CAP_K1B = 32;
 constexpr int CAP_K2 = 48;
 constexpr int CAP_K3 = 32;
 
-hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev) {
-    const unsigned nb = (unsigned)((p.ncols + WG - 1) / WG);
+hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev) {
+    const unsigned nb = (unsigned)(p.gcols / WG);
     const dim3 g(nb), b(WG), gf(FALLBACK_BLOCKS);
     hipError_t e = hipSuccess;
 #define DX_MARK(i) \
@@ -955,7 +1064,7 @@ hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev) 
     hipLaunchKernelGGL(k_seeds_count<CAP_K2>, g, b, 0, s, p);
     DX_MARK(5);
     DX_MARK(6);
-    e = scan_counts(p.cntB, p.ncols, p.bsum, p.offB, s);
+    e = scan_counts(p.cntB_g, p.gcols, p.bsum, p.offB_g, p.hdr, s);
     if (e != hipSuccess) return e;
     DX_MARK(7);
     hipLaunchKernelGGL(k_seeds_fill<CAP_K2>, g, b, 0, s, p);
@@ -965,19 +1074,18 @@ hipError_t launch_offset_pass(const OpParams& p, hipStream_t s, hipEvent_t* ev) 
     DX_MARK(10);
     hipLaunchKernelGGL(k_union_fb, gf, b, 0, s, p);
     DX_MARK(11);
-    e = scan_counts(p.cntC, p.ncols, p.bsum, p.out_col_ptr, s);
+    e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
     DX_MARK(12);
-    hipLaunchKernelGGL(k_copy_out, dim3((unsigned)((p.ncols + 255) / 256)), dim3(256), 0, s, p);
+    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
     DX_MARK(13);
 #undef DX_MARK
     return hipGetLastError();
 }
 
-hipError_t launch_finish(WsHeader* hdr, const int64_t* out_col_ptr, int64_t ncols,
-                         int64_t* nseg_out, int32_t* status, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, hdr, out_col_ptr, ncols, nseg_out,
-                       status);
+hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s) {
+    const unsigned nb = (unsigned)((p.nshapes + 63) / 64);
+    hipLaunchKernelGGL(k_finish, dim3(nb), dim3(64), 0, s, p, zbase);
     return hipGetLastError();
 }
 
