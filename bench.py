@@ -41,6 +41,8 @@ WORKLOADS = {
                ops=[(op, r) for r in (2.0, 8.0, 32.0) for op in ("dilate", "erode")]),
     "c1": dict(desc="dilation r=3 of a 64x64 union of 8 spheres (R in U[4,12])",
                ops=[("dilate", 3.0)]),
+    "c4": dict(desc="batched dilation of 64 primitive soups (sides log-uniform 128..1024, "
+                    "20..300 spheres/boxes, per-shape radius U[2,32])", ops=[]),
 }
 
 
@@ -110,6 +112,128 @@ def cpu_baseline(grid, ops, budget_s=20.0):
                       f"{dt:.2f} s"}
 
 
+def pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q))
+
+
+def run_batch(args, dx, torch):
+    """c4: one batched enqueue (autotuned kernel variant, replayed from a
+    captured HIP graph) against 64 plain per-shape calls on the same stream."""
+    from synth import gen
+    t0 = time.perf_counter()
+    shapes = gen.batch_shapes(0)
+    grids = [g for g, _ in shapes]
+    radii = [r for _, r in shapes]
+    ops = ["dilate"] * len(grids)
+    n_in = sum(g.nseg for g in grids)
+    print(f"[bench] c4: {len(grids)} shapes, {n_in} intervals, "
+          f"{sum(g.nx * g.ny for g in grids)} columns ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    eng = dx.Engine(0)
+    dgs = [dx.DeviceGrid.from_host(g) for g in grids]
+
+    # plain: one call per shape, completion time of each shape from the step start
+    plans = [dx.Plan(eng, dg, r, op) for dg, r, op in zip(dgs, radii, ops)]
+    for _ in range(args.warmup):
+        for p in plans:
+            p.enqueue()
+    torch.cuda.synchronize()
+    plain_ms, lat_plain = [], []
+    for _ in range(args.steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in plans]
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        ev0.record()
+        for p, e in zip(plans, evs):
+            p.enqueue()
+            e.record()
+        torch.cuda.synchronize()
+        plain_ms.append((time.perf_counter() - t_a) * 1000.0)
+        lat_plain.extend(ev0.elapsed_time(e) for e in evs)
+
+    # batched: autotune the kernel variant, capture the enqueue in a graph
+    bp = dx.BatchPlan(eng, dgs, radii, ops)
+    chosen, var_ms = bp.autotune(reps=2)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    cap_stream = torch.cuda.Stream()
+    cap_stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap_stream):
+        bp.enqueue()  # warm on the capture stream
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=cap_stream):
+        bp.enqueue(stream=cap_stream)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    batch_ms = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        batch_ms.append((time.perf_counter() - t_a) * 1000.0)
+    if any(st != 0 for st in bp.statuses()):
+        raise RuntimeError(f"batch statuses {bp.statuses()}")
+
+    # kernel breakdown of one eager batched enqueue (profiled, outside the graph)
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
+    bp.enqueue()
+    torch.cuda.synchronize()
+    dx.dexel_profile_enable(eng.ctx, False)
+    prof_ms, passes = dx.dexel_profile_read(eng.ctx, reset=True)
+    per = {s: prof_ms[i] for i, s in enumerate(dx.PROFILE_STAGES)}
+    dom = max(per, key=per.get)
+
+    ms_step = float(np.median(batch_ms))
+    value = n_in / (ms_step / 1000.0)
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": value,
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c4: {WORKLOADS['c4']['desc']}", "shapes": len(grids),
+                   "nseg_in": n_in, "ops": "dilate"},
+        "batched": {"ms_per_step": ms_step, "latency_ms_p50": ms_step, "latency_ms_p99": ms_step,
+                    "variant": chosen, "variant_ms": [round(v, 3) for v in var_ms],
+                    "graph": True},
+        "plain": {"ms_per_step": float(np.median(plain_ms)),
+                  "segments_per_s": n_in / (float(np.median(plain_ms)) / 1000.0),
+                  "latency_ms_p50": pct(lat_plain, 50), "latency_ms_p99": pct(lat_plain, 99)},
+        "speedup_vs_plain": float(np.median(plain_ms)) / ms_step,
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per.items()},
+        "dominant_kernel": dx.PROFILE_KERNELS[dx.PROFILE_STAGES.index(dom)],
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t_c = time.perf_counter()
+        done_seg, done = 0, 0
+        for g0, r0 in zip(grids, radii):
+            oracle.offset_columns(g0, r0, "dilate", "f64")
+            done_seg += g0.nseg
+            done += 1
+            if time.perf_counter() - t_c > args.cpu_budget:
+                break
+        dt = time.perf_counter() - t_c
+        line["cpu_baseline"] = {"value": done_seg / dt, "unit": "input segments/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"full dilation of the first {done} batch shapes in "
+                                          f"order ({done_seg} intervals), {dt:.2f} s"}
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +251,8 @@ def main():
     import torch
     import paper_1804_08968_amd as dx
 
+    if args.workload == "c4":
+        return run_batch(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)
@@ -147,7 +273,8 @@ def main():
             pass_stats.append((cur.nseg, st))
             cur = plan.result()
     plans = [dx.Plan(eng, dg, r, op) for op, r in wl["ops"]]
-    print(f"[bench] plans ready ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    variants = [p.autotune(reps=2)[0] for p in plans]
+    print(f"[bench] plans ready, variants {variants} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         for p in plans:
@@ -207,6 +334,7 @@ def main():
                    "nseg_out": [p.nseg_out for p in plans]},
         "roofline": roofline,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "variants": variants,
         "pass_sizes": [dict(st, nseg_in=n) for n, st in pass_stats],
     }
     if not args.no_cpu_baseline:

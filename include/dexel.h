@@ -148,6 +148,25 @@ dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_b
 dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
                                 size_t ws_bytes, void* stream, uint32_t flags);
 
+/* Kernel variants.  The per-column kernels keep per-lane interval lists in
+ * LDS; a variant fixes their capacities (larger lists replay fewer columns
+ * from global memory, smaller ones fit more resident waves per CU).  All
+ * variants compute the same result.  dexel_set_variant forces a variant
+ * (0..DEXEL_NVARIANT-1) for every later call of the context, -1 restores
+ * automatic choice: the variant dexel_autotune picked for a batch with the
+ * same signature (item count, grid sizes, ops, radii, order of magnitude of
+ * each input size), else variant 0.
+ *
+ * dexel_autotune runs the batch once per variant untimed and `reps` times
+ * timed (HIP events on `stream`, synchronising), records the fastest for this
+ * batch signature and returns it in *chosen; ms[DEXEL_NVARIANT] (optional)
+ * receives the mean milliseconds per run of each variant.  Outputs and
+ * workspace are used as by dexel_batch_offset; device errors are returned. */
+#define DEXEL_NVARIANT 4
+dexel_status dexel_set_variant(dexel_ctx* ctx, int variant);
+dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
+                            size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen, float* ms);
+
 /* Profiling.  When enabled, every pass of every later call records HIP
  * events on its stream around each of its DEXEL_NPROF launch groups: row
  * offset, its global-memory replay, neighbour intersection, its replay, seed

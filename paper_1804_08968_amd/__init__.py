@@ -17,7 +17,8 @@ from .binding import (  # noqa: F401
     dexel_ctx_create, dexel_ctx_destroy, dexel_dilate, dexel_erode, dexel_grid_out,
     dexel_grid_view, dexel_last_error, dexel_offset, dexel_profile_enable, dexel_profile_read,
     dexel_status_string, dexel_workspace_need, dexel_workspace_size, dexel_workspace_stats,
-    make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES,
+    make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES, NVARIANT, dexel_autotune,
+    dexel_set_variant,
 )
 
 
@@ -146,6 +147,17 @@ class Plan:
         if st != DEXEL_OK:
             raise DexelError(st, dexel_last_error(self.engine.ctx))
 
+    def autotune(self, reps: int = 2, stream=None):
+        """Pick the fastest kernel variant for this call (cached in the
+        context for calls with the same signature)."""
+        it = dexel_batch_item()
+        it.in_ = self.view
+        it.r = self.r
+        it.op = self.code
+        it.out = self.out
+        ws = self.engine.workspace(self.ws_bytes)
+        return dexel_autotune(self.engine.ctx, [it], ws, stream, reps)
+
     def status(self) -> int:
         return int(self.status_t.item())
 
@@ -198,6 +210,46 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
             continue
         raise DexelError(st, dexel_last_error(engine.ctx))
     raise DexelError(DEXEL_ERR_WORKSPACE, "retries exhausted")
+
+
+class BatchPlan:
+    """A pre-sized batch for repeated asynchronous enqueues (and graph
+    capture): construction runs the batch once synchronously to size the
+    outputs and the workspace."""
+
+    def __init__(self, engine: "Engine", grids, radii, ops):
+        self.engine = engine
+        self.grids = list(grids)
+        self.radii = [float(r) for r in radii]
+        self.ops = list(ops)
+        res = batch_offset(engine, self.grids, self.radii, self.ops)
+        dev = engine.device
+        self.nseg_out = [g.nseg for g in res]
+        self.nseg_in = [g.nseg for g in self.grids]
+        self.outs = [(torch.empty(g.nx * g.ny + 1, dtype=torch.int64, device=dev),
+                      torch.empty(2 * max(n, 1), dtype=torch.float32, device=dev),
+                      torch.zeros(1, dtype=torch.int64, device=dev),
+                      torch.zeros(1, dtype=torch.int32, device=dev))
+                     for g, n in zip(self.grids, self.nseg_out)]
+        self.items = _items(self.grids, self.radii, self.ops, self.outs)
+        self.ws_bytes = dexel_batch_workspace_size(engine.ctx, self.items, engine._hint)
+        engine.workspace(self.ws_bytes)
+
+    def enqueue(self, stream=None, flags: int = 0) -> None:
+        ws = self.engine.workspace(self.ws_bytes)
+        st = dexel_batch_offset(self.engine.ctx, self.items, ws, stream, flags)
+        if st != DEXEL_OK:
+            raise DexelError(st, dexel_last_error(self.engine.ctx))
+
+    def autotune(self, reps: int = 2, stream=None):
+        ws = self.engine.workspace(self.ws_bytes)
+        return dexel_autotune(self.engine.ctx, self.items, ws, stream, reps)
+
+    def statuses(self):
+        return [int(o[3].item()) for o in self.outs]
+
+    def results(self):
+        return [DeviceGrid(g.nx, g.ny, o[0], o[1]) for g, o in zip(self.grids, self.outs)]
 
 
 _default_engine = None

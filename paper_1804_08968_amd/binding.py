@@ -79,6 +79,11 @@ lib.dexel_profile_read.argtypes = [c_void_p, _P(ctypes.c_double), _P(c_int64), c
 lib.dexel_profile_read.restype = c_int
 lib.dexel_workspace_stats.argtypes = [c_void_p, c_void_p, _P(c_int64)]
 lib.dexel_workspace_stats.restype = c_int
+lib.dexel_set_variant.argtypes = [c_void_p, c_int]
+lib.dexel_set_variant.restype = c_int
+lib.dexel_autotune.argtypes = [c_void_p, c_int32, _P(dexel_batch_item), c_void_p, c_size_t, c_void_p,
+                               c_int32, _P(c_int32), _P(ctypes.c_float)]
+lib.dexel_autotune.restype = c_int
 lib.dexel_status_string.argtypes = [c_int]
 lib.dexel_status_string.restype = ctypes.c_char_p
 lib.dexel_last_error.argtypes = [c_void_p]
@@ -87,8 +92,9 @@ lib.dexel_last_error.restype = ctypes.c_char_p
 EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_workspace_need", "dexel_dilate", "dexel_erode", "dexel_offset",
             "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_profile_enable",
-            "dexel_profile_read", "dexel_workspace_stats", "dexel_status_string",
-            "dexel_last_error"]
+            "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
+            "dexel_autotune", "dexel_status_string", "dexel_last_error"]
+NVARIANT = 4
 NPROF = 13
 PROFILE_STAGES = ["row_offset", "row_offset_replay", "neighbour", "neighbour_replay",
                   "seeds_count", "unused5", "seeds_scan", "seeds_fill",
@@ -216,3 +222,21 @@ def dexel_workspace_stats(ctx, ws: torch.Tensor) -> dict:
         raise DexelError(st, dexel_last_error(ctx))
     keys = ["row_offset", "neighbour", "seeds", "result", "arena", "replayed", "need", "nseg_out"]
     return dict(zip(keys, list(v)))
+
+
+def dexel_set_variant(ctx, variant: int) -> None:
+    st = lib.dexel_set_variant(ctx, int(variant))
+    if st != DEXEL_OK:
+        raise DexelError(st)
+
+
+def dexel_autotune(ctx, items, ws: torch.Tensor, stream=None, reps: int = 2):
+    """Returns (chosen variant, ms per variant)."""
+    arr = (dexel_batch_item * len(items))(*items)
+    chosen = c_int32()
+    ms = (ctypes.c_float * NVARIANT)()
+    st = lib.dexel_autotune(ctx, len(items), arr, _ptr(ws), int(ws.numel()), _stream_ptr(stream),
+                            int(reps), ctypes.byref(chosen), ms)
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    return int(chosen.value), list(ms)

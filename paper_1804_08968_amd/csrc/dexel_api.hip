@@ -28,6 +28,9 @@ struct dexel_ctx {
     std::vector<std::vector<hipEvent_t>> pending;
     double acc[dexel::NPROF] = {0};
     int64_t passes = 0;
+    // Kernel variant: forced (>= 0) or chosen per batch signature by dexel_autotune.
+    int forced_variant = -1;
+    std::map<uint64_t, int> tuned;
 };
 
 namespace {
@@ -230,10 +233,37 @@ int64_t cap_for_bytes(const std::vector<ItemInfo>& info, size_t ws_bytes) {
     return lo;
 }
 
+// Signature of a batch for the autotune cache: item count, grid sizes,
+// ops, radii and the order of magnitude of each input size.
+uint64_t batch_signature(int32_t n, const dexel_batch_item* items) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix((uint64_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        mix((uint64_t)items[i].in.nx);
+        mix((uint64_t)items[i].in.ny);
+        mix((uint64_t)items[i].op);
+        mix((uint64_t)float_bits(items[i].r));
+        int lg = 0;
+        for (int64_t v = items[i].in.nseg; v > 0; v >>= 1) ++lg;
+        mix((uint64_t)lg);
+    }
+    return h;
+}
+
+int pick_variant(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items) {
+    if (ctx->forced_variant >= 0) return ctx->forced_variant;
+    auto it = ctx->tuned.find(batch_signature(n, items));
+    return it == ctx->tuned.end() ? 0 : it->second;
+}
+
 // Enqueue a batch (already argument-checked) into a workspace of ws_bytes.
 dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,
                            const std::vector<ItemInfo>& info, void* ws, size_t ws_bytes,
-                           hipStream_t s, uint32_t flags) {
+                           hipStream_t s, uint32_t flags, int variant) {
     if (n == 0) return DEXEL_OK;
     if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
     if (((uintptr_t)ws) % kAlign != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
@@ -377,7 +407,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             ctx->pending.push_back(group);
             ev = ctx->pending.back().data();
         }
-        HIP_TRY(dexel::launch_pass(q, s, ev));
+        HIP_TRY(dexel::launch_pass(q, s, ev, variant));
         HIP_TRY(dexel::launch_finish(q, zbase, s));
         return DEXEL_OK;
     };
@@ -493,9 +523,64 @@ dexel_status dexel_batch_offset(dexel_ctx* ctx, int32_t n, const dexel_batch_ite
     dexel_status st = check_items(ctx, n, items, &info, true);
     if (st != DEXEL_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    st = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, flags);
+    st = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, flags, pick_variant(ctx, n, items));
     if (st != DEXEL_OK) return st;
     if (flags & DEXEL_FLAG_SYNC) return sync_status(ctx, s, n, items);
+    return DEXEL_OK;
+}
+
+dexel_status dexel_set_variant(dexel_ctx* ctx, int variant) {
+    if (!ctx || variant < -1 || variant >= dexel::NVARIANT) return DEXEL_ERR_INVALID;
+    ctx->forced_variant = variant;
+    return DEXEL_OK;
+}
+
+dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items, void* ws,
+                            size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen,
+                            float* ms) {
+    if (!ctx || reps < 1) return DEXEL_ERR_INVALID;
+    ctx->err.clear();
+    std::vector<ItemInfo> info;
+    dexel_status st = check_items(ctx, n, items, &info, true);
+    if (st != DEXEL_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const bool prof = ctx->profile;
+    ctx->profile = false;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 0.f;
+    dexel_status result = DEXEL_OK;
+    for (int v = 0; v < dexel::NVARIANT && result == DEXEL_OK; ++v) {
+        // one untimed run (also checks the workspace and outputs fit)
+        result = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, 0, v);
+        if (result != DEXEL_OK) break;
+        result = sync_status(ctx, s, n, items);
+        if (result != DEXEL_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { result = DEXEL_ERR_HIP; break; }
+        for (int k = 0; k < reps && result == DEXEL_OK; ++k)
+            result = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, 0, v);
+        if (result != DEXEL_OK) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            result = DEXEL_ERR_HIP;
+            break;
+        }
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        t /= (float)reps;
+        if (ms) ms[v] = t;
+        if (v == 0 || t < best_ms) {
+            best = v;
+            best_ms = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->profile = prof;
+    if (result != DEXEL_OK) return result;
+    ctx->tuned[batch_signature(n, items)] = best;
+    if (chosen) *chosen = best;
     return DEXEL_OK;
 }
 

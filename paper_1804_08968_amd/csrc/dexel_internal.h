@@ -128,7 +128,9 @@ hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
 // compaction copy.
 constexpr int NPROF = 13;
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
-hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev);
+// variant: kernel variant (per-lane LDS list capacities), 0..NVARIANT-1.
+constexpr int NVARIANT = 4;
+hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant);
 hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s);
 
 }  // namespace dexel

@@ -1041,36 +1041,36 @@ hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s) {
     return hipGetLastError();
 }
 
-constexpr int CAP_K1 = 40;
-constexpr int CAP_K1B = 32;
-constexpr int CAP_K2 = 48;
-constexpr int CAP_K3 = 32;
-
-hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev) {
+// Kernel variants: per-lane LDS list capacities of K1, K1b (each of two
+// lists), K2 and K3.  Larger lists replay fewer columns from global memory;
+// smaller ones leave room for more resident waves per CU.  The host picks
+// one per call (default, forced, or autotuned).
+template <int C1, int C1B, int C2, int C3>
+static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     const unsigned nb = (unsigned)(p.gcols / WG);
     const dim3 g(nb), b(WG), gf(FALLBACK_BLOCKS);
     hipError_t e = hipSuccess;
 #define DX_MARK(i) \
     if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) return e
     DX_MARK(0);
-    hipLaunchKernelGGL(k_row_offset<CAP_K1>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
     DX_MARK(1);
     hipLaunchKernelGGL(k_row_offset_fb, gf, b, 0, s, p);
     DX_MARK(2);
-    hipLaunchKernelGGL(k_neighbour<CAP_K1B>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
     DX_MARK(3);
     hipLaunchKernelGGL(k_neighbour_fb, gf, b, 0, s, p);
     DX_MARK(4);
-    hipLaunchKernelGGL(k_seeds_count<CAP_K2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_count<C2>, g, b, 0, s, p);
     DX_MARK(5);
     DX_MARK(6);
     e = scan_counts(p.cntB_g, p.gcols, p.bsum, p.offB_g, p.hdr, s);
     if (e != hipSuccess) return e;
     DX_MARK(7);
-    hipLaunchKernelGGL(k_seeds_fill<CAP_K2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_fill<C2>, g, b, 0, s, p);
     DX_MARK(8);
     DX_MARK(9);
-    hipLaunchKernelGGL(k_union<CAP_K3>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(10);
     hipLaunchKernelGGL(k_union_fb, gf, b, 0, s, p);
     DX_MARK(11);
@@ -1081,6 +1081,15 @@ hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(13);
 #undef DX_MARK
     return hipGetLastError();
+}
+
+hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant) {
+    switch (variant) {
+        case 1: return pass_variant<24, 16, 32, 24>(p, s, ev);
+        case 2: return pass_variant<64, 32, 64, 48>(p, s, ev);
+        case 3: return pass_variant<32, 16, 40, 16>(p, s, ev);
+        default: return pass_variant<40, 32, 48, 32>(p, s, ev);
+    }
 }
 
 hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s) {
