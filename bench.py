@@ -43,6 +43,11 @@ WORKLOADS = {
                ops=[("dilate", 3.0)]),
     "c4": dict(desc="batched dilation of 64 primitive soups (sides log-uniform 128..1024, "
                     "20..300 spheres/boxes, per-shape radius U[2,32])", ops=[]),
+    "c5": dict(desc="served stream of dilate/erode/open/close requests (r U[1,24], 30% chained "
+                    "on the session's previous result) over 16 seeded shapes, sides log-uniform "
+                    "256..2048, half primitive soups, half gyroids; Poisson arrivals at 0.5, 0.9 "
+                    "and 1.2 x the plain server's saturation rate on the same request mix",
+               ops=[]),
 }
 
 
@@ -234,6 +239,83 @@ def run_batch(args, dx, torch):
     eng.close()
 
 
+def run_serving(args, dx, torch):
+    """c5: continuous batching against a plain one-request-at-a-time server."""
+    from paper_1804_08968_amd import serve
+    from synth import gen
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    hosts = []
+    for i in range(16):
+        side = int(round(np.exp(rng.uniform(np.log(256), np.log(2048)))))
+        sub = int(rng.integers(0, 2**31 - 1))
+        if i % 2 == 0:
+            hosts.append(gen.primitives_grid(sub, n=side, count=int(rng.integers(20, 301)),
+                                             smin=4.0 * side / 512, smax=64.0 * side / 512,
+                                             height=float(side)))
+        else:
+            hosts.append(gen.gyroid_grid(sub, n=side))
+    print(f"[bench] c5 pool: sides {[h.nx for h in hosts]}, "
+          f"{sum(h.nseg for h in hosts)} intervals ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    eng = dx.Engine(0)
+    pool = [dx.DeviceGrid.from_host(h) for h in hosts]
+    ops = ["dilate", "erode", "open", "close"]
+
+    def make(n, rate, seed):
+        r1 = np.random.default_rng(seed)
+        r2 = np.random.default_rng(seed + 7)
+        t, out = 0.0, []
+        for i in range(n):
+            t += 0.0 if rate is None else r2.exponential(1.0 / rate)
+            out.append(serve.Request(i, t, int(r1.integers(0, len(pool))),
+                                     ops[int(r1.integers(0, 4))], float(r1.uniform(1.0, 24.0)),
+                                     bool(r1.random() < 0.3), int(r1.integers(0, 16))))
+        return out
+
+    # warm the library (LUTs, kernel code) and measure the plain service rate
+    serve.Server(eng, pool, mode="plain").run(make(4, None, 99))
+    sat_reqs = make(args.serve_requests, None, 2)  # the same mix as the loaded runs
+    sat = serve.summarize(serve.Server(eng, pool, mode="plain").run(sat_reqs))
+    print(f"[bench] saturation run {sat}", file=sys.stderr, flush=True)
+    if not sat["completed"] or not sat["makespan_s"]:
+        raise RuntimeError(f"saturation run completed nothing: {sat}")
+    mu = sat["completed"] / sat["makespan_s"]
+    print(f"[bench] plain saturation rate {mu:.2f} req/s", file=sys.stderr, flush=True)
+    table = []
+    for f in (0.5, 0.9, 1.2):
+        reqs = make(args.serve_requests, f * mu, 2)
+        row = {"load": f, "rate_req_s": f * mu}
+        for mode in ("continuous", "plain"):
+            srv = serve.Server(eng, pool, mode=mode, max_batch=16, slots=2)
+            row[mode] = serve.summarize(srv.run(reqs))
+            print(f"[bench] load {f}: {mode} {row[mode]}", file=sys.stderr, flush=True)
+        table.append(row)
+    top = table[-1]["continuous"]
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": top["segments_per_s"],
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.serve_requests,
+        "warmup": 4,
+        "ms_per_step": top["makespan_s"] * 1000.0 / max(1, top["completed"]),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c5: {WORKLOADS['c5']['desc']}",
+                   "requests_per_load": args.serve_requests, "max_batch": 16, "slots": 2,
+                   "budget_bytes": 64 << 30},
+        "serving": {"saturation_req_s_plain": mu, "loads": table},
+        "latency_ms_p50": top["latency_ms_p50"],
+        "latency_ms_p99": top["latency_ms_p99"],
+    }
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +324,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the offset of one "
@@ -253,6 +336,8 @@ def main():
 
     if args.workload == "c4":
         return run_batch(args, dx, torch)
+    if args.workload == "c5":
+        return run_serving(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)

@@ -54,14 +54,19 @@ class Done:
 
 class Server:
     def __init__(self, engine: Engine, pool, budget_bytes: int = 64 << 30, max_batch: int = 16,
-                 slots: int = 2, mode: str = "continuous"):
+                 slots: int = 2, mode: str = "continuous", work_cap_cols: int = 4 << 20):
         self.engine = engine
         self.pool = list(pool)
         self.budget = int(budget_bytes)
         self.mode = mode
         self.max_batch = 1 if mode == "plain" else int(max_batch)
         self.slots = 1 if mode == "plain" else int(slots)
+        # A batch holds at most this many columns (one request always fits):
+        # a request that fills the GPU on its own gains nothing from company,
+        # and small requests should not wait for a large one to finish.
+        self.work_cap = int(work_cap_cols)
         self.streams = [torch.cuda.Stream(device=engine.device) for _ in range(self.slots)]
+        self.ws = [None] * self.slots   # per-slot workspace, grown on demand
         self.rejected = 0
 
     # -- footprint -----------------------------------------------------------
@@ -88,7 +93,8 @@ class Server:
         it.in_ = view
         it.r = float(r)
         it.op = OPS[op]
-        ws = dexel_batch_workspace_size(self.engine.ctx, [it], self.engine._hint)
+        # this request's own default capacity, not the engine-wide retry hint
+        ws = dexel_batch_workspace_size(self.engine.ctx, [it], 0)
         out = 8 * (grid.nx * grid.ny + 1) + 8 * self._out_cap(grid)
         return ws + out
 
@@ -146,6 +152,7 @@ class Server:
             launched = False
             if free_slots and waiting:
                 members, mem_b, keep = [], 0, []
+                cols_b = 0
                 held = set()           # sessions with an earlier request still waiting
                 for req in waiting:
                     if (len(members) >= self.max_batch or req.session in session_busy
@@ -163,12 +170,14 @@ class Server:
                         results[req.id] = Done(req.id, req.arrival, now, now, grid_in.nseg_cached,
                                                -4, -1, None)
                         continue
-                    if used + mem_b + fp > self.budget:
-                        keep.append(req)   # waits until memory frees up
+                    if used + mem_b + fp > self.budget or (
+                            members and cols_b + grid_in.nx * grid_in.ny > self.work_cap):
+                        keep.append(req)   # waits until memory or batch room frees up
                         held.add(req.session)
                         continue
                     members.append((req, grid_in))
                     mem_b += fp
+                    cols_b += grid_in.nx * grid_in.ny
                     session_busy.add(req.session)
                 waiting = keep
                 if members:
@@ -179,9 +188,14 @@ class Server:
                         it, out = self._item(grid_in, req.r, req.op, self._out_cap(grid_in))
                         items.append(it)
                         outs.append(out)
-                    nbytes = dexel_batch_workspace_size(eng.ctx, items, eng._hint)
-                    with torch.cuda.stream(stream):
-                        ws = torch.empty(nbytes, dtype=torch.uint8, device=eng.device)
+                    nbytes = dexel_batch_workspace_size(eng.ctx, items, 0)
+                    ws = self.ws[slot]
+                    if ws is None or ws.numel() < nbytes:
+                        self.ws[slot] = None
+                        with torch.cuda.stream(stream):
+                            ws = torch.empty(int(nbytes * 1.25), dtype=torch.uint8,
+                                             device=eng.device)
+                        self.ws[slot] = ws
                     # the outputs were allocated and zeroed on the current stream
                     stream.wait_stream(torch.cuda.current_stream(eng.device))
                     st = dexel_batch_offset(eng.ctx, items, ws, stream, 0)
