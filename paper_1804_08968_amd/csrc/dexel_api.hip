@@ -202,6 +202,8 @@ dexel_status check_items(dexel_ctx* ctx, int32_t n, const dexel_batch_item* item
         } else {
             if (it.in.nx <= 0 || it.in.ny <= 0 || it.in.nseg < 0)
                 return fail(ctx, DEXEL_ERR_INVALID, "bad grid size");
+            if ((int64_t)it.in.nx * it.in.ny >= ((int64_t)1 << 31) - 64)
+                return fail(ctx, DEXEL_ERR_UNSUPPORTED, "nx * ny must be below 2^31");
         }
         if ((st = check_radius(ctx, it.r)) != DEXEL_OK) return st;
         if (it.op < DEXEL_DILATE || it.op > DEXEL_CLOSE) return fail(ctx, DEXEL_ERR_INVALID, "unknown op");

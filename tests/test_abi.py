@@ -1,0 +1,148 @@
+"""The C ABI without a GPU: libdexel.so loads, exports every function that
+include/dexel.h declares, agrees with the binding on constants, rejects null
+arguments on the host, and the package refuses to import without it."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dexel.h")
+LIB = os.path.join(ROOT, "paper_1804_08968_amd", "libdexel.so")
+
+
+def _header():
+    with open(HEADER) as f:
+        return f.read()
+
+
+def declared_functions():
+    text = re.sub(r"//[^\n]*", "", _header())
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dexel_[a-z_]+)\s*\(", text)))
+
+
+def header_constants():
+    text = _header()
+    out = {}
+    for name, val in re.findall(r"\b(DEXEL_[A-Z_0-9]+)\s*=\s*(-?\d+)", text):
+        out[name] = int(val)
+    for name, val in re.findall(r"#define\s+(DEXEL_[A-Z_0-9]+)\s+(-?\d+)", text):
+        out[name] = int(val)
+    return out
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} is not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("dexel_dilate", "dexel_erode", "dexel_offset", "dexel_batch_offset",
+                     "dexel_workspace_size", "dexel_ctx_create", "dexel_ctx_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, f"declared in dexel.h but not exported: {missing}"
+
+
+def test_binding_lists_exactly_the_header():
+    from paper_1804_08968_amd import binding
+    assert sorted(binding.EXPORTED) == declared_functions()
+
+
+def test_constants_match_binding():
+    from paper_1804_08968_amd import binding
+    c = header_constants()
+    for name in ("DEXEL_OK", "DEXEL_ERR_INVALID", "DEXEL_ERR_NOT_CANONICAL", "DEXEL_ERR_CAPACITY",
+                 "DEXEL_ERR_WORKSPACE", "DEXEL_ERR_HIP", "DEXEL_ERR_UNSUPPORTED", "DEXEL_DILATE",
+                 "DEXEL_ERODE", "DEXEL_OPEN", "DEXEL_CLOSE", "DEXEL_FLAG_SYNC",
+                 "DEXEL_FLAG_VALIDATE"):
+        assert name in c, name
+        assert getattr(binding, name) == c[name], name
+    assert c["DEXEL_NVARIANT"] == binding.NVARIANT
+    assert c["DEXEL_NPROF"] == binding.NPROF == len(binding.PROFILE_STAGES)
+
+
+def test_struct_layouts():
+    from paper_1804_08968_amd import binding
+    assert ctypes.sizeof(binding.dexel_grid_view) == 32
+    assert ctypes.sizeof(binding.dexel_grid_out) == 48
+    assert binding.dexel_batch_item.out.offset == 40
+    assert ctypes.sizeof(binding.dexel_batch_item) == 88
+
+
+def test_status_strings(lib):
+    lib.dexel_status_string.restype = ctypes.c_char_p
+    lib.dexel_status_string.argtypes = [ctypes.c_int]
+    seen = set()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        s = lib.dexel_status_string(code).decode()
+        assert s and s not in seen
+        seen.add(s)
+    assert lib.dexel_status_string(-99).decode()
+
+
+def test_null_arguments_rejected_on_host(lib):
+    """Calls with a null context or null out-pointers return INVALID without
+    touching a device (this process has none)."""
+    from paper_1804_08968_amd import binding as b
+    inv = b.DEXEL_ERR_INVALID
+    assert lib.dexel_ctx_create(0, None) == inv
+    view = b.dexel_grid_view(4, 4, 0, None, None)
+    nbytes = ctypes.c_size_t()
+    assert b.lib.dexel_workspace_size(None, ctypes.byref(view), 1.0, 0, 0, ctypes.byref(nbytes)) == inv
+    assert b.lib.dexel_batch_workspace_size(None, 0, None, 0, ctypes.byref(nbytes)) == inv
+    assert b.lib.dexel_batch_offset(None, 0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_offset(None, ctypes.byref(view), 1.0, 0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_dilate(None, ctypes.byref(view), 1.0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_erode(None, ctypes.byref(view), 1.0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_workspace_need(None, None, None) == inv
+    assert b.lib.dexel_workspace_stats(None, None, None) == inv
+    assert b.lib.dexel_set_variant(None, 0) == inv
+    assert b.lib.dexel_profile_enable(None, 1) == inv
+    assert b.lib.dexel_autotune(None, 0, None, None, 0, None, 1, None, None) == inv
+    b.lib.dexel_ctx_destroy(None)          # no-op
+
+
+def test_no_gpu_context_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert lib.dexel_ctx_create(0, ctypes.byref(h)) == -5   # DEXEL_ERR_HIP
+    assert not h.value
+
+
+def test_package_import_fails_without_library(tmp_path):
+    """The product path has no CPU fallback: without libdexel.so, importing
+    the package raises."""
+    pkg = os.path.join(ROOT, "paper_1804_08968_amd")
+    dst = tmp_path / "paper_1804_08968_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "csrc", "__pycache__"))
+    code = "import paper_1804_08968_amd"
+    env = dict(os.environ, PYTHONPATH=str(tmp_path))
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libdexel.so is not built" in r.stderr
+
+
+def test_package_does_not_reference_oracle():
+    pkg = os.path.join(ROOT, "paper_1804_08968_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                with open(os.path.join(dirpath, f)) as fh:
+                    text = fh.read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "oracle.c" not in text and "liboracle" not in text, f
