@@ -73,9 +73,8 @@ def kernel_bytes(stage, ncols, n_in, st):
     return {
         "row_offset": inp + lst_v0,
         "neighbour": lst_v0 + lst_i,
-        "seeds_count": inp + lst_i + 4 * ncols,
-        "seeds_fill": inp + lst_i + 8 * (ncols + 1) + 9 * seeds,
-        "y_union": lst_v0 + 8 * (ncols + 1) + 9 * seeds + 12 * ncols + 8 * res,
+        "seeds": inp + lst_i + 20 * ncols + 9 * seeds,
+        "y_union": lst_v0 + 20 * ncols + 9 * seeds + 12 * ncols + 8 * res,
         "compact": 4 * ncols + 8 * (ncols + 1) + 12 * ncols + 16 * res,
     }.get(stage)
 
@@ -325,6 +324,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a plain copy "
+                         "kernel of known size, the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the offset of one "
@@ -333,6 +335,16 @@ def main():
 
     import torch
     import paper_1804_08968_amd as dx
+
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nb} bytes", file=sys.stderr, flush=True)
+        del src, dst
 
     if args.workload == "c4":
         return run_batch(args, dx, torch)

@@ -169,8 +169,8 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
 
 /* Profiling.  When enabled, every pass of every later call records HIP
  * events on its stream around each of its DEXEL_NPROF launch groups: row
- * offset, its global-memory replay, neighbour intersection, its replay, seed
- * count, (unused), seed-count scan, seed fill, (unused), y dilation with
+ * offset, its global-memory replay, neighbour intersection, its replay,
+ * extrusion seeds, their replay, three unused groups, y dilation with
  * per-column union, its replay, result scan, compaction copy.
  * dexel_profile_read waits for the recorded events and returns the
  * accumulated milliseconds per group and the number of passes (a dilation or

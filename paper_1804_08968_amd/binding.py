@@ -97,11 +97,11 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
 NVARIANT = 4
 NPROF = 13
 PROFILE_STAGES = ["row_offset", "row_offset_replay", "neighbour", "neighbour_replay",
-                  "seeds_count", "unused5", "seeds_scan", "seeds_fill",
+                  "seeds", "seeds_replay", "unused6", "unused7",
                   "unused8", "y_union", "y_union_replay", "result_scan", "compact"]
 # main HIP kernel of each profiled group (as rocprofv3 names it)
 PROFILE_KERNELS = ["k_row_offset", "k_row_offset_fb", "k_neighbour", "k_neighbour_fb",
-                   "k_seeds_count", "-", "k_scan", "k_seeds_fill",
+                   "k_seeds", "k_seeds_fb", "-", "-",
                    "-", "k_union", "k_union_fb", "k_scan", "k_copy_out"]
 
 

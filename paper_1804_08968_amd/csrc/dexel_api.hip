@@ -62,7 +62,7 @@ void radius_params(float r, int* R, int* d2max) {
 struct Layout {
     size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
     size_t offA, cntA, offI, cntI, offB, cntB, hullB, offC, cntC, scanC;
-    size_t A, I, B, tagB, C, ovf, arena, bsum, mid_ptr, mid_z, total;
+    size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table
 };
@@ -110,19 +110,20 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.cntA = take(4 * g);
     L.offI = take(8 * g);
     L.cntI = take(4 * g);
-    L.offB = take(8 * (g + 1));
+    L.offB = take(8 * g);
     L.cntB = take(4 * g);
-    L.hullB = take(8 * g);
+    L.hullB = take(16 * g);
     L.offC = take(8 * g);
     L.cntC = take(4 * g);
     L.scanC = take(8 * (g + 1));
     L.A = take(8 * cp);
     L.I = take(8 * cp);
-    L.B = take(8 * cp);
-    L.tagB = take(cp);
+    L.B = take(8 * g * dexel::SEED_SLOT);
+    L.tagB = take(g * dexel::SEED_SLOT);
     L.C = take(8 * cp);
     L.ovf = take(4 * g * dexel::NSTAGE);
     L.arena = take(8 * cp);
+    L.arena_tag = take(cp);
     L.bsum = take(8 * ((g + 1023) / 1024 + 2));
     L.mid_ptr = take(8 * (size_t)L.mid_cols);
     L.mid_z = take(L.gcols2 ? 8 * cp : 0);
@@ -301,7 +302,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.cntI = (int32_t*)(w + L.cntI) + gbase;
             S.offB = (int64_t*)(w + L.offB) + gbase;
             S.cntB = (int32_t*)(w + L.cntB) + gbase;
-            S.hullB = (float2*)(w + L.hullB) + gbase;
+            S.hullB = (float4*)(w + L.hullB) + gbase;
             S.offC = (int64_t*)(w + L.offC) + gbase;
             S.cntC = (int32_t*)(w + L.cntC) + gbase;
             S.scanC = (int64_t*)(w + L.scanC) + gbase;
@@ -365,12 +366,11 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         q.B = (float2*)(w + L.B);
         q.tagB = (uint8_t*)(w + L.tagB);
         q.C = (float2*)(w + L.C);
-        q.cntB_g = (int32_t*)(w + L.cntB);
-        q.offB_g = (int64_t*)(w + L.offB);
         q.cntC_g = (int32_t*)(w + L.cntC);
         q.scanC_g = (int64_t*)(w + L.scanC);
         q.ovf = (int32_t*)(w + L.ovf);
         q.arena = (float2*)(w + L.arena);
+        q.arena_tag = (uint8_t*)(w + L.arena_tag);
         q.bsum = (int64_t*)(w + L.bsum);
         return q;
     };
@@ -624,7 +624,7 @@ dexel_status dexel_workspace_stats(dexel_ctx* ctx, const void* ws, int64_t* stat
     for (int i = 0; i < dexel::NSTAGE; ++i) novf += h.novf[i];
     stats[0] = (int64_t)h.bumpA;
     stats[1] = (int64_t)h.bumpI;
-    stats[2] = h.nseeds;
+    stats[2] = (int64_t)h.nseeds;
     stats[3] = (int64_t)h.bumpC;
     stats[4] = (int64_t)h.arena;
     stats[5] = novf;

@@ -19,12 +19,17 @@ struct WsHeader {
     unsigned long long arena;       // bump allocator of the overflow arena
     int64_t nseg_out;
     int32_t novf[8];                // columns whose per-lane list overflowed LDS, per stage
-    int64_t nseeds;                 // kept extrusion seeds of the last pass
+    unsigned long long nseeds;      // kept extrusion seeds of the current pass
     int64_t reserved[2];
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
-enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K3 = 2, NSTAGE = 3 };
+enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3, NSTAGE = 4 };
+
+// Seed slots per column: the seeds of a column are written at
+// B[g * SEED_SLOT ...] (g = global column); a column with more seeds is
+// recomputed into the workspace arena and its offset stored as -(pos + 1).
+constexpr int SEED_SLOT = 32;
 
 // One shape of one pass, in device memory.  Per-column arrays are already
 // offset to the shape's first global column, so kernels index them with the
@@ -44,7 +49,9 @@ struct Shape {
     const float* H;           // H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..d2max
     int64_t* offA; int32_t* cntA;
     int64_t* offI; int32_t* cntI;
-    int64_t* offB; int32_t* cntB; float2* hullB;
+    // seed position (see SEED_SLOT), count, hull (x, y: of the seed chords at
+    // |dy| = 1; z, w: of the seed pieces themselves)
+    int64_t* offB; int32_t* cntB; float4* hullB;
     int64_t* offC; int32_t* cntC;
     int64_t* scanC;           // global exclusive scan of the result counts
     // output
@@ -70,15 +77,14 @@ struct Pass {
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
     float2* A;
     float2* I;
-    float2* B;
+    float2* B;                // [gcols * SEED_SLOT] seed slots, tags in tagB
     uint8_t* tagB;
     float2* C;
-    int32_t* cntB_g;          // global views of the per-column arrays (for the scans)
-    int64_t* offB_g;
-    int32_t* cntC_g;
+    int32_t* cntC_g;          // global views of the per-column result arrays (for the scan)
     int64_t* scanC_g;
     int32_t* ovf;             // [NSTAGE * gcols] overflow column lists (global ids)
     float2* arena;
+    uint8_t* arena_tag;       // [cap] tags of seeds placed in the arena
     int64_t* bsum;
 };
 
@@ -97,9 +103,10 @@ struct OpParams {
     int64_t cap;
     int64_t* offA; int32_t* cntA; float2* A;
     int64_t* offI; int32_t* cntI; float2* I;
-    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float2* hullB;
+    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float4* hullB;
     int64_t* offC; int32_t* cntC; float2* C;
     float2* arena;
+    uint8_t* arena_tag;
 };
 
 // Descriptor upload through kernel arguments (no host buffer outlives the call).
@@ -123,9 +130,8 @@ hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hi
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
 // Profiled intervals of one pass, one per launch group: row offset, its
-// replay, neighbour intersection, its replay, seed count, (unused), seed
-// scan, seed fill, (unused), y dilation + union, its replay, result scan,
-// compaction copy.
+// replay, neighbour intersection, its replay, seeds, their replay, three
+// unused groups, y dilation + union, its replay, result scan, compaction.
 constexpr int NPROF = 13;
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
 // variant: kernel variant (per-lane LDS list capacities), 0..NVARIANT-1.

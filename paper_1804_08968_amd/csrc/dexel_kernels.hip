@@ -18,7 +18,9 @@
 //                    in order of |dx|; a piece is kept only if its chord at
 //                    |dy| = 1 (its largest off-row chord) is not inside I(c):
 //                    a dropped seed's power disk lies inside V0 of every row
-//                    it can reach.  Count pass, scan, fill pass (CSR).
+//                    it can reach.  One traversal writes a column's seeds to
+//                    its fixed slot; the rare longer lists are recomputed
+//                    into the workspace arena.
 //   K3  y dilation   out(c) = V0(c) U chords of the kept seeds of the rows
 //                    y+-1 .. y+-R at their power weight r^2 - t^2 - dy^2.
 //   K4  compaction   exclusive scan of the per-column counts, copy to CSR.
@@ -45,19 +47,32 @@ namespace dexel {
 #define DX_INF __builtin_inff()
 
 constexpr int WG = 64;
-constexpr int FALLBACK_BLOCKS = 256;
-constexpr int CAP_FB = 160;  // LDS list capacity of the replay kernels' first tier
+// Replay kernels: overflow entry i goes to block i % FALLBACK_BLOCKS, so the
+// (typically heavy) replayed columns are spread over many waves instead of
+// being packed 64 to a wave and run in lockstep.
+constexpr int FALLBACK_BLOCKS = 1024;
+constexpr int CAP_FB = 128;  // LDS list capacity of the replay kernels' first tier
+// K2 defers a column to its replay kernel when I(c) has more intervals than
+// this, K3 when V0(c) has; CAP_Z is the per-lane list capacity of the z-slab
+// replays.
+constexpr int K2_DEFER_NI = 8;
+constexpr int K3_DEFER_N = 8;
+constexpr int CAP_Z = 32;
 
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
 
-struct LV {  // per-lane interval list: element i at p[i * stride]
+// Per-lane interval list: element i at p[i * S].  S = WG: a lane's list in
+// LDS, interleaved by lane; S = 1: a contiguous list in global memory (replay
+// kernels).  The stride is a compile-time constant, so list indexing is a
+// shift of a 32-bit index.
+template <int S>
+struct LV {
     float2* p;
-    int stride;
     int cap;
-    __device__ __forceinline__ float2 get(int i) const { return p[(int64_t)i * stride]; }
-    __device__ __forceinline__ void set(int i, float2 v) const { p[(int64_t)i * stride] = v; }
+    __device__ __forceinline__ float2 get(int i) const { return p[i * S]; }
+    __device__ __forceinline__ void set(int i, float2 v) const { p[i * S] = v; }
 };
 
 __device__ __forceinline__ void set_error(WsHeader* h, int code) {
@@ -78,7 +93,8 @@ __device__ __forceinline__ float2 col_item(const float2* z, int64_t b, int n, in
 }
 
 // First index i in [0, n) of a canonical list with U[i].y >= v (n if none).
-__device__ __forceinline__ int lv_lower_hi(const LV& U, int n, float v) {
+template <class L>
+__device__ __forceinline__ int lv_lower_hi(const L& U, int n, float v) {
     int l = 0, h = n;
     while (l < h) {
         int m = (l + h) >> 1;
@@ -90,7 +106,8 @@ __device__ __forceinline__ int lv_lower_hi(const LV& U, int n, float v) {
 // Insert the closed interval [lo, hi] into a canonical list of size n.
 // Returns the new size, or -1 if the list would exceed its capacity (the list
 // is unchanged then).
-__device__ int lv_insert(const LV& U, int n, float lo, float hi) {
+template <class L>
+__device__ int lv_insert(const L& U, int n, float lo, float hi) {
     int i = lv_lower_hi(U, n, lo);
     if (i == n || U.get(i).x > hi) {
         if (n >= U.cap) return -1;
@@ -119,7 +136,8 @@ __device__ int lv_insert(const LV& U, int n, float lo, float hi) {
 // lv_insert for candidates arriving in non-decreasing order of start: the
 // insertion point is found by walking forward from *hint (the position the
 // previous candidate landed at) instead of a binary search.
-__device__ int lv_insert_fwd(const LV& U, int n, float lo, float hi, int* hint) {
+template <class L>
+__device__ int lv_insert_fwd(const L& U, int n, float lo, float hi, int* hint) {
     int i = *hint;
     while (i < n && U.get(i).y < lo) ++i;
     *hint = i;
@@ -138,50 +156,6 @@ __device__ int lv_insert_fwd(const LV& U, int n, float lo, float hi, int* hint) 
     if (sh > 0)
         for (int k = j + 1; k < n; ++k) U.set(k - sh, U.get(k));
     return n - sh;
-}
-
-// Insert the chords [a - h, b + h] of column items k0 .. k1-1 (starts
-// non-decreasing).  Returns the new size or -1 on overflow.
-__device__ int insert_chords(const OpParams& P, const LV& U, int n, int64_t b, int m, int k0,
-                             int k1, float h) {
-    int hint = 0;
-    int k = k0;
-    if (!P.erode) {
-        // four loads in flight per lane before the dependent list updates
-        for (; k + 4 <= k1; k += 4) {
-            const float2 c0 = P.z[b + k], c1 = P.z[b + k + 1];
-            const float2 c2 = P.z[b + k + 2], c3 = P.z[b + k + 3];
-            if ((n = lv_insert_fwd(U, n, c0.x - h, c0.y + h, &hint)) < 0) return -1;
-            if ((n = lv_insert_fwd(U, n, c1.x - h, c1.y + h, &hint)) < 0) return -1;
-            if ((n = lv_insert_fwd(U, n, c2.x - h, c2.y + h, &hint)) < 0) return -1;
-            if ((n = lv_insert_fwd(U, n, c3.x - h, c3.y + h, &hint)) < 0) return -1;
-        }
-    }
-    for (; k < k1; ++k) {
-        const float2 iv = col_item(P.z, b, m, k, P.erode);
-        n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
-        if (n < 0) return -1;
-    }
-    return n;
-}
-
-// Add the chords of one column to the union U.  Within a column the chord
-// starts and the chord ends are both non-decreasing (disjoint sorted
-// intervals, one half-width), so when U is a single interval [L, R] only a
-// leading run of chords starting below L and a trailing run ending above R
-// can change it; the chords between them lie inside [L, R].
-__device__ int add_column_chords(const OpParams& P, const LV& U, int n, int64_t b, int m, float h) {
-    const int cnt = P.erode ? m + 1 : m;
-    if (cnt == 0) return n;
-    if (n != 1) return insert_chords(P, U, n, b, m, 0, cnt, h);
-    const float2 u = U.get(0);
-    int k0 = 0;
-    while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
-    int k1 = cnt;
-    while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
-    n = insert_chords(P, U, n, b, m, 0, k0, h);
-    if (n < 0) return -1;
-    return insert_chords(P, U, n, b, m, k1, cnt, h);
 }
 
 // Is [lo, hi] inside one interval of the canonical global list L[0..n)?
@@ -221,11 +195,22 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // ---------------------------------------------------------------------------
 // per-column computations (same code for LDS and global lists)
 // ---------------------------------------------------------------------------
+//
+// Lanes of a wave run these loops in lockstep, so every loop body that
+// inserts into a list has a single call site: a lane's candidates of one
+// input column are enumerated as one index sequence, whatever the reason a
+// candidate was selected.
 
 // K1: V0 = union over |dx| <= R of the chords [a - H[dx^2], b + H[dx^2]] of
 // the row's columns x + dx, nearest columns first (largest chords first, so
-// most later chords are found inside the list and skipped).
-__device__ int k1_column(const OpParams& P, int64_t c, const LV& U) {
+// most later chords are found inside the list and skipped).  Within a column
+// the chord starts and the chord ends are both non-decreasing (disjoint
+// sorted intervals, one half-width), so while the partial union is a single
+// interval [L, E] only a leading run of chords starting below L and a
+// trailing run ending above E can change it; the candidates of a column are
+// the whole column otherwise.
+template <class L>
+__device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -237,8 +222,28 @@ __device__ int k1_column(const OpParams& P, int64_t c, const LV& U) {
             if (xx < 0 || xx >= P.nx) continue;
             int64_t b;
             const int m = col_len(P, row + xx, &b);
-            n = add_column_chords(P, U, n, b, m, h);
-            if (n < 0) return -1;
+            const int cnt = P.erode ? m + 1 : m;
+            int k0 = cnt, k1 = cnt;
+            if (n == 1) {
+                const float2 u = U.get(0);
+                k0 = 0;
+                while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
+                while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
+            }
+            // candidates: items [0, k0) then [k1, cnt); the next item is
+            // loaded before the current one is inserted
+            const int nc = k0 + (cnt - k1);
+            int hint = 0;
+            float2 nxt = nc > 0 ? col_item(P.z, b, m, k0 > 0 ? 0 : k1, P.erode) : make_float2(0.f, 0.f);
+            for (int j = 0; j < nc; ++j) {
+                const float2 iv = nxt;
+                if (j + 1 < nc) {
+                    const int k = j + 1 < k0 ? j + 1 : k1 + (j + 1 - k0);
+                    nxt = col_item(P.z, b, m, k, P.erode);
+                }
+                n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
+                if (n < 0) return -1;
+            }
         }
     }
     return n;
@@ -254,7 +259,8 @@ __device__ int64_t k1_bound(const OpParams& P, int64_t c) {
 
 // K1b: I = intersection of V0 over the in-grid rows y+-1 .. y+-R (the whole
 // line if there are none).  Two lists, result in *res (0 or 1).
-__device__ int k1b_column(const OpParams& P, int64_t c, const LV& L0, const LV& L1, int* res) {
+template <class L>
+__device__ int k1b_column(const OpParams& P, int64_t c, const L& L0, const L& L1, int* res) {
     int x, y;
     col_xy(P, c, &x, &y);
     L0.set(0, make_float2(-DX_INF, DX_INF));
@@ -266,8 +272,8 @@ __device__ int k1b_column(const OpParams& P, int64_t c, const LV& L0, const LV& 
             const int64_t cc = (int64_t)yy * P.nx + x;
             const float2* J = P.A + P.offA[cc];
             const int m = P.cntA[cc];
-            const LV& S = cur ? L1 : L0;
-            const LV& D = cur ? L0 : L1;
+            const L& S = cur ? L1 : L0;
+            const L& D = cur ? L0 : L1;
             int i = 0, j = 0, k = 0;
             while (i < n && j < m) {
                 float2 a = S.get(i), bb = J[j];
@@ -304,32 +310,36 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
 // x-t and x+t not covered by the columns nearer to x.  Only pieces whose
 // chord at |dy| = 1 pokes out of I(c) are kept.  A column whose whole chord
 // is inside I(c) is not added to the cover list, and the cover list simply
-// stops growing when its LDS capacity is reached: either way the pieces it
-// would hide are then kept whole, which adds valid seeds and changes
-// nothing in the result.  FILL == false: returns the number of kept pieces;
-// FILL == true: also writes them at dst.
+// stops growing when its capacity is reached: either way the pieces it would
+// hide are then kept whole, which adds valid seeds and changes nothing in
+// the result.  The first `dcap` kept pieces are written at dst/dtag, the
+// hull of the chords at |dy| = 1 of all kept pieces (x, y) and of the pieces
+// themselves (z, w) is accumulated in *hull, and the number of kept pieces is
+// returned.
+
 // Is [lo, hi] inside I(c)?  A one-interval I is tested from registers.
 __device__ __forceinline__ bool in_I(const float2* Ip, int ni, float2 i0, float lo, float hi) {
     if (ni == 1) return i0.x <= lo && hi <= i0.y;
     return in_list(Ip, ni, lo, hi);
 }
 
-template <bool FILL>
 __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, int* np, float2* dst,
-                                        uint8_t* dtag, float2* hull) {
-    if (FILL) {
+                                        uint8_t* dtag, int dcap, float4* hull) {
+    if (*np < dcap) {
         dst[*np] = make_float2(p, q);
         dtag[*np] = (uint8_t)t;
-        hull->x = fminf(hull->x, p - h1);
-        hull->y = fmaxf(hull->y, q + h1);
     }
+    hull->x = fminf(hull->x, p - h1);
+    hull->y = fmaxf(hull->y, q + h1);
+    hull->z = fminf(hull->z, p);
+    hull->w = fmaxf(hull->w, q);
     ++*np;
 }
 
-template <bool FILL>
-__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, float2 i0, const LV& U, int* n,
+template <class L>
+__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, float2 i0, const L& U, int* n,
                                            float a, float e, float h1, int t, int* np,
-                                           float2* dst, uint8_t* dtag, float2* hull) {
+                                           float2* dst, uint8_t* dtag, int dcap, float4* hull) {
     if (in_I(Ip, ni, i0, a - h1, e + h1)) return;
     // parts of [a, e] not covered by U (closures)
     int idx = lv_lower_hi(U, *n, a);
@@ -339,27 +349,245 @@ __device__ __forceinline__ void k2_segment(const float2* Ip, int ni, float2 i0, 
         const float2 u = U.get(idx);
         if (u.x > e) break;
         if (u.x > p) {
-            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit<FILL>(p, u.x, h1, t, np, dst, dtag, hull);
+            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit(p, u.x, h1, t, np, dst, dtag, dcap, hull);
         }
         if (u.y >= e) { done = true; break; }
         p = fmaxf(p, u.y);
         ++idx;
     }
     if (!done && (p < e || a == e)) {
-        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit<FILL>(p, e, h1, t, np, dst, dtag, hull);
+        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit(p, e, h1, t, np, dst, dtag, dcap, hull);
     }
     const int nn = lv_insert(U, *n, a, e);
     if (nn >= 0) *n = nn;
 }
 
-template <bool FILL>
-__device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst, uint8_t* dtag,
-                         float2* hull) {
+template <class L>
+__device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
+                         int dcap, float4* hull) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
     const float2* Ip = P.I + P.offI[c];
     const int ni = P.cntI[c];
+    const float2 i0 = ni == 1 ? Ip[0] : make_float2(0.f, 0.f);
+    const float ilo = ni > 0 ? (ni == 1 ? i0.x : Ip[0].x) : 0.f;
+    const float ihi = ni > 0 ? (ni == 1 ? i0.y : Ip[ni - 1].y) : 0.f;
+    int n = 0, np = 0;
+    for (int t = 0; t <= P.R; ++t) {
+        const int d2 = t * t + 1;
+        if (d2 > P.d2max) break;
+        const float h1 = P.H[d2];
+        for (int s = 0; s < (t ? 2 : 1); ++s) {
+            const int xx = s ? x + t : x - t;
+            if (xx < 0 || xx >= P.nx) continue;
+            int64_t b;
+            const int m = col_len(P, row + xx, &b);
+            const int cnt = P.erode ? m + 1 : m;
+            // Chords that can poke out of I form one run per gap of I (the
+            // two unbounded ends included), because a column's chord starts
+            // and chord ends are both non-decreasing.  Short columns, and
+            // columns tested against an empty I, are one run.
+            const bool all = ni == 0 || cnt <= 8;
+            const int nruns = all ? 1 : ni + 1;
+            int next = 0;
+            for (int g = 0; g < nruns; ++g) {
+                int kb = 0;
+                float lim = DX_INF;  // the run ends at the first chord starting at or above lim
+                if (!all) {
+                    if (g == 0) {
+                        lim = ilo;
+                    } else if (g == ni) {
+                        kb = cnt;
+                        while (kb > next && col_item(P.z, b, m, kb - 1, P.erode).y + h1 > ihi) --kb;
+                    } else {  // gap (I[g-1].y, I[g].x): first chord ending above its start
+                        const float glo = Ip[g - 1].y;
+                        lim = Ip[g].x;
+                        int l = next, hh = cnt;
+                        while (l < hh) {
+                            const int mid = (l + hh) >> 1;
+                            if (col_item(P.z, b, m, mid, P.erode).y + h1 > glo) hh = mid; else l = mid + 1;
+                        }
+                        kb = l;
+                    }
+                }
+                int k = kb;
+                for (; k < cnt; ++k) {
+                    const float2 sg = col_item(P.z, b, m, k, P.erode);
+                    if (!(sg.x - h1 < lim)) break;
+                    k2_segment(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, dcap, hull);
+                }
+                next = max(next, k);
+            }
+        }
+    }
+    return np;
+}
+
+// K3: V0(c) plus the chords of the kept seeds of rows y+-dy at weight
+// r^2 - t^2 - dy^2, nearest rows first.  TAB: the wave's lanes (all of
+// them, one shape per wave) first stage the half-widths of the current dy
+// for every tag in the LDS table `tab` (negative: outside the ball); the
+// per-lane work then looks up tab[t].  Without TAB the lookups read H.
+// A lane stops adding chords when its list overflows (result -1) but keeps
+// taking part in the staging.
+__device__ __forceinline__ void seed_span(const OpParams& P, int64_t cc, const float2** sp,
+                                          const uint8_t** tp, int* nb) {
+    const int64_t ob = P.offB[cc];
+    *nb = P.cntB[cc];
+    if (ob >= 0) {
+        *sp = P.B + ob;
+        *tp = P.tagB + ob;
+        *nb = min(*nb, SEED_SLOT);
+    } else {
+        *sp = P.arena + (-ob - 1);
+        *tp = P.arena_tag + (-ob - 1);
+    }
+}
+
+template <bool TAB, class L>
+__device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, float* tab) {
+    int x = 0, y = 0;
+    if (live) col_xy(P, c, &x, &y);
+    int n = 0;
+    bool ok = live;
+    if (ok) {
+        const int n0 = P.cntA[c];
+        if (n0 > U.cap) {
+            ok = false;
+        } else {
+            const float2* V = P.A + P.offA[c];
+            for (int i = 0; i < n0; ++i) U.set(i, V[i]);
+            n = n0;
+        }
+    }
+    // While the union is one interval, keep it in registers: most seed
+    // chords land inside it and are dropped after two compares.
+    float2 u0 = (ok && n == 1) ? U.get(0) : make_float2(0.f, 0.f);
+    for (int dy = 1; dy <= P.R; ++dy) {
+        const int dy2 = dy * dy;
+        if (TAB) {
+            __syncthreads();
+            for (int t = threadIdx.x; t <= P.R; t += WG) {
+                const int d2 = t * t + dy2;
+                tab[t] = d2 <= P.d2max ? P.H[d2] : -1.0f;
+            }
+            __syncthreads();
+        }
+        if (!ok) continue;
+        const float hd = P.H[dy2];
+        for (int s = 0; s < 2 && ok; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            // Every chord of this seed column at this dy lies inside its hull
+            // at |dy| = 1 and inside its piece hull widened by H[dy^2] (the
+            // widest half-width at this dy); skip the column when the
+            // tighter of the two bounds is inside the union.
+            const float4 h4 = P.hullB[cc];
+            if (h4.x > h4.y) continue;
+            const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
+            if (n == 1) {
+                if (u0.x <= hlo && hhi <= u0.y) continue;
+            } else {
+                const int i = lv_lower_hi(U, n, hhi);
+                if (i < n && U.get(i).x <= hlo) continue;
+            }
+            const float2* sp;
+            const uint8_t* tp;
+            int nb;
+            seed_span(P, cc, &sp, &tp, &nb);
+            for (int j = 0; j < nb; ++j) {
+                const int t = tp[j];
+                const float2 pc = sp[j];
+                float h;
+                if (TAB) {
+                    h = tab[t];
+                    if (h < 0.0f) continue;
+                } else {
+                    const int d2 = t * t + dy2;
+                    if (d2 > P.d2max) continue;
+                    h = P.H[d2];
+                }
+                const float lo = pc.x - h, hi = pc.y + h;
+                if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
+                n = lv_insert(U, n, lo, hi);
+                if (n < 0) {
+                    ok = false;
+                    break;
+                }
+                if (n == 1) u0 = U.get(0);
+            }
+        }
+    }
+    if (!live) return 0;
+    return ok ? n : -1;
+}
+
+__device__ int64_t k3_bound(const OpParams& P, int64_t c) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    int64_t b = (int64_t)P.cntA[c] + 1;
+    for (int dy = 1; dy <= P.R; ++dy)
+        for (int s = 0; s < 2; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            b += P.cntB[(int64_t)yy * P.nx + x];
+        }
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// z-slab evaluation of one heavy column by a whole wave
+// ---------------------------------------------------------------------------
+//
+// A column whose lists are long (typically at the grid's x border, where the
+// one-sided row window leaves many gaps) is evaluated by all 64 lanes of a
+// wave: lane l restricts the computation to the closed slab [b_l, b_l+1] of
+// z, with b_0 = -inf, b_64 = +inf and b_1 .. b_63 evenly spaced over the
+// finite range of the data.  Restricting to a slab commutes with the union
+// (clip every candidate to the slab), and two parts of one interval cut at
+// a slab boundary overlap there, so the slab results concatenate to the same
+// float union once intervals touching at a boundary are merged.
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Slab of this lane for data spanning [zmin, zmax] (zmin > zmax: no finite data).
+__device__ __forceinline__ float2 lane_slab(float zmin, float zmax) {
+    const int l = threadIdx.x & 63;
+    if (!(zmin <= zmax)) zmin = zmax = 0.0f;
+    const float w = zmax - zmin;
+    const float lo = l == 0 ? -DX_INF : zmin + w * ((float)l * (1.0f / 64.0f));
+    const float hi = l == 63 ? DX_INF : zmin + w * ((float)(l + 1) * (1.0f / 64.0f));
+    return make_float2(lo, hi);
+}
+
+__device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
+    if (v > -DX_INF && v < DX_INF) {
+        *zmin = fminf(*zmin, v);
+        *zmax = fmaxf(*zmax, v);
+    }
+}
+
+// K2 restricted to the slab [zs, ze]: the input items of the row window are
+// clipped to the slab before painting, so a piece cut at a slab boundary is
+// kept as two pieces whose chords overlap.
+template <class L>
+__device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, const float2* Ip, int ni,
+                       const L& U, float2* dst, uint8_t* dtag, int dcap, float4* hull) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int64_t row = (int64_t)y * P.nx;
     const float2 i0 = ni == 1 ? Ip[0] : make_float2(0.f, 0.f);
     int n = 0, np = 0;
     for (int t = 0; t <= P.R; ++t) {
@@ -372,110 +600,93 @@ __device__ int k2_column(const OpParams& P, int64_t c, const LV& U, float2* dst,
             int64_t b;
             const int m = col_len(P, row + xx, &b);
             const int cnt = P.erode ? m + 1 : m;
-            // Chords that can poke out of I: for each gap of I (the two
-            // unbounded ends included) the chords meeting it form one run,
-            // because a column's chord starts and chord ends are both
-            // non-decreasing.  Short columns are simply scanned whole.
-            if (ni == 0 || cnt <= 8) {
-                for (int k = 0; k < cnt; ++k) {
-                    const float2 sg = col_item(P.z, b, m, k, P.erode);
-                    k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
-                }
-                continue;
+            int l = 0, hh = cnt;  // first item ending at or above zs
+            while (l < hh) {
+                const int mid = (l + hh) >> 1;
+                if (col_item(P.z, b, m, mid, P.erode).y < zs) l = mid + 1; else hh = mid;
             }
-            const float ilo = ni == 1 ? i0.x : Ip[0].x;
-            const float ihi = ni == 1 ? i0.y : Ip[ni - 1].y;
-            int k = 0;
-            for (; k < cnt; ++k) {  // gap below I
+            for (int k = l; k < cnt; ++k) {
                 const float2 sg = col_item(P.z, b, m, k, P.erode);
-                if (!(sg.x - h1 < ilo)) break;
-                k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
-            }
-            int next = k;
-            for (int g = 1; g < ni; ++g) {  // interior gaps (I[g-1].y, I[g].x)
-                const float glo = Ip[g - 1].y, ghi = Ip[g].x;
-                int l = next, hh = cnt;  // first chord with end > glo
-                while (l < hh) {
-                    const int mid = (l + hh) >> 1;
-                    if (col_item(P.z, b, m, mid, P.erode).y + h1 > glo) hh = mid; else l = mid + 1;
-                }
-                for (k = l; k < cnt; ++k) {
-                    const float2 sg = col_item(P.z, b, m, k, P.erode);
-                    if (!(sg.x - h1 < ghi)) break;
-                    k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
-                }
-                next = max(next, k);
-            }
-            int k1 = cnt;  // gap above I
-            while (k1 > next && col_item(P.z, b, m, k1 - 1, P.erode).y + h1 > ihi) --k1;
-            for (k = k1; k < cnt; ++k) {
-                const float2 sg = col_item(P.z, b, m, k, P.erode);
-                k2_segment<FILL>(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, hull);
+                if (sg.x > ze) break;
+                k2_segment(Ip, ni, i0, U, &n, fmaxf(sg.x, zs), fminf(sg.y, ze), h1, t, &np, dst,
+                           dtag, dcap, hull);
             }
         }
     }
     return np;
 }
 
-// K3: V0(c) plus the chords of the kept seeds of rows y+-dy at weight
-// r^2 - t^2 - dy^2, nearest rows first.
-__device__ int k3_column(const OpParams& P, int64_t c, const LV& U) {
+// K3 restricted to the slab [zs, ze]: V0(c) and every seed chord clipped to
+// the slab.  Called by all lanes of a wave for one column: at each dy they
+// stage the half-widths of every tag in `tab` together, and a lane stops
+// adding chords once its slab holds env[dy] (the hull of every chord the rows
+// dy .. R can still add) or overflows.  Returns the list size or -1 on
+// overflow.
+template <class L>
+__device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L& U, float* tab,
+                       const float2* env) {
     int x, y;
     col_xy(P, c, &x, &y);
-    const int n0 = P.cntA[c];
-    if (n0 > U.cap) return -1;
+    int n = 0;
+    bool ok = true;
     const float2* V = P.A + P.offA[c];
-    for (int i = 0; i < n0; ++i) U.set(i, V[i]);
-    int n = n0;
-    // While the union is one interval, keep it in registers: most seed
-    // chords land inside it and are dropped after two compares.
-    float2 u0 = n == 1 ? U.get(0) : make_float2(0.f, 0.f);
+    const int n0 = P.cntA[c];
+    for (int i = 0; i < n0 && ok; ++i) {
+        const float2 v = V[i];
+        const float lo = fmaxf(v.x, zs), hi = fminf(v.y, ze);
+        if (lo > hi) continue;
+        if (n >= U.cap) ok = false; else U.set(n++, make_float2(lo, hi));
+    }
+    bool busy = ok;
     for (int dy = 1; dy <= P.R; ++dy) {
         const int dy2 = dy * dy;
-        for (int s = 0; s < 2; ++s) {
+        __syncthreads();
+        for (int t = threadIdx.x; t <= P.R; t += WG) {
+            const int d2 = t * t + dy2;
+            tab[t] = d2 <= P.d2max ? P.H[d2] : -1.0f;
+        }
+        __syncthreads();
+        if (busy) {
+            const float2 e = env[dy];
+            const float lo = fmaxf(e.x, zs), hi = fminf(e.y, ze);
+            if (lo > hi) {
+                busy = false;
+            } else {
+                const int i = lv_lower_hi(U, n, hi);
+                if (i < n && U.get(i).x <= lo) busy = false;
+            }
+        }
+        if (__all(!busy)) break;
+        if (!busy) continue;
+        const float hd = tab[0];
+        for (int s = 0; s < 2 && busy; ++s) {
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
             const int64_t cc = (int64_t)yy * P.nx + x;
-            // Every chord of this seed column at |dy| >= 1 lies inside its hull
-            // at |dy| = 1; skip the column when the hull is inside the union.
-            const float2 hb = P.hullB[cc];
-            if (hb.x > hb.y) continue;
-            if (n == 1) {
-                if (u0.x <= hb.x && hb.y <= u0.y) continue;
-            } else {
-                const int i = lv_lower_hi(U, n, hb.y);
-                if (i < n && U.get(i).x <= hb.x) continue;
-            }
-            const int64_t pb = P.offB[cc], pe = P.offB[cc + 1];
-            for (int64_t j = pb; j < pe; ++j) {
-                const int t = P.tagB[j];
-                const int d2 = t * t + dy2;
-                if (d2 > P.d2max) continue;
-                const float h = P.H[d2];
-                const float2 pc = P.B[j];
-                const float lo = pc.x - h, hi = pc.y + h;
-                if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
+            const float4 h4 = P.hullB[cc];
+            if (h4.x > h4.y) continue;
+            const float hlo = fmaxf(fmaxf(h4.x, h4.z - hd), zs);
+            const float hhi = fminf(fminf(h4.y, h4.w + hd), ze);
+            if (hlo > hhi) continue;
+            const float2* sp;
+            const uint8_t* tp;
+            int nb;
+            seed_span(P, cc, &sp, &tp, &nb);
+            for (int j = 0; j < nb; ++j) {
+                const float h = tab[tp[j]];
+                if (h < 0.0f) continue;
+                const float2 pc = sp[j];
+                const float lo = fmaxf(pc.x - h, zs), hi = fminf(pc.y + h, ze);
+                if (lo > hi) continue;
                 n = lv_insert(U, n, lo, hi);
-                if (n < 0) return -1;
-                if (n == 1) u0 = U.get(0);
+                if (n < 0) {
+                    ok = busy = false;
+                    break;
+                }
             }
         }
     }
-    return n;
-}
-
-__device__ int64_t k3_bound(const OpParams& P, int64_t c) {
-    int x, y;
-    col_xy(P, c, &x, &y);
-    int64_t b = (int64_t)P.cntA[c] + 1;
-    for (int dy = 1; dy <= P.R; ++dy)
-        for (int s = 0; s < 2; ++s) {
-            const int yy = s ? y + dy : y - dy;
-            if (yy < 0 || yy >= P.ny) continue;
-            const int64_t cc = (int64_t)yy * P.nx + x;
-            b += P.offB[cc + 1] - P.offB[cc];
-        }
-    return b;
+    return ok ? n : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -484,7 +695,8 @@ __device__ int64_t k3_bound(const OpParams& P, int64_t c) {
 
 // Write list U (or its complement's closures, dropping the unbounded ends)
 // of every valid lane.  Wave-cooperative: one atomic per wave.
-__device__ void emit_wave(const OpParams& P, int64_t c, bool valid, const LV& U, int n,
+template <class L>
+__device__ void emit_wave(const OpParams& P, int64_t c, bool valid, const L& U, int n,
                           int complement, unsigned long long* bump, int64_t* off, int32_t* cnt,
                           float2* dst) {
     const int outn = valid ? (complement ? (n > 0 ? n - 1 : 0) : n) : 0;
@@ -512,7 +724,8 @@ __device__ void emit_wave(const OpParams& P, int64_t c, bool valid, const LV& U,
 }
 
 // Single-lane variant for the fallback path.
-__device__ void emit_lane(const OpParams& P, int64_t c, const LV& U, int n, int complement,
+template <class L>
+__device__ void emit_lane(const OpParams& P, int64_t c, const L& U, int n, int complement,
                           unsigned long long* bump, int64_t* off, int32_t* cnt, float2* dst) {
     const int outn = complement ? (n > 0 ? n - 1 : 0) : n;
     const unsigned long long base = atomicAdd(bump, (unsigned long long)outn);
@@ -533,18 +746,19 @@ __device__ void emit_lane(const OpParams& P, int64_t c, const LV& U, int n, int 
     }
 }
 
-// Carve `len` intervals from the arena; nullptr (and a workspace error) if
-// it does not fit.  The counter advances either way, so after a failed call
-// it holds the arena size every replayed column together would need.
-__device__ float2* arena_alloc(const OpParams& P, int64_t len) {
+// Carve `len` intervals from the arena: their position, or -1 (and a
+// workspace error) if they do not fit.  The counter advances either way, so
+// after a failed call it holds the arena size every replayed column together
+// would need.
+__device__ int64_t arena_alloc(const OpParams& P, int64_t len) {
     const unsigned long long base = atomicAdd(&P.hdr->arena, (unsigned long long)len);
     const unsigned long long end = base + (unsigned long long)len;
     if (end > (unsigned long long)P.cap) {
         note_need(P.hdr, end);
         set_error(P.hdr, DEXEL_ERR_WORKSPACE);
-        return nullptr;
+        return -1;
     }
-    return P.arena + base;
+    return (int64_t)base;
 }
 
 // ---------------------------------------------------------------------------
@@ -584,6 +798,7 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B; p.tagB = Q.tagB; p.hullB = S.hullB;
     p.offC = S.offC; p.cntC = S.cntC; p.C = Q.C;
     p.arena = Q.arena;
+    p.arena_tag = Q.arena_tag;
     return p;
 }
 
@@ -621,6 +836,9 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
 // kernels
 // ---------------------------------------------------------------------------
 
+using LdsList = LV<WG>;
+using MemList = LV<1>;
+
 template <int CAP>
 __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     __shared__ float2 lds[CAP * WG];
@@ -628,7 +846,7 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     const Place pl = place_block(Q);
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     bool valid = pl.valid;
-    LV U{&lds[threadIdx.x], WG, CAP};
+    LdsList U{&lds[threadIdx.x], CAP};
     int n = valid ? k1_column(P, pl.c, U) : 0;
     if (n < 0) {
         push_overflow(Q, ST_K1, pl.g0 + threadIdx.x);
@@ -642,13 +860,13 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     __shared__ float2 lds[CAP_FB * WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K1];
-    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+    for (int i = threadIdx.x * gridDim.x + blockIdx.x; i < cnt; i += gridDim.x * WG) {
         const int64_t g = Q.ovf[(int64_t)ST_K1 * Q.gcols + i];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
         {
-            LV L{&lds[threadIdx.x], WG, CAP_FB};
+            LdsList L{&lds[threadIdx.x], CAP_FB};
             const int n = k1_column(P, c, L);
             if (n >= 0) {
                 emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
@@ -656,9 +874,9 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
             }
         }
         const int64_t bound = k1_bound(P, c);
-        float2* buf = arena_alloc(P, bound);
-        if (!buf) continue;  // keep counting the arena demand
-        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
+        const int64_t pos = arena_alloc(P, bound);
+        if (pos < 0) continue;  // keep counting the arena demand
+        MemList U{P.arena + pos, (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k1_column(P, c, U);
         if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
         emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
@@ -672,8 +890,8 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     const Place pl = place_block(Q);
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     bool valid = pl.valid;
-    LV L0{&lds[threadIdx.x], WG, CAP};
-    LV L1{&lds[CAP * WG + threadIdx.x], WG, CAP};
+    LdsList L0{&lds[threadIdx.x], CAP};
+    LdsList L1{&lds[CAP * WG + threadIdx.x], CAP};
     int res = 0;
     int n = valid ? k1b_column(P, pl.c, L0, L1, &res) : 0;
     if (n < 0) {
@@ -688,14 +906,14 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
     __shared__ float2 lds[CAP_FB * WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K1B];
-    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
+    for (int i = threadIdx.x * gridDim.x + blockIdx.x; i < cnt; i += gridDim.x * WG) {
         const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + i];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
         {
-            LV L0{&lds[threadIdx.x], WG, CAP_FB / 2};
-            LV L1{&lds[(CAP_FB / 2) * WG + threadIdx.x], WG, CAP_FB / 2};
+            LdsList L0{&lds[threadIdx.x], CAP_FB / 2};
+            LdsList L1{&lds[(CAP_FB / 2) * WG + threadIdx.x], CAP_FB / 2};
             int res = 0;
             const int n = k1b_column(P, c, L0, L1, &res);
             if (n >= 0) {
@@ -704,10 +922,10 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
             }
         }
         const int64_t bound = k1b_bound(P, c);
-        float2* buf = arena_alloc(P, 2 * bound);
-        if (!buf) continue;  // keep counting the arena demand
+        const int64_t pos = arena_alloc(P, 2 * bound);
+        if (pos < 0) continue;  // keep counting the arena demand
         const int cap = (int)min<int64_t>(bound, 0x7fffffff);
-        LV L0{buf, 1, cap}, L1{buf + bound, 1, cap};
+        MemList L0{P.arena + pos, cap}, L1{P.arena + pos + bound, cap};
         int res = 0;
         const int n = k1b_column(P, c, L0, L1, &res);
         if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
@@ -715,60 +933,121 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
     }
 }
 
+// One traversal per column: the seeds go to the column's slot.  A column
+// tested against a fragmented I(c) is deferred, and one with more than
+// SEED_SLOT seeds is redone, by k_seeds_fb.
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_seeds_count(Pass Q) {
+__global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
-    if (!pl.valid) {
-        Q.cntB_g[pl.g0 + threadIdx.x] = 0;  // padding column
-        return;
-    }
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
-    LV U{&lds[threadIdx.x], WG, CAP};
-    P.cntB[pl.c] = k2_column<false>(P, pl.c, U, nullptr, nullptr, nullptr);
+    int np = 0;
+    if (pl.valid) {
+        const int64_t g = pl.g0 + threadIdx.x;
+        if (P.cntI[pl.c] > K2_DEFER_NI) {
+            P.cntB[pl.c] = 0;
+            push_overflow(Q, ST_K2, g);
+        } else {
+            LdsList U{&lds[threadIdx.x], CAP};
+            float4 hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+            np = k2_column(P, pl.c, U, Q.B + g * SEED_SLOT, Q.tagB + g * SEED_SLOT, SEED_SLOT, &hull);
+            P.offB[pl.c] = g * SEED_SLOT;
+            P.cntB[pl.c] = np;
+            P.hullB[pl.c] = hull;
+            if (np > SEED_SLOT) {
+                push_overflow(Q, ST_K2, g);
+                np = 0;  // counted by the replay
+            }
+        }
+    }
+    int tot;
+    wave_excl_scan(np, &tot);
+    if ((threadIdx.x & 63) == 0 && tot > 0) atomicAdd(&Q.hdr->nseeds, (unsigned long long)tot);
 }
 
-// Checks the scanned seed count against the buffer; all lanes of all blocks
-// read the same total.
-__device__ __forceinline__ bool seeds_fit(const Pass& Q) {
-    const int64_t tot = Q.offB_g[Q.gcols];
-    if (tot > Q.cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            note_need(Q.hdr, (unsigned long long)tot);
-            set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
-        }
-        return false;
-    }
-    return true;
-}
+// Replay of K2 for the deferred and overflowing columns: one wave per column,
+// one z-slab per lane (count, wave scan, one arena allocation, fill).  I(c)
+// is staged in LDS when it fits.
+constexpr int ISH = 512;
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_seeds_fill(Pass Q) {
+__global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
     __shared__ float2 lds[CAP * WG];
-    if (Q.hdr->abort || !seeds_fit(Q)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) Q.hdr->nseeds = Q.offB_g[Q.gcols];
-    const Place pl = place_block(Q);
-    if (!pl.valid) return;
-    const OpParams P = make_op(Q, Q.shapes[pl.s]);
-    LV U{&lds[threadIdx.x], WG, CAP};
-    const int64_t o = P.offB[pl.c];
-    float2 hull = make_float2(DX_INF, -DX_INF);
-    k2_column<true>(P, pl.c, U, P.B + o, P.tagB + o, &hull);
-    P.hullB[pl.c] = hull;
+    __shared__ float2 ish[ISH];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K2];
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int64_t g = Q.ovf[(int64_t)ST_K2 * Q.gcols + e];
+        const int s = find_shape(Q, g);
+        const OpParams P = make_op(Q, Q.shapes[s]);
+        const int64_t c = g - Q.sbase[s];
+        const int ni = P.cntI[c];
+        const float2* Ig = P.I + P.offI[c];
+        const bool staged = ni <= ISH;
+        __syncthreads();  // the previous column's readers of ish are done
+        if (staged)
+            for (int i = lane; i < ni; i += WG) ish[i] = Ig[i];
+        __syncthreads();
+        const float2* Ip = staged ? (const float2*)ish : Ig;
+        // finite z range of the row window's input
+        int x, y;
+        col_xy(P, c, &x, &y);
+        float zmin = DX_INF, zmax = -DX_INF;
+        for (int j = lane; j <= 2 * P.R; j += WG) {
+            const int xx = x - P.R + j;
+            if (xx < 0 || xx >= P.nx) continue;
+            int64_t b;
+            const int m = col_len(P, (int64_t)y * P.nx + xx, &b);
+            if (m > 0) {
+                widen(&zmin, &zmax, P.z[b].x);
+                widen(&zmin, &zmax, P.z[b + m - 1].y);
+            }
+        }
+        zmin = wave_min(zmin);
+        zmax = wave_max(zmax);
+        const float2 sl = lane_slab(zmin, zmax);
+        LdsList U{&lds[lane], CAP};
+        float4 hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+        const int np = k2_slab(P, c, sl.x, sl.y, Ip, ni, U, nullptr, nullptr, 0, &hull);
+        int tot;
+        const int pre = wave_excl_scan(np, &tot);
+        int64_t pos = 0;
+        if (lane == 0) pos = arena_alloc(P, tot);
+        pos = __shfl(pos, 0, 64);
+        if (pos < 0) continue;  // keep counting the arena demand
+        hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+        const int np2 = k2_slab(P, c, sl.x, sl.y, Ip, ni, U, P.arena + pos + pre,
+                                P.arena_tag + pos + pre, np, &hull);
+        if (np2 != np) set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+        hull.x = wave_min(hull.x);
+        hull.y = wave_max(hull.y);
+        hull.z = wave_min(hull.z);
+        hull.w = wave_max(hull.w);
+        if (lane == 0) {
+            P.offB[c] = -(pos + 1);
+            P.cntB[c] = tot;
+            P.hullB[c] = hull;
+            atomicAdd(&Q.hdr->nseeds, (unsigned long long)tot);
+        }
+    }
 }
 
 template <int CAP>
 __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     __shared__ float2 lds[CAP * WG];
+    __shared__ float tab[256];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
-    bool valid = pl.valid;
-    LV U{&lds[threadIdx.x], WG, CAP};
-    int n = valid ? k3_column(P, pl.c, U) : 0;
-    if (n < 0) {
+    // a column whose V0 is fragmented goes straight to the replay
+    const bool defer = pl.valid && P.cntA[pl.c] > K3_DEFER_N;
+    bool valid = pl.valid && !defer;
+    LdsList U{&lds[threadIdx.x], CAP};
+    int n = k3_column<true>(P, pl.c, valid, U, tab);
+    if (n < 0 || defer) {
         push_overflow(Q, ST_K3, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
@@ -776,30 +1055,85 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     emit_wave(P, pl.c, valid, U, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
 }
 
+// Replay of K3: one wave per column, one z-slab per lane; lane 0 stitches the
+// slab lists into an arena list and emits it.  If a slab list overflows, lane
+// 0 evaluates the column alone with an arena list sized from an upper bound.
 __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
-    __shared__ float2 lds[CAP_FB * WG];
+    __shared__ float2 lds[CAP_Z * WG];
+    __shared__ float tab[256];
+    __shared__ float2 env[256];
+    __shared__ int nsh[WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K3];
-    for (int i = blockIdx.x * WG + threadIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t g = Q.ovf[(int64_t)ST_K3 * Q.gcols + i];
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int64_t g = Q.ovf[(int64_t)ST_K3 * Q.gcols + e];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
-        {
-            LV L{&lds[threadIdx.x], WG, CAP_FB};
-            const int n = k3_column(P, c, L);
-            if (n >= 0) {
-                emit_lane(P, c, L, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
-                continue;
+        int x, y;
+        col_xy(P, c, &x, &y);
+        __syncthreads();  // the previous column's stitch has read nsh, lds and env
+        // env[dy]: hull of the chords the seed rows y+-dy .. y+-R can add
+        // (suffix over dy of the per-row bounds); z range of the data
+        float zmin = DX_INF, zmax = -DX_INF;
+        if (lane == 0) {
+            float2 acc = make_float2(DX_INF, -DX_INF);
+            for (int dy = P.R; dy >= 1; --dy) {
+                const float hd = P.H[dy * dy];
+                for (int sd = 0; sd < 2; ++sd) {
+                    const int yy = sd ? y + dy : y - dy;
+                    if (yy < 0 || yy >= P.ny) continue;
+                    const float4 h4 = P.hullB[(int64_t)yy * P.nx + x];
+                    if (h4.x > h4.y) continue;
+                    acc.x = fminf(acc.x, fmaxf(h4.x, h4.z - hd));
+                    acc.y = fmaxf(acc.y, fminf(h4.y, h4.w + hd));
+                }
+                env[dy] = acc;
             }
+            widen(&zmin, &zmax, acc.x);
+            widen(&zmin, &zmax, acc.y);
         }
-        const int64_t bound = k3_bound(P, c);
-        float2* buf = arena_alloc(P, bound);
-        if (!buf) continue;  // keep counting the arena demand
-        LV U{buf, 1, (int)min<int64_t>(bound, 0x7fffffff)};
-        const int n = k3_column(P, c, U);
-        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, U, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+        const float2* V = P.A + P.offA[c];
+        const int n0 = P.cntA[c];
+        for (int i = lane; i < n0; i += WG) {
+            widen(&zmin, &zmax, V[i].x);
+            widen(&zmin, &zmax, V[i].y);
+        }
+        zmin = wave_min(zmin);
+        zmax = wave_max(zmax);
+        __syncthreads();  // env is written
+        const float2 sl = lane_slab(zmin, zmax);
+        LdsList U{&lds[lane], CAP_Z};
+        const int n = k3_slab(P, c, sl.x, sl.y, U, tab, env);
+        nsh[lane] = n;
+        __syncthreads();
+        const bool fail = __any(n < 0);
+        if (lane != 0) continue;
+        if (fail) {
+            const int64_t bound = k3_bound(P, c);
+            const int64_t pos = arena_alloc(P, bound);
+            if (pos < 0) continue;  // keep counting the arena demand
+            MemList M{P.arena + pos, (int)min<int64_t>(bound, 0x7fffffff)};
+            const int nn = k3_column<false>(P, c, true, M, nullptr);
+            if (nn < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); continue; }
+            emit_lane(P, c, M, nn, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+            continue;
+        }
+        int64_t tot = 0;
+        for (int l = 0; l < WG; ++l) tot += nsh[l];
+        const int64_t pos = arena_alloc(P, tot > 0 ? tot : 1);
+        if (pos < 0) continue;
+        float2* out = P.arena + pos;
+        int k = 0;
+        for (int l = 0; l < WG; ++l)
+            for (int i = 0; i < nsh[l]; ++i) {
+                const float2 v = lds[i * WG + l];
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                else out[k++] = v;
+            }
+        MemList M{out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
+        emit_lane(P, c, M, k, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
     }
 }
 
@@ -940,7 +1274,10 @@ __global__ void k_init_call(WsHeader* h, int32_t* shape_status, int nitems) {
 
 __global__ void k_init_pass(WsHeader* h) {
     if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
-    if (threadIdx.x == 0) { h->bumpA = h->bumpI = h->bumpC = h->arena = 0; }
+    if (threadIdx.x == 0) {
+        h->bumpA = h->bumpI = h->bumpC = h->arena = 0;
+        h->nseeds = 0;
+    }
 }
 
 __global__ void k_put_shapes(Shape* dst, ShapeChunk ch) {
@@ -1061,13 +1398,11 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(3);
     hipLaunchKernelGGL(k_neighbour_fb, gf, b, 0, s, p);
     DX_MARK(4);
-    hipLaunchKernelGGL(k_seeds_count<C2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(5);
+    hipLaunchKernelGGL(k_seeds_fb<C2>, gf, b, 0, s, p);
     DX_MARK(6);
-    e = scan_counts(p.cntB_g, p.gcols, p.bsum, p.offB_g, p.hdr, s);
-    if (e != hipSuccess) return e;
     DX_MARK(7);
-    hipLaunchKernelGGL(k_seeds_fill<C2>, g, b, 0, s, p);
     DX_MARK(8);
     DX_MARK(9);
     hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
