@@ -11,7 +11,6 @@
 #include "../../include/dexel.h"
 #include "dexel_internal.h"
 
-using dexel::OpParams;
 using dexel::WsHeader;
 
 struct dexel_ctx {

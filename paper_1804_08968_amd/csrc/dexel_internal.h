@@ -88,27 +88,6 @@ struct Pass {
     int64_t* bsum;
 };
 
-// Per-column view used by the algorithms: one shape's fields plus the
-// shared buffers.
-struct OpParams {
-    int32_t nx, ny;
-    int64_t ncols;
-    const int64_t* col_ptr;
-    const float2* z;
-    int32_t erode;
-    int32_t R;
-    int32_t d2max;
-    const float* H;
-    WsHeader* hdr;
-    int64_t cap;
-    int64_t* offA; int32_t* cntA; float2* A;
-    int64_t* offI; int32_t* cntI; float2* I;
-    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float4* hullB;
-    int64_t* offC; int32_t* cntC; float2* C;
-    float2* arena;
-    uint8_t* arena_tag;
-};
-
 // Descriptor upload through kernel arguments (no host buffer outlives the call).
 constexpr int DESC_CHUNK = 12;
 struct ShapeChunk {

@@ -46,6 +46,53 @@ namespace dexel {
 
 #define DX_INF __builtin_inff()
 
+// Loads from workspace and input arrays go through gld(): the pointers come
+// from descriptors in memory, so the compiler would otherwise emit flat
+// loads, which also count against the LDS wait counter and make every LDS
+// wait also wait for outstanding global loads.
+#define DX_GLOBAL __attribute__((address_space(1)))
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float2 gld(const float2* p) {
+    const f2v v = *(const DX_GLOBAL f2v*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 gld(const float4* p) {
+    const f4v v = *(const DX_GLOBAL f4v*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float gld(const float* p) { return *(const DX_GLOBAL float*)p; }
+__device__ __forceinline__ int64_t gld(const int64_t* p) { return *(const DX_GLOBAL int64_t*)p; }
+__device__ __forceinline__ int32_t gld(const int32_t* p) { return *(const DX_GLOBAL int32_t*)p; }
+__device__ __forceinline__ uint8_t gld(const uint8_t* p) { return *(const DX_GLOBAL uint8_t*)p; }
+__device__ __forceinline__ void gst(float2* p, float2 v) { *(DX_GLOBAL f2v*)p = f2v{v.x, v.y}; }
+__device__ __forceinline__ void gst(float4* p, float4 v) { *(DX_GLOBAL f4v*)p = f4v{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ void gst(int64_t* p, int64_t v) { *(DX_GLOBAL int64_t*)p = v; }
+__device__ __forceinline__ void gst(int32_t* p, int32_t v) { *(DX_GLOBAL int32_t*)p = v; }
+__device__ __forceinline__ void gst(uint8_t* p, uint8_t v) { *(DX_GLOBAL uint8_t*)p = v; }
+
+// Per-column view used by the algorithms: one shape's fields plus the
+// shared buffers.
+struct OpParams {
+    int32_t nx, ny;
+    int64_t ncols;
+    const int64_t* col_ptr;
+    const float2* z;
+    int32_t erode;
+    int32_t R;
+    int32_t d2max;
+    const float* H;
+    WsHeader* hdr;
+    int64_t cap;
+    int64_t* offA; int32_t* cntA; float2* A;
+    int64_t* offI; int32_t* cntI; float2* I;
+    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float4* hullB;
+    int64_t* offC; int32_t* cntC; float2* C;
+    float2* arena;
+    uint8_t* arena_tag;
+};
+
 constexpr int WG = 64;
 // Replay kernels: overflow entry i goes to block i % FALLBACK_BLOCKS, so the
 // (typically heavy) replayed columns are spread over many waves instead of
@@ -86,9 +133,9 @@ __device__ __forceinline__ void note_need(WsHeader* h, unsigned long long need) 
 
 // k-th interval of a column (complemented for erosion: closed gaps).
 __device__ __forceinline__ float2 col_item(const float2* z, int64_t b, int n, int k, int erode) {
-    if (!erode) return z[b + k];
-    float lo = (k == 0) ? -DX_INF : z[b + k - 1].y;
-    float hi = (k == n) ? DX_INF : z[b + k].x;
+    if (!erode) return gld(&z[b + k]);
+    float lo = (k == 0) ? -DX_INF : gld(&z[b + k - 1]).y;
+    float hi = (k == n) ? DX_INF : gld(&z[b + k]).x;
     return make_float2(lo, hi);
 }
 
@@ -158,8 +205,9 @@ __device__ int lv_insert_fwd(const L& U, int n, float lo, float hi, int* hint) {
     return n - sh;
 }
 
-// Is [lo, hi] inside one interval of the canonical global list L[0..n)?
-__device__ __forceinline__ bool in_list(const float2* L, int n, float lo, float hi) {
+// Is [lo, hi] inside one interval of the canonical list L[0..n)?
+template <class Ptr>
+__device__ __forceinline__ bool in_list(Ptr L, int n, float lo, float hi) {
     int l = 0, h = n;
     while (l < h) {
         int m = (l + h) >> 1;
@@ -188,8 +236,8 @@ __device__ __forceinline__ void col_xy(const OpParams& P, int64_t c, int* x, int
 
 // Number of (possibly complemented) intervals of input column cc.
 __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b) {
-    *b = P.col_ptr[cc];
-    return (int)(P.col_ptr[cc + 1] - *b);
+    *b = gld(&P.col_ptr[cc]);
+    return (int)(gld(&P.col_ptr[cc + 1]) - *b);
 }
 
 // ---------------------------------------------------------------------------
@@ -201,14 +249,75 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // input column are enumerated as one index sequence, whatever the reason a
 // candidate was selected.
 
+// Merge the chords [item.x - h, item.y + h] of items [0, cnt) of one input
+// column into the canonical list U of size n (chords and U both sorted by
+// start).  U is first moved to the top of its buffer and the merged list is
+// written from the bottom; a write may take the slot of an entry already
+// read, never one still to be read.  Returns the new size, or -1 if the
+// merged list would overtake the unread entries or exceed the capacity.
+// Two heads of each input are kept in registers so that every load has one
+// merge step to arrive.
+template <class L>
+__device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int m, int cnt, float h) {
+    const int top = U.cap - n;
+    for (int i = n - 1; i >= 0; --i) U.set(top + i, U.get(i));
+    float2 u0 = n > 0 ? U.get(top) : make_float2(0.f, 0.f);
+    float2 u1 = n > 1 ? U.get(top + 1) : make_float2(0.f, 0.f);
+    float2 c0 = make_float2(0.f, 0.f), c1 = make_float2(0.f, 0.f);
+    if (cnt > 0) {
+        const float2 it = col_item(P.z, b, m, 0, P.erode);
+        c0 = make_float2(it.x - h, it.y + h);
+    }
+    if (cnt > 1) {
+        const float2 it = col_item(P.z, b, m, 1, P.erode);
+        c1 = make_float2(it.x - h, it.y + h);
+    }
+    int i = 0, j = 0, k = 0;
+    float clo = 0.f, chi = 0.f;
+    bool have = false;
+    while (i < n || j < cnt) {
+        const bool takeU = j >= cnt || (i < n && u0.x <= c0.x);
+        float2 v;
+        if (takeU) {
+            v = u0;
+            u0 = u1;
+            ++i;
+            if (i + 1 < n) u1 = U.get(top + i + 1);
+        } else {
+            v = c0;
+            c0 = c1;
+            ++j;
+            if (j + 1 < cnt) {
+                const float2 it = col_item(P.z, b, m, j + 1, P.erode);
+                c1 = make_float2(it.x - h, it.y + h);
+            }
+        }
+        if (have && v.x <= chi) {
+            chi = fmaxf(chi, v.y);
+        } else {
+            if (have) {
+                if (k > top + i || k >= U.cap) return -1;
+                U.set(k++, make_float2(clo, chi));
+            }
+            clo = v.x;
+            chi = v.y;
+            have = true;
+        }
+    }
+    if (have) {
+        if (k >= U.cap) return -1;
+        U.set(k++, make_float2(clo, chi));
+    }
+    return k;
+}
+
 // K1: V0 = union over |dx| <= R of the chords [a - H[dx^2], b + H[dx^2]] of
-// the row's columns x + dx, nearest columns first (largest chords first, so
-// most later chords are found inside the list and skipped).  Within a column
-// the chord starts and the chord ends are both non-decreasing (disjoint
-// sorted intervals, one half-width), so while the partial union is a single
-// interval [L, E] only a leading run of chords starting below L and a
-// trailing run ending above E can change it; the candidates of a column are
-// the whole column otherwise.
+// the row's columns x + dx, nearest columns first (largest chords first).
+// Within a column the chord starts and the chord ends are both
+// non-decreasing (disjoint sorted intervals, one half-width), so while the
+// partial union is a single interval [L, E] only a leading run of chords
+// starting below L and a trailing run ending above E can change it, and are
+// inserted; otherwise the column's chords are merged with the list.
 template <class L>
 __device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
     int x, y;
@@ -216,20 +325,23 @@ __device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
     const int64_t row = (int64_t)y * P.nx;
     int n = 0;
     for (int t = 0; t <= P.R; ++t) {
-        const float h = P.H[t * t];
+        const float h = gld(&P.H[t * t]);
         for (int s = 0; s < (t ? 2 : 1); ++s) {
             const int xx = s ? x + t : x - t;
             if (xx < 0 || xx >= P.nx) continue;
             int64_t b;
             const int m = col_len(P, row + xx, &b);
             const int cnt = P.erode ? m + 1 : m;
-            int k0 = cnt, k1 = cnt;
-            if (n == 1) {
-                const float2 u = U.get(0);
-                k0 = 0;
-                while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
-                while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
+            if (cnt == 0) continue;
+            if (n != 1) {
+                n = merge_column(P, U, n, b, m, cnt, h);
+                if (n < 0) return -1;
+                continue;
             }
+            const float2 u = U.get(0);
+            int k0 = 0, k1 = cnt;
+            while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
+            while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
             // candidates: items [0, k0) then [k1, cnt); the next item is
             // loaded before the current one is inserted
             const int nc = k0 + (cnt - k1);
@@ -270,13 +382,13 @@ __device__ int k1b_column(const OpParams& P, int64_t c, const L& L0, const L& L1
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
             const int64_t cc = (int64_t)yy * P.nx + x;
-            const float2* J = P.A + P.offA[cc];
-            const int m = P.cntA[cc];
+            const float2* J = P.A + gld(&P.offA[cc]);
+            const int m = gld(&P.cntA[cc]);
             const L& S = cur ? L1 : L0;
             const L& D = cur ? L0 : L1;
             int i = 0, j = 0, k = 0;
             while (i < n && j < m) {
-                float2 a = S.get(i), bb = J[j];
+                float2 a = S.get(i), bb = gld(&J[j]);
                 float lo = fmaxf(a.x, bb.x), hi = fminf(a.y, bb.y);
                 if (lo < hi) {
                     if (k >= D.cap) return -1;
@@ -300,7 +412,7 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
         for (int s = 0; s < 2; ++s) {
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
-            b += P.cntA[(int64_t)yy * P.nx + x];
+            b += gld(&P.cntA[(int64_t)yy * P.nx + x]);
         }
     return b;
 }
@@ -318,7 +430,8 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
 // returned.
 
 // Is [lo, hi] inside I(c)?  A one-interval I is tested from registers.
-__device__ __forceinline__ bool in_I(const float2* Ip, int ni, float2 i0, float lo, float hi) {
+template <class Ptr>
+__device__ __forceinline__ bool in_I(Ptr Ip, int ni, float2 i0, float lo, float hi) {
     if (ni == 1) return i0.x <= lo && hi <= i0.y;
     return in_list(Ip, ni, lo, hi);
 }
@@ -326,8 +439,8 @@ __device__ __forceinline__ bool in_I(const float2* Ip, int ni, float2 i0, float 
 __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, int* np, float2* dst,
                                         uint8_t* dtag, int dcap, float4* hull) {
     if (*np < dcap) {
-        dst[*np] = make_float2(p, q);
-        dtag[*np] = (uint8_t)t;
+        gst(&dst[*np], make_float2(p, q));
+        gst(&dtag[*np], (uint8_t)t);
     }
     hull->x = fminf(hull->x, p - h1);
     hull->y = fmaxf(hull->y, q + h1);
@@ -336,8 +449,8 @@ __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, int* 
     ++*np;
 }
 
-template <class L>
-__device__ __forceinline__ void k2_segment(const float2* Ip, int ni, float2 i0, const L& U, int* n,
+template <class Ptr, class L>
+__device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U, int* n,
                                            float a, float e, float h1, int t, int* np,
                                            float2* dst, uint8_t* dtag, int dcap, float4* hull) {
     if (in_I(Ip, ni, i0, a - h1, e + h1)) return;
@@ -368,16 +481,17 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
-    const float2* Ip = P.I + P.offI[c];
-    const int ni = P.cntI[c];
-    const float2 i0 = ni == 1 ? Ip[0] : make_float2(0.f, 0.f);
-    const float ilo = ni > 0 ? (ni == 1 ? i0.x : Ip[0].x) : 0.f;
-    const float ihi = ni > 0 ? (ni == 1 ? i0.y : Ip[ni - 1].y) : 0.f;
+    const float2* Ip = P.I + gld(&P.offI[c]);
+    const int ni = gld(&P.cntI[c]);
+    float2 i0 = make_float2(0.f, 0.f);
+    if (ni == 1) i0 = gld(&Ip[0]);
+    const float ilo = ni > 0 ? (ni == 1 ? i0.x : gld(&Ip[0]).x) : 0.f;
+    const float ihi = ni > 0 ? (ni == 1 ? i0.y : gld(&Ip[ni - 1]).y) : 0.f;
     int n = 0, np = 0;
     for (int t = 0; t <= P.R; ++t) {
         const int d2 = t * t + 1;
         if (d2 > P.d2max) break;
-        const float h1 = P.H[d2];
+        const float h1 = gld(&P.H[d2]);
         for (int s = 0; s < (t ? 2 : 1); ++s) {
             const int xx = s ? x + t : x - t;
             if (xx < 0 || xx >= P.nx) continue;
@@ -401,8 +515,8 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
                         kb = cnt;
                         while (kb > next && col_item(P.z, b, m, kb - 1, P.erode).y + h1 > ihi) --kb;
                     } else {  // gap (I[g-1].y, I[g].x): first chord ending above its start
-                        const float glo = Ip[g - 1].y;
-                        lim = Ip[g].x;
+                        const float glo = gld(&Ip[g - 1]).y;
+                        lim = gld(&Ip[g]).x;
                         int l = next, hh = cnt;
                         while (l < hh) {
                             const int mid = (l + hh) >> 1;
@@ -433,8 +547,8 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
 // taking part in the staging.
 __device__ __forceinline__ void seed_span(const OpParams& P, int64_t cc, const float2** sp,
                                           const uint8_t** tp, int* nb) {
-    const int64_t ob = P.offB[cc];
-    *nb = P.cntB[cc];
+    const int64_t ob = gld(&P.offB[cc]);
+    *nb = gld(&P.cntB[cc]);
     if (ob >= 0) {
         *sp = P.B + ob;
         *tp = P.tagB + ob;
@@ -452,12 +566,12 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
     int n = 0;
     bool ok = live;
     if (ok) {
-        const int n0 = P.cntA[c];
+        const int n0 = gld(&P.cntA[c]);
         if (n0 > U.cap) {
             ok = false;
         } else {
-            const float2* V = P.A + P.offA[c];
-            for (int i = 0; i < n0; ++i) U.set(i, V[i]);
+            const float2* V = P.A + gld(&P.offA[c]);
+            for (int i = 0; i < n0; ++i) U.set(i, gld(&V[i]));
             n = n0;
         }
     }
@@ -470,12 +584,12 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             __syncthreads();
             for (int t = threadIdx.x; t <= P.R; t += WG) {
                 const int d2 = t * t + dy2;
-                tab[t] = d2 <= P.d2max ? P.H[d2] : -1.0f;
+                tab[t] = d2 <= P.d2max ? gld(&P.H[d2]) : -1.0f;
             }
             __syncthreads();
         }
         if (!ok) continue;
-        const float hd = P.H[dy2];
+        const float hd = gld(&P.H[dy2]);
         for (int s = 0; s < 2 && ok; ++s) {
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
@@ -484,7 +598,7 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             // at |dy| = 1 and inside its piece hull widened by H[dy^2] (the
             // widest half-width at this dy); skip the column when the
             // tighter of the two bounds is inside the union.
-            const float4 h4 = P.hullB[cc];
+            const float4 h4 = gld(&P.hullB[cc]);
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
             if (n == 1) {
@@ -498,8 +612,8 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             int nb;
             seed_span(P, cc, &sp, &tp, &nb);
             for (int j = 0; j < nb; ++j) {
-                const int t = tp[j];
-                const float2 pc = sp[j];
+                const int t = gld(&tp[j]);
+                const float2 pc = gld(&sp[j]);
                 float h;
                 if (TAB) {
                     h = tab[t];
@@ -507,7 +621,7 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
                 } else {
                     const int d2 = t * t + dy2;
                     if (d2 > P.d2max) continue;
-                    h = P.H[d2];
+                    h = gld(&P.H[d2]);
                 }
                 const float lo = pc.x - h, hi = pc.y + h;
                 if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
@@ -527,12 +641,12 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
 __device__ int64_t k3_bound(const OpParams& P, int64_t c) {
     int x, y;
     col_xy(P, c, &x, &y);
-    int64_t b = (int64_t)P.cntA[c] + 1;
+    int64_t b = (int64_t)gld(&P.cntA[c]) + 1;
     for (int dy = 1; dy <= P.R; ++dy)
         for (int s = 0; s < 2; ++s) {
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
-            b += P.cntB[(int64_t)yy * P.nx + x];
+            b += gld(&P.cntB[(int64_t)yy * P.nx + x]);
         }
     return b;
 }
@@ -582,18 +696,19 @@ __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
 // K2 restricted to the slab [zs, ze]: the input items of the row window are
 // clipped to the slab before painting, so a piece cut at a slab boundary is
 // kept as two pieces whose chords overlap.
-template <class L>
-__device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, const float2* Ip, int ni,
+template <class Ptr, class L>
+__device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni,
                        const L& U, float2* dst, uint8_t* dtag, int dcap, float4* hull) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
-    const float2 i0 = ni == 1 ? Ip[0] : make_float2(0.f, 0.f);
+    float2 i0 = make_float2(0.f, 0.f);
+    if (ni == 1) i0 = Ip[0];
     int n = 0, np = 0;
     for (int t = 0; t <= P.R; ++t) {
         const int d2 = t * t + 1;
         if (d2 > P.d2max) break;
-        const float h1 = P.H[d2];
+        const float h1 = gld(&P.H[d2]);
         for (int s = 0; s < (t ? 2 : 1); ++s) {
             const int xx = s ? x + t : x - t;
             if (xx < 0 || xx >= P.nx) continue;
@@ -629,10 +744,10 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
     col_xy(P, c, &x, &y);
     int n = 0;
     bool ok = true;
-    const float2* V = P.A + P.offA[c];
-    const int n0 = P.cntA[c];
+    const float2* V = P.A + gld(&P.offA[c]);
+    const int n0 = gld(&P.cntA[c]);
     for (int i = 0; i < n0 && ok; ++i) {
-        const float2 v = V[i];
+        const float2 v = gld(&V[i]);
         const float lo = fmaxf(v.x, zs), hi = fminf(v.y, ze);
         if (lo > hi) continue;
         if (n >= U.cap) ok = false; else U.set(n++, make_float2(lo, hi));
@@ -643,7 +758,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
         __syncthreads();
         for (int t = threadIdx.x; t <= P.R; t += WG) {
             const int d2 = t * t + dy2;
-            tab[t] = d2 <= P.d2max ? P.H[d2] : -1.0f;
+            tab[t] = d2 <= P.d2max ? gld(&P.H[d2]) : -1.0f;
         }
         __syncthreads();
         if (busy) {
@@ -663,7 +778,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const int yy = s ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
             const int64_t cc = (int64_t)yy * P.nx + x;
-            const float4 h4 = P.hullB[cc];
+            const float4 h4 = gld(&P.hullB[cc]);
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(fmaxf(h4.x, h4.z - hd), zs);
             const float hhi = fminf(fminf(h4.y, h4.w + hd), ze);
@@ -673,9 +788,9 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             int nb;
             seed_span(P, cc, &sp, &tp, &nb);
             for (int j = 0; j < nb; ++j) {
-                const float h = tab[tp[j]];
+                const float h = tab[gld(&tp[j])];
                 if (h < 0.0f) continue;
-                const float2 pc = sp[j];
+                const float2 pc = gld(&sp[j]);
                 const float lo = fmaxf(pc.x - h, zs), hi = fminf(pc.y + h, ze);
                 if (lo > hi) continue;
                 n = lv_insert(U, n, lo, hi);
@@ -712,14 +827,14 @@ __device__ void emit_wave(const OpParams& P, int64_t c, bool valid, const L& U, 
         set_error(P.hdr, DEXEL_ERR_WORKSPACE);
     }
     if (!valid) return;
-    off[c] = (int64_t)(base + pre);
-    cnt[c] = ok ? outn : 0;
+    gst(&off[c], (int64_t)(base + pre));
+    gst(&cnt[c], ok ? outn : 0);
     if (!ok) return;
     float2* d = dst + base + pre;
     if (!complement) {
-        for (int i = 0; i < n; ++i) d[i] = U.get(i);
+        for (int i = 0; i < n; ++i) gst(&d[i], U.get(i));
     } else {
-        for (int i = 0; i + 1 < n; ++i) d[i] = make_float2(U.get(i).y, U.get(i + 1).x);
+        for (int i = 0; i + 1 < n; ++i) gst(&d[i], make_float2(U.get(i).y, U.get(i + 1).x));
     }
 }
 
@@ -786,7 +901,7 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.ny = S.ny;
     p.ncols = S.ncols;
     p.col_ptr = S.col_ptr;
-    p.z = S.zoff ? S.z + *S.zoff : S.z;
+    p.z = (S.zoff ? S.z + *S.zoff : S.z);
     p.erode = S.erode;
     p.R = S.R;
     p.d2max = S.d2max;
@@ -795,7 +910,8 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.cap = Q.cap;
     p.offA = S.offA; p.cntA = S.cntA; p.A = Q.A;
     p.offI = S.offI; p.cntI = S.cntI; p.I = Q.I;
-    p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B; p.tagB = Q.tagB; p.hullB = S.hullB;
+    p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B;
+    p.tagB = Q.tagB; p.hullB = S.hullB;
     p.offC = S.offC; p.cntC = S.cntC; p.C = Q.C;
     p.arena = Q.arena;
     p.arena_tag = Q.arena_tag;
@@ -876,7 +992,7 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
         const int64_t bound = k1_bound(P, c);
         const int64_t pos = arena_alloc(P, bound);
         if (pos < 0) continue;  // keep counting the arena demand
-        MemList U{P.arena + pos, (int)min<int64_t>(bound, 0x7fffffff)};
+        MemList U{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
         const int n = k1_column(P, c, U);
         if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
         emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
@@ -925,7 +1041,7 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
         const int64_t pos = arena_alloc(P, 2 * bound);
         if (pos < 0) continue;  // keep counting the arena demand
         const int cap = (int)min<int64_t>(bound, 0x7fffffff);
-        MemList L0{P.arena + pos, cap}, L1{P.arena + pos + bound, cap};
+        MemList L0{(float2*)(P.arena + pos), cap}, L1{P.arena + pos + bound, cap};
         int res = 0;
         const int n = k1b_column(P, c, L0, L1, &res);
         if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
@@ -945,16 +1061,16 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     int np = 0;
     if (pl.valid) {
         const int64_t g = pl.g0 + threadIdx.x;
-        if (P.cntI[pl.c] > K2_DEFER_NI) {
+        if (gld(&P.cntI[pl.c]) > K2_DEFER_NI) {
             P.cntB[pl.c] = 0;
             push_overflow(Q, ST_K2, g);
         } else {
             LdsList U{&lds[threadIdx.x], CAP};
             float4 hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
-            np = k2_column(P, pl.c, U, Q.B + g * SEED_SLOT, Q.tagB + g * SEED_SLOT, SEED_SLOT, &hull);
-            P.offB[pl.c] = g * SEED_SLOT;
-            P.cntB[pl.c] = np;
-            P.hullB[pl.c] = hull;
+            np = k2_column(P, pl.c, U, P.B + g * SEED_SLOT, P.tagB + g * SEED_SLOT, SEED_SLOT, &hull);
+            gst(&P.offB[pl.c], g * SEED_SLOT);
+            gst(&P.cntB[pl.c], np);
+            gst(&P.hullB[pl.c], hull);
             if (np > SEED_SLOT) {
                 push_overflow(Q, ST_K2, g);
                 np = 0;  // counted by the replay
@@ -983,12 +1099,12 @@ __global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
-        const int ni = P.cntI[c];
-        const float2* Ig = P.I + P.offI[c];
+        const int ni = gld(&P.cntI[c]);
+        const float2* Ig = P.I + gld(&P.offI[c]);
         const bool staged = ni <= ISH;
         __syncthreads();  // the previous column's readers of ish are done
         if (staged)
-            for (int i = lane; i < ni; i += WG) ish[i] = Ig[i];
+            for (int i = lane; i < ni; i += WG) ish[i] = gld(&Ig[i]);
         __syncthreads();
         const float2* Ip = staged ? (const float2*)ish : Ig;
         // finite z range of the row window's input
@@ -1001,8 +1117,8 @@ __global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
             int64_t b;
             const int m = col_len(P, (int64_t)y * P.nx + xx, &b);
             if (m > 0) {
-                widen(&zmin, &zmax, P.z[b].x);
-                widen(&zmin, &zmax, P.z[b + m - 1].y);
+                widen(&zmin, &zmax, gld(&P.z[b]).x);
+                widen(&zmin, &zmax, gld(&P.z[b + m - 1]).y);
             }
         }
         zmin = wave_min(zmin);
@@ -1043,7 +1159,7 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
     // a column whose V0 is fragmented goes straight to the replay
-    const bool defer = pl.valid && P.cntA[pl.c] > K3_DEFER_N;
+    const bool defer = pl.valid && gld(&P.cntA[pl.c]) > K3_DEFER_N;
     bool valid = pl.valid && !defer;
     LdsList U{&lds[threadIdx.x], CAP};
     int n = k3_column<true>(P, pl.c, valid, U, tab);
@@ -1080,11 +1196,11 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
         if (lane == 0) {
             float2 acc = make_float2(DX_INF, -DX_INF);
             for (int dy = P.R; dy >= 1; --dy) {
-                const float hd = P.H[dy * dy];
+                const float hd = gld(&P.H[dy * dy]);
                 for (int sd = 0; sd < 2; ++sd) {
                     const int yy = sd ? y + dy : y - dy;
                     if (yy < 0 || yy >= P.ny) continue;
-                    const float4 h4 = P.hullB[(int64_t)yy * P.nx + x];
+                    const float4 h4 = gld(&P.hullB[(int64_t)yy * P.nx + x]);
                     if (h4.x > h4.y) continue;
                     acc.x = fminf(acc.x, fmaxf(h4.x, h4.z - hd));
                     acc.y = fmaxf(acc.y, fminf(h4.y, h4.w + hd));
@@ -1094,11 +1210,12 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
             widen(&zmin, &zmax, acc.x);
             widen(&zmin, &zmax, acc.y);
         }
-        const float2* V = P.A + P.offA[c];
-        const int n0 = P.cntA[c];
+        const float2* V = P.A + gld(&P.offA[c]);
+        const int n0 = gld(&P.cntA[c]);
         for (int i = lane; i < n0; i += WG) {
-            widen(&zmin, &zmax, V[i].x);
-            widen(&zmin, &zmax, V[i].y);
+            const float2 v = gld(&V[i]);
+            widen(&zmin, &zmax, v.x);
+            widen(&zmin, &zmax, v.y);
         }
         zmin = wave_min(zmin);
         zmax = wave_max(zmax);
@@ -1114,7 +1231,7 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
             const int64_t bound = k3_bound(P, c);
             const int64_t pos = arena_alloc(P, bound);
             if (pos < 0) continue;  // keep counting the arena demand
-            MemList M{P.arena + pos, (int)min<int64_t>(bound, 0x7fffffff)};
+            MemList M{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
             const int nn = k3_column<false>(P, c, true, M, nullptr);
             if (nn < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); continue; }
             emit_lane(P, c, M, nn, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
@@ -1132,7 +1249,7 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
                 if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
                 else out[k++] = v;
             }
-        MemList M{out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
+        MemList M{(float2*)out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
         emit_lane(P, c, M, k, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
     }
 }
