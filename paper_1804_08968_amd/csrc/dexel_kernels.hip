@@ -318,44 +318,72 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
 // partial union is a single interval [L, E] only a leading run of chords
 // starting below L and a trailing run ending above E can change it, and are
 // inserted; otherwise the column's chords are merged with the list.
+// Visit v of a row window, nearest columns first: x, x-1, x+1, x-2, x+2, ...
+__device__ __forceinline__ int visit_col(int x, int v) {
+    const int t = (v + 1) >> 1;
+    return v == 0 ? x : ((v & 1) ? x - t : x + t);
+}
+
 template <class L>
 __device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
     int n = 0;
-    for (int t = 0; t <= P.R; ++t) {
+    // column pointers of the next visit are loaded one visit ahead
+    int64_t b = 0, e = 0;
+    bool inr = true;
+    b = gld(&P.col_ptr[row + x]);
+    e = gld(&P.col_ptr[row + x + 1]);
+    for (int v = 0; v <= 2 * P.R; ++v) {
+        const int t = (v + 1) >> 1;
         const float h = gld(&P.H[t * t]);
-        for (int s = 0; s < (t ? 2 : 1); ++s) {
-            const int xx = s ? x + t : x - t;
-            if (xx < 0 || xx >= P.nx) continue;
-            int64_t b;
-            const int m = col_len(P, row + xx, &b);
-            const int cnt = P.erode ? m + 1 : m;
-            if (cnt == 0) continue;
-            if (n != 1) {
-                n = merge_column(P, U, n, b, m, cnt, h);
-                if (n < 0) return -1;
-                continue;
+        const int64_t bc = b, ec = e;
+        const bool inc = inr;
+        if (v < 2 * P.R) {
+            const int xn = visit_col(x, v + 1);
+            inr = xn >= 0 && xn < P.nx;
+            if (inr) {
+                b = gld(&P.col_ptr[row + xn]);
+                e = gld(&P.col_ptr[row + xn + 1]);
             }
-            const float2 u = U.get(0);
-            int k0 = 0, k1 = cnt;
-            while (k0 < cnt && col_item(P.z, b, m, k0, P.erode).x - h < u.x) ++k0;
-            while (k1 > k0 && col_item(P.z, b, m, k1 - 1, P.erode).y + h > u.y) --k1;
-            // candidates: items [0, k0) then [k1, cnt); the next item is
-            // loaded before the current one is inserted
-            const int nc = k0 + (cnt - k1);
-            int hint = 0;
-            float2 nxt = nc > 0 ? col_item(P.z, b, m, k0 > 0 ? 0 : k1, P.erode) : make_float2(0.f, 0.f);
-            for (int j = 0; j < nc; ++j) {
-                const float2 iv = nxt;
-                if (j + 1 < nc) {
-                    const int k = j + 1 < k0 ? j + 1 : k1 + (j + 1 - k0);
-                    nxt = col_item(P.z, b, m, k, P.erode);
-                }
-                n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
-                if (n < 0) return -1;
+        }
+        if (!inc) continue;
+        const int m = (int)(ec - bc);
+        const int cnt = P.erode ? m + 1 : m;
+        if (cnt == 0) continue;
+        if (n != 1) {
+            n = merge_column(P, U, n, bc, m, cnt, h);
+            if (n < 0) return -1;
+            continue;
+        }
+        const float2 u = U.get(0);
+        // the first and last items are loaded together
+        const float2 f = col_item(P.z, bc, m, 0, P.erode);
+        const float2 l = col_item(P.z, bc, m, cnt - 1, P.erode);
+        int k0 = 0, k1 = cnt;
+        if (f.x - h < u.x) {
+            k0 = 1;
+            while (k0 < cnt && col_item(P.z, bc, m, k0, P.erode).x - h < u.x) ++k0;
+        }
+        if (k1 > k0 && l.y + h > u.y) {
+            k1 = cnt - 1;
+            while (k1 > k0 && col_item(P.z, bc, m, k1 - 1, P.erode).y + h > u.y) --k1;
+        }
+        // candidates: items [0, k0) then [k1, cnt); the next item is
+        // loaded before the current one is inserted
+        const int nc = k0 + (cnt - k1);
+        int hint = 0;
+        float2 nxt = k0 > 0 ? f : l;
+        if (k0 == 0 && k1 < cnt - 1) nxt = col_item(P.z, bc, m, k1, P.erode);
+        for (int j = 0; j < nc; ++j) {
+            const float2 iv = nxt;
+            if (j + 1 < nc) {
+                const int k = j + 1 < k0 ? j + 1 : k1 + (j + 1 - k0);
+                nxt = col_item(P.z, bc, m, k, P.erode);
             }
+            n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
+            if (n < 0) return -1;
         }
     }
     return n;
@@ -488,51 +516,73 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
     const float ilo = ni > 0 ? (ni == 1 ? i0.x : gld(&Ip[0]).x) : 0.f;
     const float ihi = ni > 0 ? (ni == 1 ? i0.y : gld(&Ip[ni - 1]).y) : 0.f;
     int n = 0, np = 0;
-    for (int t = 0; t <= P.R; ++t) {
-        const int d2 = t * t + 1;
-        if (d2 > P.d2max) break;
-        const float h1 = gld(&P.H[d2]);
-        for (int s = 0; s < (t ? 2 : 1); ++s) {
-            const int xx = s ? x + t : x - t;
-            if (xx < 0 || xx >= P.nx) continue;
-            int64_t b;
-            const int m = col_len(P, row + xx, &b);
-            const int cnt = P.erode ? m + 1 : m;
-            // Chords that can poke out of I form one run per gap of I (the
-            // two unbounded ends included), because a column's chord starts
-            // and chord ends are both non-decreasing.  Short columns, and
-            // columns tested against an empty I, are one run.
-            const bool all = ni == 0 || cnt <= 8;
-            const int nruns = all ? 1 : ni + 1;
-            int next = 0;
-            for (int g = 0; g < nruns; ++g) {
-                int kb = 0;
-                float lim = DX_INF;  // the run ends at the first chord starting at or above lim
-                if (!all) {
-                    if (g == 0) {
-                        lim = ilo;
-                    } else if (g == ni) {
-                        kb = cnt;
-                        while (kb > next && col_item(P.z, b, m, kb - 1, P.erode).y + h1 > ihi) --kb;
-                    } else {  // gap (I[g-1].y, I[g].x): first chord ending above its start
-                        const float glo = gld(&Ip[g - 1]).y;
-                        lim = gld(&Ip[g]).x;
-                        int l = next, hh = cnt;
-                        while (l < hh) {
-                            const int mid = (l + hh) >> 1;
-                            if (col_item(P.z, b, m, mid, P.erode).y + h1 > glo) hh = mid; else l = mid + 1;
-                        }
-                        kb = l;
-                    }
-                }
-                int k = kb;
-                for (; k < cnt; ++k) {
-                    const float2 sg = col_item(P.z, b, m, k, P.erode);
-                    if (!(sg.x - h1 < lim)) break;
-                    k2_segment(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, dcap, hull);
-                }
-                next = max(next, k);
+    // visits up to |dx| = tmax (the chord at |dy| = 1 must exist)
+    int tmax = P.R;
+    while (tmax >= 0 && tmax * tmax + 1 > P.d2max) --tmax;
+    // column pointers of the next visit are loaded one visit ahead
+    int64_t b = 0, e = 0;
+    bool inr = tmax >= 0;
+    if (inr) {
+        b = gld(&P.col_ptr[row + x]);
+        e = gld(&P.col_ptr[row + x + 1]);
+    }
+    for (int v = 0; v <= 2 * tmax; ++v) {
+        const int t = (v + 1) >> 1;
+        const float h1 = gld(&P.H[t * t + 1]);
+        const int64_t bc = b, ec = e;
+        const bool inc = inr;
+        if (v < 2 * tmax) {
+            const int xn = visit_col(x, v + 1);
+            inr = xn >= 0 && xn < P.nx;
+            if (inr) {
+                b = gld(&P.col_ptr[row + xn]);
+                e = gld(&P.col_ptr[row + xn + 1]);
             }
+        }
+        if (!inc) continue;
+        const int m = (int)(ec - bc);
+        const int cnt = P.erode ? m + 1 : m;
+        if (cnt == 0) continue;
+        // the first and last items are loaded together
+        const float2 f = col_item(P.z, bc, m, 0, P.erode);
+        const float2 l = col_item(P.z, bc, m, cnt - 1, P.erode);
+        auto item = [&](int k) {
+            return k == 0 ? f : (k == cnt - 1 ? l : col_item(P.z, bc, m, k, P.erode));
+        };
+        // Chords that can poke out of I form one run per gap of I (the two
+        // unbounded ends included), because a column's chord starts and
+        // chord ends are both non-decreasing.  Short columns, and columns
+        // tested against an empty I, are one run.
+        const bool all = ni == 0 || cnt <= 8;
+        const int nruns = all ? 1 : ni + 1;
+        int next = 0;
+        for (int g = 0; g < nruns; ++g) {
+            int kb = 0;
+            float lim = DX_INF;  // the run ends at the first chord starting at or above lim
+            if (!all) {
+                if (g == 0) {
+                    lim = ilo;
+                } else if (g == ni) {
+                    kb = cnt;
+                    while (kb > next && item(kb - 1).y + h1 > ihi) --kb;
+                } else {  // gap (I[g-1].y, I[g].x): first chord ending above its start
+                    const float glo = gld(&Ip[g - 1]).y;
+                    lim = gld(&Ip[g]).x;
+                    int lo = next, hh = cnt;
+                    while (lo < hh) {
+                        const int mid = (lo + hh) >> 1;
+                        if (item(mid).y + h1 > glo) hh = mid; else lo = mid + 1;
+                    }
+                    kb = lo;
+                }
+            }
+            int k = kb;
+            for (; k < cnt; ++k) {
+                const float2 sg = item(k);
+                if (!(sg.x - h1 < lim)) break;
+                k2_segment(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, dcap, hull);
+            }
+            next = max(next, k);
         }
     }
     return np;
@@ -590,15 +640,18 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
         }
         if (!ok) continue;
         const float hd = gld(&P.H[dy2]);
+        // the hulls of both seed rows are loaded together
+        const int64_t cl = (int64_t)(y - dy) * P.nx + x, cr = (int64_t)(y + dy) * P.nx + x;
+        const float4 none = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+        const float4 hl = y - dy >= 0 ? gld(&P.hullB[cl]) : none;
+        const float4 hr = y + dy < P.ny ? gld(&P.hullB[cr]) : none;
         for (int s = 0; s < 2 && ok; ++s) {
-            const int yy = s ? y + dy : y - dy;
-            if (yy < 0 || yy >= P.ny) continue;
-            const int64_t cc = (int64_t)yy * P.nx + x;
+            const int64_t cc = s ? cr : cl;
+            const float4 h4 = s ? hr : hl;
             // Every chord of this seed column at this dy lies inside its hull
             // at |dy| = 1 and inside its piece hull widened by H[dy^2] (the
             // widest half-width at this dy); skip the column when the
             // tighter of the two bounds is inside the union.
-            const float4 h4 = gld(&P.hullB[cc]);
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
             if (n == 1) {
@@ -611,26 +664,38 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             const uint8_t* tp;
             int nb;
             seed_span(P, cc, &sp, &tp, &nb);
-            for (int j = 0; j < nb; ++j) {
-                const int t = gld(&tp[j]);
-                const float2 pc = gld(&sp[j]);
-                float h;
-                if (TAB) {
-                    h = tab[t];
-                    if (h < 0.0f) continue;
-                } else {
-                    const int d2 = t * t + dy2;
-                    if (d2 > P.d2max) continue;
-                    h = gld(&P.H[d2]);
+            // seeds in groups of four: the loads of a group are in flight together
+            for (int j = 0; j < nb && ok; j += 4) {
+                int tq[4];
+                float2 pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int jj = min(j + q, nb - 1);
+                    tq[q] = gld(&tp[jj]);
+                    pq[q] = gld(&sp[jj]);
                 }
-                const float lo = pc.x - h, hi = pc.y + h;
-                if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
-                n = lv_insert(U, n, lo, hi);
-                if (n < 0) {
-                    ok = false;
-                    break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (j + q >= nb) break;
+                    const int t = tq[q];
+                    float h;
+                    if (TAB) {
+                        h = tab[t];
+                        if (h < 0.0f) continue;
+                    } else {
+                        const int d2 = t * t + dy2;
+                        if (d2 > P.d2max) continue;
+                        h = gld(&P.H[d2]);
+                    }
+                    const float lo = pq[q].x - h, hi = pq[q].y + h;
+                    if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
+                    n = lv_insert(U, n, lo, hi);
+                    if (n < 0) {
+                        ok = false;
+                        break;
+                    }
+                    if (n == 1) u0 = U.get(0);
                 }
-                if (n == 1) u0 = U.get(0);
             }
         }
     }
