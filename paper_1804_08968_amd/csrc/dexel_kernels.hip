@@ -131,9 +131,12 @@ __device__ __forceinline__ void note_need(WsHeader* h, unsigned long long need) 
     atomicMax(&h->need_cap, need);
 }
 
-// k-th interval of a column (complemented for erosion: closed gaps).
-__device__ __forceinline__ float2 col_item(const float2* z, int64_t b, int n, int k, int erode) {
-    if (!erode) return gld(&z[b + k]);
+// k-th interval of a column (complemented for erosion, E: closed gaps).  The
+// column walks are instantiated for both cases, so that the choice is made
+// once per call rather than at every item.
+template <bool E>
+__device__ __forceinline__ float2 col_item(const float2* z, int64_t b, int n, int k) {
+    if (!E) return gld(&z[b + k]);
     float lo = (k == 0) ? -DX_INF : gld(&z[b + k - 1]).y;
     float hi = (k == n) ? DX_INF : gld(&z[b + k]).x;
     return make_float2(lo, hi);
@@ -257,57 +260,59 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // merged list would overtake the unread entries or exceed the capacity.
 // Two heads of each input are kept in registers so that every load has one
 // merge step to arrive.
-template <class L>
+template <bool E, class L>
 __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int m, int cnt, float h) {
     const int top = U.cap - n;
     for (int i = n - 1; i >= 0; --i) U.set(top + i, U.get(i));
-    float2 u0 = n > 0 ? U.get(top) : make_float2(0.f, 0.f);
-    float2 u1 = n > 1 ? U.get(top + 1) : make_float2(0.f, 0.f);
-    float2 c0 = make_float2(0.f, 0.f), c1 = make_float2(0.f, 0.f);
-    if (cnt > 0) {
-        const float2 it = col_item(P.z, b, m, 0, P.erode);
-        c0 = make_float2(it.x - h, it.y + h);
+    auto chord = [&](int k) {
+        const float2 it = col_item<E>(P.z, b, m, k);
+        return make_float2(it.x - h, it.y + h);
+    };
+    // heads: u0, u1 of the list (valid while i < n, i + 1 < n), c0, c1 of
+    // the chords; reads past the end are clamped to the last entry
+    const int nl = n > 0 ? n - 1 : 0, cl = cnt - 1;
+    float2 u0 = make_float2(0.f, 0.f), u1 = u0;
+    if (n > 0) {
+        u0 = U.get(top);
+        u1 = U.get(top + min(1, nl));
     }
-    if (cnt > 1) {
-        const float2 it = col_item(P.z, b, m, 1, P.erode);
-        c1 = make_float2(it.x - h, it.y + h);
-    }
+    float2 c0 = chord(0), c1 = chord(min(1, cl));
     int i = 0, j = 0, k = 0;
-    float clo = 0.f, chi = 0.f;
-    bool have = false;
+    // the first interval in start order opens the output
+    float2 cur;
+    if (n > 0 && u0.x <= c0.x) {
+        cur = u0;
+        u0 = u1;
+        ++i;
+        if (i < n) u1 = U.get(top + min(i + 1, nl));
+    } else {
+        cur = c0;
+        c0 = c1;
+        ++j;
+        if (j < cnt) c1 = chord(min(j + 1, cl));
+    }
     while (i < n || j < cnt) {
         const bool takeU = j >= cnt || (i < n && u0.x <= c0.x);
-        float2 v;
+        const float2 v = takeU ? u0 : c0;
         if (takeU) {
-            v = u0;
             u0 = u1;
             ++i;
-            if (i + 1 < n) u1 = U.get(top + i + 1);
+            u1 = U.get(top + min(i + 1, nl));
         } else {
-            v = c0;
             c0 = c1;
             ++j;
-            if (j + 1 < cnt) {
-                const float2 it = col_item(P.z, b, m, j + 1, P.erode);
-                c1 = make_float2(it.x - h, it.y + h);
-            }
+            c1 = chord(min(j + 1, cl));
         }
-        if (have && v.x <= chi) {
-            chi = fmaxf(chi, v.y);
+        if (v.x <= cur.y) {
+            cur.y = fmaxf(cur.y, v.y);
         } else {
-            if (have) {
-                if (k > top + i || k >= U.cap) return -1;
-                U.set(k++, make_float2(clo, chi));
-            }
-            clo = v.x;
-            chi = v.y;
-            have = true;
+            if (k > top + i || k >= U.cap) return -1;
+            U.set(k++, cur);
+            cur = v;
         }
     }
-    if (have) {
-        if (k >= U.cap) return -1;
-        U.set(k++, make_float2(clo, chi));
-    }
+    if (k >= U.cap) return -1;
+    U.set(k++, cur);
     return k;
 }
 
@@ -324,8 +329,8 @@ __device__ __forceinline__ int visit_col(int x, int v) {
     return v == 0 ? x : ((v & 1) ? x - t : x + t);
 }
 
-template <class L>
-__device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
+template <bool E, class L>
+__device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -350,43 +355,48 @@ __device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
         }
         if (!inc) continue;
         const int m = (int)(ec - bc);
-        const int cnt = P.erode ? m + 1 : m;
+        const int cnt = E ? m + 1 : m;
         if (cnt == 0) continue;
         if (n != 1) {
-            n = merge_column(P, U, n, bc, m, cnt, h);
+            n = merge_column<E>(P, U, n, bc, m, cnt, h);
             if (n < 0) return -1;
             continue;
         }
         const float2 u = U.get(0);
         // the first and last items are loaded together
-        const float2 f = col_item(P.z, bc, m, 0, P.erode);
-        const float2 l = col_item(P.z, bc, m, cnt - 1, P.erode);
+        const float2 f = col_item<E>(P.z, bc, m, 0);
+        const float2 l = col_item<E>(P.z, bc, m, cnt - 1);
         int k0 = 0, k1 = cnt;
         if (f.x - h < u.x) {
             k0 = 1;
-            while (k0 < cnt && col_item(P.z, bc, m, k0, P.erode).x - h < u.x) ++k0;
+            while (k0 < cnt && col_item<E>(P.z, bc, m, k0).x - h < u.x) ++k0;
         }
         if (k1 > k0 && l.y + h > u.y) {
             k1 = cnt - 1;
-            while (k1 > k0 && col_item(P.z, bc, m, k1 - 1, P.erode).y + h > u.y) --k1;
+            while (k1 > k0 && col_item<E>(P.z, bc, m, k1 - 1).y + h > u.y) --k1;
         }
         // candidates: items [0, k0) then [k1, cnt); the next item is
         // loaded before the current one is inserted
         const int nc = k0 + (cnt - k1);
         int hint = 0;
         float2 nxt = k0 > 0 ? f : l;
-        if (k0 == 0 && k1 < cnt - 1) nxt = col_item(P.z, bc, m, k1, P.erode);
+        if (k0 == 0 && k1 < cnt - 1) nxt = col_item<E>(P.z, bc, m, k1);
         for (int j = 0; j < nc; ++j) {
             const float2 iv = nxt;
             if (j + 1 < nc) {
                 const int k = j + 1 < k0 ? j + 1 : k1 + (j + 1 - k0);
-                nxt = col_item(P.z, bc, m, k, P.erode);
+                nxt = col_item<E>(P.z, bc, m, k);
             }
             n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
             if (n < 0) return -1;
         }
     }
     return n;
+}
+
+template <class L>
+__device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
+    return P.erode ? k1_column_e<true>(P, c, U) : k1_column_e<false>(P, c, U);
 }
 
 __device__ int64_t k1_bound(const OpParams& P, int64_t c) {
@@ -503,9 +513,9 @@ __device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U
     if (nn >= 0) *n = nn;
 }
 
-template <class L>
-__device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
-                         int dcap, float4* hull) {
+template <bool E, class L>
+__device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
+                           int dcap, float4* hull) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -541,13 +551,13 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
         }
         if (!inc) continue;
         const int m = (int)(ec - bc);
-        const int cnt = P.erode ? m + 1 : m;
+        const int cnt = E ? m + 1 : m;
         if (cnt == 0) continue;
         // the first and last items are loaded together
-        const float2 f = col_item(P.z, bc, m, 0, P.erode);
-        const float2 l = col_item(P.z, bc, m, cnt - 1, P.erode);
+        const float2 f = col_item<E>(P.z, bc, m, 0);
+        const float2 l = col_item<E>(P.z, bc, m, cnt - 1);
         auto item = [&](int k) {
-            return k == 0 ? f : (k == cnt - 1 ? l : col_item(P.z, bc, m, k, P.erode));
+            return k == 0 ? f : (k == cnt - 1 ? l : col_item<E>(P.z, bc, m, k));
         };
         // Chords that can poke out of I form one run per gap of I (the two
         // unbounded ends included), because a column's chord starts and
@@ -588,6 +598,13 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
     return np;
 }
 
+template <class L>
+__device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
+                         int dcap, float4* hull) {
+    return P.erode ? k2_column_e<true>(P, c, U, dst, dtag, dcap, hull)
+                   : k2_column_e<false>(P, c, U, dst, dtag, dcap, hull);
+}
+
 // K3: V0(c) plus the chords of the kept seeds of rows y+-dy at weight
 // r^2 - t^2 - dy^2, nearest rows first.  TAB: the wave's lanes (all of
 // them, one shape per wave) first stage the half-widths of the current dy
@@ -625,9 +642,14 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             n = n0;
         }
     }
-    // While the union is one interval, keep it in registers: most seed
-    // chords land inside it and are dropped after two compares.
-    float2 u0 = (ok && n == 1) ? U.get(0) : make_float2(0.f, 0.f);
+    // While the union has one or two intervals (a solid, or the complement
+    // of one in an erosion), keep them in registers: most seed chords land
+    // inside one and are dropped after a few compares.
+    float2 u0 = make_float2(0.f, 0.f), u1 = make_float2(0.f, 0.f);
+    if (ok && n >= 1 && n <= 2) {
+        u0 = U.get(0);
+        if (n == 2) u1 = U.get(1);
+    }
     for (int dy = 1; dy <= P.R; ++dy) {
         const int dy2 = dy * dy;
         if (TAB) {
@@ -654,8 +676,9 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             // tighter of the two bounds is inside the union.
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
-            if (n == 1) {
-                if (u0.x <= hlo && hhi <= u0.y) continue;
+            if (n <= 2) {
+                if (n >= 1 && u0.x <= hlo && hhi <= u0.y) continue;
+                if (n == 2 && u1.x <= hlo && hhi <= u1.y) continue;
             } else {
                 const int i = lv_lower_hi(U, n, hhi);
                 if (i < n && U.get(i).x <= hlo) continue;
@@ -688,13 +711,17 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
                         h = gld(&P.H[d2]);
                     }
                     const float lo = pq[q].x - h, hi = pq[q].y + h;
-                    if (n == 1 && u0.x <= lo && hi <= u0.y) continue;
+                    if (n >= 1 && n <= 2 && u0.x <= lo && hi <= u0.y) continue;
+                    if (n == 2 && u1.x <= lo && hi <= u1.y) continue;
                     n = lv_insert(U, n, lo, hi);
                     if (n < 0) {
                         ok = false;
                         break;
                     }
-                    if (n == 1) u0 = U.get(0);
+                    if (n <= 2) {
+                        u0 = U.get(0);
+                        if (n == 2) u1 = U.get(1);
+                    }
                 }
             }
         }
@@ -761,9 +788,9 @@ __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
 // K2 restricted to the slab [zs, ze]: the input items of the row window are
 // clipped to the slab before painting, so a piece cut at a slab boundary is
 // kept as two pieces whose chords overlap.
-template <class Ptr, class L>
-__device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni,
-                       const L& U, float2* dst, uint8_t* dtag, int dcap, float4* hull) {
+template <bool E, class Ptr, class L>
+__device__ int k2_slab_e(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni,
+                         const L& U, float2* dst, uint8_t* dtag, int dcap, float4* hull) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -779,14 +806,14 @@ __device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip,
             if (xx < 0 || xx >= P.nx) continue;
             int64_t b;
             const int m = col_len(P, row + xx, &b);
-            const int cnt = P.erode ? m + 1 : m;
+            const int cnt = E ? m + 1 : m;
             int l = 0, hh = cnt;  // first item ending at or above zs
             while (l < hh) {
                 const int mid = (l + hh) >> 1;
-                if (col_item(P.z, b, m, mid, P.erode).y < zs) l = mid + 1; else hh = mid;
+                if (col_item<E>(P.z, b, m, mid).y < zs) l = mid + 1; else hh = mid;
             }
             for (int k = l; k < cnt; ++k) {
-                const float2 sg = col_item(P.z, b, m, k, P.erode);
+                const float2 sg = col_item<E>(P.z, b, m, k);
                 if (sg.x > ze) break;
                 k2_segment(Ip, ni, i0, U, &n, fmaxf(sg.x, zs), fminf(sg.y, ze), h1, t, &np, dst,
                            dtag, dcap, hull);
@@ -794,6 +821,13 @@ __device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip,
         }
     }
     return np;
+}
+
+template <class Ptr, class L>
+__device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni, const L& U,
+                       float2* dst, uint8_t* dtag, int dcap, float4* hull) {
+    return P.erode ? k2_slab_e<true>(P, c, zs, ze, Ip, ni, U, dst, dtag, dcap, hull)
+                   : k2_slab_e<false>(P, c, zs, ze, Ip, ni, U, dst, dtag, dcap, hull);
 }
 
 // K3 restricted to the slab [zs, ze]: V0(c) and every seed chord clipped to
@@ -852,16 +886,28 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const uint8_t* tp;
             int nb;
             seed_span(P, cc, &sp, &tp, &nb);
-            for (int j = 0; j < nb; ++j) {
-                const float h = tab[gld(&tp[j])];
-                if (h < 0.0f) continue;
-                const float2 pc = gld(&sp[j]);
-                const float lo = fmaxf(pc.x - h, zs), hi = fminf(pc.y + h, ze);
-                if (lo > hi) continue;
-                n = lv_insert(U, n, lo, hi);
-                if (n < 0) {
-                    ok = busy = false;
-                    break;
+            // every lane reads the same seeds: groups of four loads in flight
+            for (int j = 0; j < nb && busy; j += 4) {
+                int tq[4];
+                float2 pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int jj = min(j + q, nb - 1);
+                    tq[q] = gld(&tp[jj]);
+                    pq[q] = gld(&sp[jj]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (j + q >= nb) break;
+                    const float h = tab[tq[q]];
+                    if (h < 0.0f) continue;
+                    const float lo = fmaxf(pq[q].x - h, zs), hi = fminf(pq[q].y + h, ze);
+                    if (lo > hi) continue;
+                    n = lv_insert(U, n, lo, hi);
+                    if (n < 0) {
+                        ok = busy = false;
+                        break;
+                    }
                 }
             }
         }
