@@ -60,7 +60,7 @@ void radius_params(float r, int* R, int* d2max) {
 // Workspace layout of one call (a batch of items; a single op is a batch of one).
 struct Layout {
     size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
-    size_t offA, cntA, offI, cntI, offB, cntB, hullB, offC, cntC, scanC;
+    size_t offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table
@@ -111,7 +111,8 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.cntI = take(4 * g);
     L.offB = take(8 * g);
     L.cntB = take(4 * g);
-    L.hullB = take(16 * g);
+    L.loB = take(4 * g);
+    L.hullB = take(32 * g);
     L.offC = take(8 * g);
     L.cntC = take(4 * g);
     L.scanC = take(8 * (g + 1));
@@ -301,7 +302,8 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.cntI = (int32_t*)(w + L.cntI) + gbase;
             S.offB = (int64_t*)(w + L.offB) + gbase;
             S.cntB = (int32_t*)(w + L.cntB) + gbase;
-            S.hullB = (float4*)(w + L.hullB) + gbase;
+            S.loB = (int32_t*)(w + L.loB) + gbase;
+            S.hullB = (float4*)(w + L.hullB) + 2 * gbase;
             S.offC = (int64_t*)(w + L.offC) + gbase;
             S.cntC = (int32_t*)(w + L.cntC) + gbase;
             S.scanC = (int64_t*)(w + L.scanC) + gbase;

@@ -49,9 +49,10 @@ struct Shape {
     const float* H;           // H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..d2max
     int64_t* offA; int32_t* cntA;
     int64_t* offI; int32_t* cntI;
-    // seed position (see SEED_SLOT), count, hull (x, y: of the seed chords at
-    // |dy| = 1; z, w: of the seed pieces themselves)
-    int64_t* offB; int32_t* cntB; float4* hullB;
+    // seed position (see SEED_SLOT), count, size of the low group, and two
+    // hulls per column, [2c] low group, [2c + 1] high group (x, y: of the
+    // seed chords at |dy| = 1; z, w: of the seed pieces themselves)
+    int64_t* offB; int32_t* cntB; int32_t* loB; float4* hullB;
     int64_t* offC; int32_t* cntC;
     int64_t* scanC;           // global exclusive scan of the result counts
     // output

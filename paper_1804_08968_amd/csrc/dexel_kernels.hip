@@ -87,7 +87,7 @@ struct OpParams {
     int64_t cap;
     int64_t* offA; int32_t* cntA; float2* A;
     int64_t* offI; int32_t* cntI; float2* I;
-    int64_t* offB; int32_t* cntB; float2* B; uint8_t* tagB; float4* hullB;
+    int64_t* offB; int32_t* cntB; int32_t* loB; float2* B; uint8_t* tagB; float4* hullB;
     int64_t* offC; int32_t* cntC; float2* C;
     float2* arena;
     uint8_t* arena_tag;
@@ -462,10 +462,10 @@ __device__ int64_t k1b_bound(const OpParams& P, int64_t c) {
 // is inside I(c) is not added to the cover list, and the cover list simply
 // stops growing when its capacity is reached: either way the pieces it would
 // hide are then kept whole, which adds valid seeds and changes nothing in
-// the result.  The first `dcap` kept pieces are written at dst/dtag, the
-// hull of the chords at |dy| = 1 of all kept pieces (x, y) and of the pieces
-// themselves (z, w) is accumulated in *hull, and the number of kept pieces is
-// returned.
+// the result.  The kept pieces go to a SeedSink in two groups, below and at
+// or above a split height taken from the middle of I(c): a seed group lies
+// near one end of the union it can change, and its hulls let the y union
+// skip it whole.
 
 // Is [lo, hi] inside I(c)?  A one-interval I is tested from registers.
 template <class Ptr>
@@ -474,23 +474,93 @@ __device__ __forceinline__ bool in_I(Ptr Ip, int ni, float2 i0, float lo, float 
     return in_list(Ip, ni, lo, hi);
 }
 
-__device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, int* np, float2* dst,
-                                        uint8_t* dtag, int dcap, float4* hull) {
-    if (*np < dcap) {
-        gst(&dst[*np], make_float2(p, q));
-        gst(&dtag[*np], (uint8_t)t);
+// Destination of one column's kept pieces.  Group 0: pieces whose centre is
+// below zsplit; group 1: the others.  Slot mode (cap > 0): group 0 fills dlo
+// upwards and group 1 fills dhi downwards, both within cap entries in total.
+// Linear mode (cap == 0): each group fills its own region upwards within
+// cap_lo / cap_hi entries.  Hulls per group: x, y of the chords at |dy| = 1,
+// z, w of the pieces.
+struct SeedSink {
+    float2* dlo;
+    uint8_t* tlo;
+    float2* dhi;
+    uint8_t* thi;
+    int cap, cap_lo, cap_hi;
+    float zsplit;
+    int nlo, nhi;
+    float4 hlo, hhi;
+};
+
+__device__ __forceinline__ SeedSink sink_make(float2* dlo, uint8_t* tlo, float2* dhi, uint8_t* thi,
+                                              int cap, int cap_lo, int cap_hi, float zsplit) {
+    SeedSink o;
+    o.dlo = dlo;
+    o.tlo = tlo;
+    o.dhi = dhi;
+    o.thi = thi;
+    o.cap = cap;
+    o.cap_lo = cap_lo;
+    o.cap_hi = cap_hi;
+    o.zsplit = zsplit;
+    o.nlo = o.nhi = 0;
+    o.hlo = o.hhi = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+    return o;
+}
+
+__device__ __forceinline__ void hull_add(float4* h, float p, float q, float h1) {
+    h->x = fminf(h->x, p - h1);
+    h->y = fmaxf(h->y, q + h1);
+    h->z = fminf(h->z, p);
+    h->w = fmaxf(h->w, q);
+}
+
+__device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, SeedSink& o) {
+    const bool hi = !(0.5f * p + 0.5f * q < o.zsplit);
+    const float2 v = make_float2(p, q);
+    if (o.cap > 0) {
+        if (o.nlo + o.nhi < o.cap) {
+            if (hi) {
+                gst(&o.dhi[-o.nhi], v);
+                gst(&o.thi[-o.nhi], (uint8_t)t);
+            } else {
+                gst(&o.dlo[o.nlo], v);
+                gst(&o.tlo[o.nlo], (uint8_t)t);
+            }
+        }
+    } else if (hi) {
+        if (o.nhi < o.cap_hi) {
+            gst(&o.dhi[o.nhi], v);
+            gst(&o.thi[o.nhi], (uint8_t)t);
+        }
+    } else if (o.nlo < o.cap_lo) {
+        gst(&o.dlo[o.nlo], v);
+        gst(&o.tlo[o.nlo], (uint8_t)t);
     }
-    hull->x = fminf(hull->x, p - h1);
-    hull->y = fmaxf(hull->y, q + h1);
-    hull->z = fminf(hull->z, p);
-    hull->w = fmaxf(hull->w, q);
-    ++*np;
+    if (hi) {
+        hull_add(&o.hhi, p, q, h1);
+        ++o.nhi;
+    } else {
+        hull_add(&o.hlo, p, q, h1);
+        ++o.nlo;
+    }
+}
+
+// Split height of column c: the middle of the finite extent of I(c) (0 if
+// I(c) has no finite endpoint).
+__device__ __forceinline__ float seed_split(const OpParams& P, int64_t c) {
+    const int ni = gld(&P.cntI[c]);
+    if (ni == 0) return 0.0f;
+    const float2* Ip = P.I + gld(&P.offI[c]);
+    const float2 a = gld(&Ip[0]), b = gld(&Ip[ni - 1]);
+    const float lo = (a.x > -DX_INF) ? a.x : a.y;
+    const float hi = (b.y < DX_INF) ? b.y : b.x;
+    if (!(lo > -DX_INF && lo < DX_INF && hi > -DX_INF && hi < DX_INF)) return 0.0f;
+    return 0.5f * lo + 0.5f * hi;
 }
 
 template <class Ptr, class L>
 __device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U, int* n,
-                                           float a, float e, float h1, int t, int* np,
-                                           float2* dst, uint8_t* dtag, int dcap, float4* hull) {
+                                           float a, float e, float h1, int t, SeedSink& o) {
     if (in_I(Ip, ni, i0, a - h1, e + h1)) return;
     // parts of [a, e] not covered by U (closures)
     int idx = lv_lower_hi(U, *n, a);
@@ -500,22 +570,21 @@ __device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U
         const float2 u = U.get(idx);
         if (u.x > e) break;
         if (u.x > p) {
-            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit(p, u.x, h1, t, np, dst, dtag, dcap, hull);
+            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit(p, u.x, h1, t, o);
         }
         if (u.y >= e) { done = true; break; }
         p = fmaxf(p, u.y);
         ++idx;
     }
     if (!done && (p < e || a == e)) {
-        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit(p, e, h1, t, np, dst, dtag, dcap, hull);
+        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit(p, e, h1, t, o);
     }
     const int nn = lv_insert(U, *n, a, e);
     if (nn >= 0) *n = nn;
 }
 
 template <bool E, class L>
-__device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
-                           int dcap, float4* hull) {
+__device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, SeedSink& o) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -525,7 +594,7 @@ __device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, float2* dst
     if (ni == 1) i0 = gld(&Ip[0]);
     const float ilo = ni > 0 ? (ni == 1 ? i0.x : gld(&Ip[0]).x) : 0.f;
     const float ihi = ni > 0 ? (ni == 1 ? i0.y : gld(&Ip[ni - 1]).y) : 0.f;
-    int n = 0, np = 0;
+    int n = 0;
     // visits up to |dx| = tmax (the chord at |dy| = 1 must exist)
     int tmax = P.R;
     while (tmax >= 0 && tmax * tmax + 1 > P.d2max) --tmax;
@@ -590,19 +659,17 @@ __device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, float2* dst
             for (; k < cnt; ++k) {
                 const float2 sg = item(k);
                 if (!(sg.x - h1 < lim)) break;
-                k2_segment(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, &np, dst, dtag, dcap, hull);
+                k2_segment(Ip, ni, i0, U, &n, sg.x, sg.y, h1, t, o);
             }
             next = max(next, k);
         }
     }
-    return np;
+    return o.nlo + o.nhi;
 }
 
 template <class L>
-__device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, uint8_t* dtag,
-                         int dcap, float4* hull) {
-    return P.erode ? k2_column_e<true>(P, c, U, dst, dtag, dcap, hull)
-                   : k2_column_e<false>(P, c, U, dst, dtag, dcap, hull);
+__device__ int k2_column(const OpParams& P, int64_t c, const L& U, SeedSink& o) {
+    return P.erode ? k2_column_e<true>(P, c, U, o) : k2_column_e<false>(P, c, U, o);
 }
 
 // K3: V0(c) plus the chords of the kept seeds of rows y+-dy at weight
@@ -612,18 +679,38 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, float2* dst, 
 // per-lane work then looks up tab[t].  Without TAB the lookups read H.
 // A lane stops adding chords when its list overflows (result -1) but keeps
 // taking part in the staging.
-__device__ __forceinline__ void seed_span(const OpParams& P, int64_t cc, const float2** sp,
-                                          const uint8_t** tp, int* nb) {
+// The two seed groups of column cc (see SeedSink): group g has n[g] seeds at
+// s[g], tags at t[g].  Slot columns hold group 0 at the slot's start and
+// group 1 at its end; arena columns (offset -(pos + 1)) hold group 0 then
+// group 1.
+struct SeedSpans {
+    const float2* s[2];
+    const uint8_t* t[2];
+    int n[2];
+};
+
+__device__ __forceinline__ SeedSpans seed_spans(const OpParams& P, int64_t cc) {
+    SeedSpans r;
     const int64_t ob = gld(&P.offB[cc]);
-    *nb = gld(&P.cntB[cc]);
+    const int cnt = gld(&P.cntB[cc]);
+    const int lo = gld(&P.loB[cc]);
     if (ob >= 0) {
-        *sp = P.B + ob;
-        *tp = P.tagB + ob;
-        *nb = min(*nb, SEED_SLOT);
+        r.n[0] = min(lo, SEED_SLOT);
+        r.n[1] = min(cnt - lo, SEED_SLOT - r.n[0]);
+        r.s[0] = P.B + ob;
+        r.t[0] = P.tagB + ob;
+        r.s[1] = P.B + ob + SEED_SLOT - r.n[1];
+        r.t[1] = P.tagB + ob + SEED_SLOT - r.n[1];
     } else {
-        *sp = P.arena + (-ob - 1);
-        *tp = P.arena_tag + (-ob - 1);
+        const int64_t a = -ob - 1;
+        r.n[0] = lo;
+        r.n[1] = cnt - lo;
+        r.s[0] = P.arena + a;
+        r.t[0] = P.arena_tag + a;
+        r.s[1] = P.arena + a + lo;
+        r.t[1] = P.arena_tag + a + lo;
     }
+    return r;
 }
 
 template <bool TAB, class L>
@@ -662,18 +749,22 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
         }
         if (!ok) continue;
         const float hd = gld(&P.H[dy2]);
-        // the hulls of both seed rows are loaded together
+        // the hulls of both seed groups of both seed rows are loaded together
         const int64_t cl = (int64_t)(y - dy) * P.nx + x, cr = (int64_t)(y + dy) * P.nx + x;
         const float4 none = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
-        const float4 hl = y - dy >= 0 ? gld(&P.hullB[cl]) : none;
-        const float4 hr = y + dy < P.ny ? gld(&P.hullB[cr]) : none;
-        for (int s = 0; s < 2 && ok; ++s) {
-            const int64_t cc = s ? cr : cl;
-            const float4 h4 = s ? hr : hl;
-            // Every chord of this seed column at this dy lies inside its hull
+        float4 hq[4];
+        hq[0] = y - dy >= 0 ? gld(&P.hullB[2 * cl]) : none;
+        hq[1] = y - dy >= 0 ? gld(&P.hullB[2 * cl + 1]) : none;
+        hq[2] = y + dy < P.ny ? gld(&P.hullB[2 * cr]) : none;
+        hq[3] = y + dy < P.ny ? gld(&P.hullB[2 * cr + 1]) : none;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok) break;
+            const float4 h4 = hq[k];
+            // Every chord of this seed group at this dy lies inside its hull
             // at |dy| = 1 and inside its piece hull widened by H[dy^2] (the
-            // widest half-width at this dy); skip the column when the
-            // tighter of the two bounds is inside the union.
+            // widest half-width at this dy); skip the group when the tighter
+            // of the two bounds is inside the union.
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
             if (n <= 2) {
@@ -683,10 +774,10 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
                 const int i = lv_lower_hi(U, n, hhi);
                 if (i < n && U.get(i).x <= hlo) continue;
             }
-            const float2* sp;
-            const uint8_t* tp;
-            int nb;
-            seed_span(P, cc, &sp, &tp, &nb);
+            const SeedSpans sp = seed_spans(P, (k >> 1) ? cr : cl);
+            const float2* sv = sp.s[k & 1];
+            const uint8_t* tv = sp.t[k & 1];
+            const int nb = sp.n[k & 1];
             // seeds in groups of four: the loads of a group are in flight together
             for (int j = 0; j < nb && ok; j += 4) {
                 int tq[4];
@@ -694,8 +785,8 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jj = min(j + q, nb - 1);
-                    tq[q] = gld(&tp[jj]);
-                    pq[q] = gld(&sp[jj]);
+                    tq[q] = gld(&tv[jj]);
+                    pq[q] = gld(&sv[jj]);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -790,13 +881,13 @@ __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
 // kept as two pieces whose chords overlap.
 template <bool E, class Ptr, class L>
 __device__ int k2_slab_e(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni,
-                         const L& U, float2* dst, uint8_t* dtag, int dcap, float4* hull) {
+                         const L& U, SeedSink& o) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
     float2 i0 = make_float2(0.f, 0.f);
     if (ni == 1) i0 = Ip[0];
-    int n = 0, np = 0;
+    int n = 0;
     for (int t = 0; t <= P.R; ++t) {
         const int d2 = t * t + 1;
         if (d2 > P.d2max) break;
@@ -815,19 +906,17 @@ __device__ int k2_slab_e(const OpParams& P, int64_t c, float zs, float ze, Ptr I
             for (int k = l; k < cnt; ++k) {
                 const float2 sg = col_item<E>(P.z, b, m, k);
                 if (sg.x > ze) break;
-                k2_segment(Ip, ni, i0, U, &n, fmaxf(sg.x, zs), fminf(sg.y, ze), h1, t, &np, dst,
-                           dtag, dcap, hull);
+                k2_segment(Ip, ni, i0, U, &n, fmaxf(sg.x, zs), fminf(sg.y, ze), h1, t, o);
             }
         }
     }
-    return np;
+    return o.nlo + o.nhi;
 }
 
 template <class Ptr, class L>
 __device__ int k2_slab(const OpParams& P, int64_t c, float zs, float ze, Ptr Ip, int ni, const L& U,
-                       float2* dst, uint8_t* dtag, int dcap, float4* hull) {
-    return P.erode ? k2_slab_e<true>(P, c, zs, ze, Ip, ni, U, dst, dtag, dcap, hull)
-                   : k2_slab_e<false>(P, c, zs, ze, Ip, ni, U, dst, dtag, dcap, hull);
+                       SeedSink& o) {
+    return P.erode ? k2_slab_e<true>(P, c, zs, ze, Ip, ni, U, o) : k2_slab_e<false>(P, c, zs, ze, Ip, ni, U, o);
 }
 
 // K3 restricted to the slab [zs, ze]: V0(c) and every seed chord clipped to
@@ -873,19 +962,19 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
         if (__all(!busy)) break;
         if (!busy) continue;
         const float hd = tab[0];
-        for (int s = 0; s < 2 && busy; ++s) {
-            const int yy = s ? y + dy : y - dy;
+        for (int k = 0; k < 4 && busy; ++k) {
+            const int yy = (k >> 1) ? y + dy : y - dy;
             if (yy < 0 || yy >= P.ny) continue;
             const int64_t cc = (int64_t)yy * P.nx + x;
-            const float4 h4 = gld(&P.hullB[cc]);
+            const float4 h4 = gld(&P.hullB[2 * cc + (k & 1)]);
             if (h4.x > h4.y) continue;
             const float hlo = fmaxf(fmaxf(h4.x, h4.z - hd), zs);
             const float hhi = fminf(fminf(h4.y, h4.w + hd), ze);
             if (hlo > hhi) continue;
-            const float2* sp;
-            const uint8_t* tp;
-            int nb;
-            seed_span(P, cc, &sp, &tp, &nb);
+            const SeedSpans sp = seed_spans(P, cc);
+            const float2* sv = sp.s[k & 1];
+            const uint8_t* tv = sp.t[k & 1];
+            const int nb = sp.n[k & 1];
             // every lane reads the same seeds: groups of four loads in flight
             for (int j = 0; j < nb && busy; j += 4) {
                 int tq[4];
@@ -893,8 +982,8 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int jj = min(j + q, nb - 1);
-                    tq[q] = gld(&tp[jj]);
-                    pq[q] = gld(&sp[jj]);
+                    tq[q] = gld(&tv[jj]);
+                    pq[q] = gld(&sv[jj]);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -1022,7 +1111,7 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.offA = S.offA; p.cntA = S.cntA; p.A = Q.A;
     p.offI = S.offI; p.cntI = S.cntI; p.I = Q.I;
     p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B;
-    p.tagB = Q.tagB; p.hullB = S.hullB;
+    p.tagB = Q.tagB; p.hullB = S.hullB; p.loB = S.loB;
     p.offC = S.offC; p.cntC = S.cntC; p.C = Q.C;
     p.arena = Q.arena;
     p.arena_tag = Q.arena_tag;
@@ -1177,11 +1266,16 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
             push_overflow(Q, ST_K2, g);
         } else {
             LdsList U{&lds[threadIdx.x], CAP};
-            float4 hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
-            np = k2_column(P, pl.c, U, P.B + g * SEED_SLOT, P.tagB + g * SEED_SLOT, SEED_SLOT, &hull);
+            float2* slot = P.B + g * SEED_SLOT;
+            uint8_t* tslot = P.tagB + g * SEED_SLOT;
+            SeedSink o = sink_make(slot, tslot, slot + SEED_SLOT - 1, tslot + SEED_SLOT - 1, SEED_SLOT,
+                                   0, 0, seed_split(P, pl.c));
+            np = k2_column(P, pl.c, U, o);
             gst(&P.offB[pl.c], g * SEED_SLOT);
             gst(&P.cntB[pl.c], np);
-            gst(&P.hullB[pl.c], hull);
+            gst(&P.loB[pl.c], o.nlo);
+            gst(&P.hullB[2 * pl.c], o.hlo);
+            gst(&P.hullB[2 * pl.c + 1], o.hhi);
             if (np > SEED_SLOT) {
                 push_overflow(Q, ST_K2, g);
                 np = 0;  // counted by the replay
@@ -1236,26 +1330,38 @@ __global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
         zmax = wave_max(zmax);
         const float2 sl = lane_slab(zmin, zmax);
         LdsList U{&lds[lane], CAP};
-        float4 hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
-        const int np = k2_slab(P, c, sl.x, sl.y, Ip, ni, U, nullptr, nullptr, 0, &hull);
-        int tot;
-        const int pre = wave_excl_scan(np, &tot);
+        const float zsplit = seed_split(P, c);
+        SeedSink o = sink_make(nullptr, nullptr, nullptr, nullptr, 0, 0, 0, zsplit);
+        k2_slab(P, c, sl.x, sl.y, Ip, ni, U, o);
+        const int nlo = o.nlo, nhi = o.nhi;
+        int totlo, tothi;
+        const int prelo = wave_excl_scan(nlo, &totlo);
+        const int prehi = wave_excl_scan(nhi, &tothi);
+        const int tot = totlo + tothi;
         int64_t pos = 0;
         if (lane == 0) pos = arena_alloc(P, tot);
         pos = __shfl(pos, 0, 64);
         if (pos < 0) continue;  // keep counting the arena demand
-        hull = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
-        const int np2 = k2_slab(P, c, sl.x, sl.y, Ip, ni, U, P.arena + pos + pre,
-                                P.arena_tag + pos + pre, np, &hull);
-        if (np2 != np) set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
-        hull.x = wave_min(hull.x);
-        hull.y = wave_max(hull.y);
-        hull.z = wave_min(hull.z);
-        hull.w = wave_max(hull.w);
+        const int64_t plo = pos + prelo, phi = pos + totlo + prehi;
+        SeedSink o2 = sink_make(P.arena + plo, P.arena_tag + plo, P.arena + phi, P.arena_tag + phi, 0,
+                                nlo, nhi, zsplit);
+        k2_slab(P, c, sl.x, sl.y, Ip, ni, U, o2);
+        if (o2.nlo != nlo || o2.nhi != nhi) set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+        float4 hlo = o2.hlo, hhi = o2.hhi;
+        hlo.x = wave_min(hlo.x);
+        hlo.y = wave_max(hlo.y);
+        hlo.z = wave_min(hlo.z);
+        hlo.w = wave_max(hlo.w);
+        hhi.x = wave_min(hhi.x);
+        hhi.y = wave_max(hhi.y);
+        hhi.z = wave_min(hhi.z);
+        hhi.w = wave_max(hhi.w);
         if (lane == 0) {
             P.offB[c] = -(pos + 1);
             P.cntB[c] = tot;
-            P.hullB[c] = hull;
+            P.loB[c] = totlo;
+            P.hullB[2 * c] = hlo;
+            P.hullB[2 * c + 1] = hhi;
             atomicAdd(&Q.hdr->nseeds, (unsigned long long)tot);
         }
     }
@@ -1308,10 +1414,10 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
             float2 acc = make_float2(DX_INF, -DX_INF);
             for (int dy = P.R; dy >= 1; --dy) {
                 const float hd = gld(&P.H[dy * dy]);
-                for (int sd = 0; sd < 2; ++sd) {
-                    const int yy = sd ? y + dy : y - dy;
+                for (int k = 0; k < 4; ++k) {
+                    const int yy = (k >> 1) ? y + dy : y - dy;
                     if (yy < 0 || yy >= P.ny) continue;
-                    const float4 h4 = gld(&P.hullB[(int64_t)yy * P.nx + x]);
+                    const float4 h4 = gld(&P.hullB[2 * ((int64_t)yy * P.nx + x) + (k & 1)]);
                     if (h4.x > h4.y) continue;
                     acc.x = fminf(acc.x, fmaxf(h4.x, h4.z - hd));
                     acc.y = fmaxf(acc.y, fminf(h4.y, h4.w + hd));
