@@ -32,6 +32,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1804_08968_amd", "csrc", "dexel_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_close_r16_hbm_traffic.txt")
+
+
+def kernels_sha256():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, each counter scaled by what it reads for a plain copy of
+    known size; None if there is no summary for the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals, rows = {}, {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            if parts[0] == "kernel" and len(parts) >= 4:
+                rows[parts[1]] = (float(parts[2]), float(parts[3]))
+            elif len(parts) == 2:
+                vals[parts[0]] = parts[1]
+    if vals.get("kernels_source_sha256") != kernels_sha256() or kernel not in rows:
+        return None
+    copy_bytes = float(vals["copy_bytes"])
+    f_scale = copy_bytes / (float(vals["copy_fetch_kib"]) * 1024.0)
+    w_scale = copy_bytes / (float(vals["copy_write_kib"]) * 1024.0)
+    fetch_kib, write_kib = rows[kernel]
+    return (fetch_kib * f_scale + write_kib * w_scale) * 1024.0
 
 WORKLOADS = {
     "c3": dict(desc="closing r=16 of a 2048x2048 gyroid lattice (period 64, wall ~3 voxels, "
@@ -325,8 +359,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="first run one device-to-device copy of this many MiB (a plain copy "
-                         "kernel of known size, the reference for HBM byte counters)")
+                    help="first run one elementwise kernel over this many MiB (reads and writes "
+                         "a known number of bytes: the reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the offset of one "
@@ -337,13 +371,16 @@ def main():
     import paper_1804_08968_amd as dx
 
     if args.calibrate_copy > 0:
+        # an elementwise kernel that reads nb bytes and writes nb bytes
+        # (a device-to-device copy_ may go to a DMA engine, not a kernel)
         nb = args.calibrate_copy << 20
         src = torch.ones(nb, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.add(src, 1, out=dst)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy of {nb} bytes", file=sys.stderr, flush=True)
+        print(f"[bench] calibration kernel: {nb} bytes read, {nb} bytes written", file=sys.stderr,
+              flush=True)
         del src, dst
 
     if args.workload == "c4":
@@ -408,10 +445,13 @@ def main():
         tot_bytes += b if b is not None else 0
     bytes_per_launch = tot_bytes / max(1, len(pass_stats))
     achieved = bytes_per_launch / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+    kname = dx.PROFILE_KERNELS[stages.index(dom)]
+    traffic = measured_traffic(kname) if args.workload == "c3" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": dx.PROFILE_KERNELS[stages.index(dom)],
-                "kernel_ms": round(dom_ms, 4), "bytes_per_launch": int(bytes_per_launch)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": int(traffic) if traffic is not None else None,
+                "kernel": kname, "kernel_ms": round(dom_ms, 4),
+                "bytes_per_launch": int(bytes_per_launch)}
 
     line = {
         "metric": "input dexel segments offset/sec",
