@@ -876,6 +876,49 @@ __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
     }
 }
 
+// K1b restricted to the slab [zs, ze]: starts from the slab itself and
+// intersects it with V0 of the rows y+-1 .. y+-R, visiting only the V0
+// intervals that reach the slab.  Two lists, result in *res.
+template <class L>
+__device__ int k1b_slab(const OpParams& P, int64_t c, float zs, float ze, const L& L0, const L& L1,
+                        int* res) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    L0.set(0, make_float2(zs, ze));
+    int n = 1, cur = 0;
+    for (int dy = 1; dy <= P.R && n > 0; ++dy) {
+        for (int s = 0; s < 2 && n > 0; ++s) {
+            const int yy = s ? y + dy : y - dy;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            const float2* J = P.A + gld(&P.offA[cc]);
+            const int m = gld(&P.cntA[cc]);
+            int j = 0, hh = m;  // first V0 interval ending at or above zs
+            while (j < hh) {
+                const int mid = (j + hh) >> 1;
+                if (gld(&J[mid]).y < zs) j = mid + 1; else hh = mid;
+            }
+            const L& S = cur ? L1 : L0;
+            const L& D = cur ? L0 : L1;
+            int i = 0, k = 0;
+            while (i < n && j < m) {
+                const float2 a = S.get(i), bb = gld(&J[j]);
+                if (bb.x > ze) break;
+                const float lo = fmaxf(a.x, bb.x), hi = fminf(a.y, bb.y);
+                if (lo < hi) {
+                    if (k >= D.cap) return -1;
+                    D.set(k++, make_float2(lo, hi));
+                }
+                if (a.y < bb.y) ++i; else ++j;
+            }
+            n = k;
+            cur ^= 1;
+        }
+    }
+    *res = cur;
+    return n;
+}
+
 // K2 restricted to the slab [zs, ze]: the input items of the row window are
 // clipped to the slab before painting, so a piece cut at a slab boundary is
 // kept as two pieces whose chords overlap.
@@ -1205,12 +1248,15 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
-    bool valid = pl.valid;
+    // a column whose own V0 is fragmented (its neighbours' are too, as a
+    // rule) goes straight to the replay
+    const bool defer = pl.valid && gld(&P.cntA[pl.c]) > K3_DEFER_N;
+    bool valid = pl.valid && !defer;
     LdsList L0{&lds[threadIdx.x], CAP};
     LdsList L1{&lds[CAP * WG + threadIdx.x], CAP};
     int res = 0;
     int n = valid ? k1b_column(P, pl.c, L0, L1, &res) : 0;
-    if (n < 0) {
+    if (n < 0 || defer) {
         push_overflow(Q, ST_K1B, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
@@ -1218,34 +1264,80 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     emit_wave(P, pl.c, valid, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
 }
 
+// Replay of K1b: one wave per column, one z-slab per lane; lane 0 stitches
+// the slab lists (intervals cut at a slab boundary touch there) into an arena
+// list and emits it.  If a slab list overflows, lane 0 evaluates the column
+// alone with arena lists sized from an upper bound.
 __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
-    __shared__ float2 lds[CAP_FB * WG];
+    __shared__ float2 lds[2 * CAP_Z * WG];
+    __shared__ int nsh[WG];
+    __shared__ int rsh[WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K1B];
-    for (int i = threadIdx.x * gridDim.x + blockIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + i];
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + e];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
-        {
-            LdsList L0{&lds[threadIdx.x], CAP_FB / 2};
-            LdsList L1{&lds[(CAP_FB / 2) * WG + threadIdx.x], CAP_FB / 2};
-            int res = 0;
-            const int n = k1b_column(P, c, L0, L1, &res);
-            if (n >= 0) {
-                emit_lane(P, c, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
-                continue;
+        int x, y;
+        col_xy(P, c, &x, &y);
+        // finite z range of V0 over the rows y+-1 .. y+-R
+        float zmin = DX_INF, zmax = -DX_INF;
+        for (int j = lane; j < 2 * P.R; j += WG) {
+            const int yy = (j & 1) ? y + (j >> 1) + 1 : y - (j >> 1) - 1;
+            if (yy < 0 || yy >= P.ny) continue;
+            const int64_t cc = (int64_t)yy * P.nx + x;
+            const int m = gld(&P.cntA[cc]);
+            if (m == 0) continue;
+            const float2* J = P.A + gld(&P.offA[cc]);
+            const float2 f = gld(&J[0]), l = gld(&J[m - 1]);
+            widen(&zmin, &zmax, f.x);
+            widen(&zmin, &zmax, f.y);
+            widen(&zmin, &zmax, l.x);
+            widen(&zmin, &zmax, l.y);
+        }
+        zmin = wave_min(zmin);
+        zmax = wave_max(zmax);
+        const float2 sl = lane_slab(zmin, zmax);
+        LdsList L0{&lds[lane], CAP_Z};
+        LdsList L1{&lds[CAP_Z * WG + lane], CAP_Z};
+        int res = 0;
+        const int n = k1b_slab(P, c, sl.x, sl.y, L0, L1, &res);
+        __syncthreads();  // the previous column's stitch has read nsh, rsh and lds
+        nsh[lane] = n;
+        rsh[lane] = res;
+        __syncthreads();
+        const bool fail = __any(n < 0);
+        if (lane != 0) continue;
+        if (fail) {
+            const int64_t bound = k1b_bound(P, c);
+            const int64_t pos = arena_alloc(P, 2 * bound);
+            if (pos < 0) continue;  // keep counting the arena demand
+            const int cap = (int)min<int64_t>(bound, 0x7fffffff);
+            MemList M0{(float2*)(P.arena + pos), cap}, M1{P.arena + pos + bound, cap};
+            int r2 = 0;
+            const int nn = k1b_column(P, c, M0, M1, &r2);
+            if (nn < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); continue; }
+            emit_lane(P, c, r2 ? M1 : M0, nn, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+            continue;
+        }
+        int64_t tot = 0;
+        for (int l = 0; l < WG; ++l) tot += nsh[l];
+        const int64_t pos = arena_alloc(P, tot > 0 ? tot : 1);
+        if (pos < 0) continue;
+        float2* out = P.arena + pos;
+        int k = 0;
+        for (int l = 0; l < WG; ++l) {
+            const int base = rsh[l] ? CAP_Z * WG : 0;
+            for (int i = 0; i < nsh[l]; ++i) {
+                const float2 v = lds[base + i * WG + l];
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                else out[k++] = v;
             }
         }
-        const int64_t bound = k1b_bound(P, c);
-        const int64_t pos = arena_alloc(P, 2 * bound);
-        if (pos < 0) continue;  // keep counting the arena demand
-        const int cap = (int)min<int64_t>(bound, 0x7fffffff);
-        MemList L0{(float2*)(P.arena + pos), cap}, L1{P.arena + pos + bound, cap};
-        int res = 0;
-        const int n = k1b_column(P, c, L0, L1, &res);
-        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+        MemList M{out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
+        emit_lane(P, c, M, k, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
     }
 }
 
