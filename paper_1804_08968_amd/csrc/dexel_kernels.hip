@@ -103,6 +103,9 @@ constexpr int CAP_FB = 128;  // LDS list capacity of the replay kernels' first t
 // this, K3 when V0(c) has; CAP_Z is the per-lane list capacity of the z-slab
 // replays.
 constexpr int K2_DEFER_NI = 8;
+// Entries (float2) after the seeds of a replayed column: slab range and the
+// per-slab offsets of both groups (2 x 65 int32).
+constexpr int SEED_META = 1 + 65;
 constexpr int K3_DEFER_N = 8;
 constexpr int CAP_Z = 32;
 
@@ -860,13 +863,23 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // Slab of this lane for data spanning [zmin, zmax] (zmin > zmax: no finite data).
+// Boundary b_k (k = 0 .. 64) of the slabs over [zmin, zmax] (already
+// normalised: zmin <= zmax).
+__device__ __forceinline__ float slab_bound(float zmin, float zmax, int k) {
+    if (k <= 0) return -DX_INF;
+    if (k >= 64) return DX_INF;
+    return zmin + (zmax - zmin) * ((float)k * (1.0f / 64.0f));
+}
+
+__device__ __forceinline__ float2 slab_range(float zmin, float zmax) {
+    if (!(zmin <= zmax)) zmin = zmax = 0.0f;
+    return make_float2(zmin, zmax);
+}
+
 __device__ __forceinline__ float2 lane_slab(float zmin, float zmax) {
     const int l = threadIdx.x & 63;
-    if (!(zmin <= zmax)) zmin = zmax = 0.0f;
-    const float w = zmax - zmin;
-    const float lo = l == 0 ? -DX_INF : zmin + w * ((float)l * (1.0f / 64.0f));
-    const float hi = l == 63 ? DX_INF : zmin + w * ((float)(l + 1) * (1.0f / 64.0f));
-    return make_float2(lo, hi);
+    const float2 r = slab_range(zmin, zmax);
+    return make_float2(slab_bound(r.x, r.y, l), slab_bound(r.x, r.y, l + 1));
 }
 
 __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
@@ -1017,9 +1030,33 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const SeedSpans sp = seed_spans(P, cc);
             const float2* sv = sp.s[k & 1];
             const uint8_t* tv = sp.t[k & 1];
-            const int nb = sp.n[k & 1];
+            int j0 = 0, nb = sp.n[k & 1];
+            const int64_t ob = gld(&P.offB[cc]);
+            if (ob < 0) {
+                // a replayed seed column is ordered by its own slabs: scan only
+                // the slabs whose chords can reach [zs, ze]
+                const int64_t a = -ob - 1;
+                const float2* meta = P.arena + a + gld(&P.cntB[cc]);
+                const float2 rg = gld(&meta[0]);
+                const int* off = (const int*)(meta + 1) + 65 * (k & 1);
+                int lo = 0, hi = 63;  // first slab whose top + hd reaches zs
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (slab_bound(rg.x, rg.y, mid + 1) + hd >= zs) hi = mid; else lo = mid + 1;
+                }
+                const int k0 = lo;
+                lo = k0;
+                hi = 63;  // last slab whose bottom - hd is at most ze
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (slab_bound(rg.x, rg.y, mid) - hd <= ze) lo = mid; else hi = mid - 1;
+                }
+                const int k1 = lo;
+                j0 = gld(&off[k0]);
+                nb = gld(&off[k1 + 1]);
+            }
             // every lane reads the same seeds: groups of four loads in flight
-            for (int j = 0; j < nb && busy; j += 4) {
+            for (int j = j0; j < nb && busy; j += 4) {
                 int tq[4];
                 float2 pq[4];
 #pragma unroll
@@ -1431,9 +1468,22 @@ __global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
         const int prehi = wave_excl_scan(nhi, &tothi);
         const int tot = totlo + tothi;
         int64_t pos = 0;
-        if (lane == 0) pos = arena_alloc(P, tot);
+        if (lane == 0) pos = arena_alloc(P, tot + SEED_META);
         pos = __shfl(pos, 0, 64);
         if (pos < 0) continue;  // keep counting the arena demand
+        // after the seeds: the slab range, then the first seed of every
+        // slab in each group (relative to the group's start)
+        {
+            float2* meta = P.arena + pos + tot;
+            int* off = (int*)(meta + 1);
+            if (lane == 0) {
+                meta[0] = slab_range(zmin, zmax);
+                off[64] = totlo;
+                off[65 + 64] = tothi;
+            }
+            off[lane] = prelo;
+            off[65 + lane] = prehi;
+        }
         const int64_t plo = pos + prelo, phi = pos + totlo + prehi;
         SeedSink o2 = sink_make(P.arena + plo, P.arena_tag + plo, P.arena + phi, P.arena_tag + phi, 0,
                                 nlo, nhi, zsplit);
