@@ -24,7 +24,9 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
-enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3, NSTAGE = 4 };
+// Overflow lists: K1, K1b and K3 replays, K2 seed lists longer than the slot
+// (ST_K2) and K2 columns deferred as heavy (ST_K2H).
+enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3, ST_K2H = 4, NSTAGE = 5 };
 
 // Seed slots per column: the seeds of a column are written at
 // B[g * SEED_SLOT ...] (g = global column); a column with more seeds is

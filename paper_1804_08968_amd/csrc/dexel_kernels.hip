@@ -682,6 +682,10 @@ __device__ int k2_column(const OpParams& P, int64_t c, const L& U, SeedSink& o) 
 // per-lane work then looks up tab[t].  Without TAB the lookups read H.
 // A lane stops adding chords when its list overflows (result -1) but keeps
 // taking part in the staging.
+// Size of the low seed group from loB: a column whose seeds the slab replay
+// wrote (ordered by slab, with the slab index after them) stores ~size.
+__device__ __forceinline__ int seed_lo(int v) { return v < 0 ? ~v : v; }
+
 // The two seed groups of column cc (see SeedSink): group g has n[g] seeds at
 // s[g], tags at t[g].  Slot columns hold group 0 at the slot's start and
 // group 1 at its end; arena columns (offset -(pos + 1)) hold group 0 then
@@ -696,7 +700,7 @@ __device__ __forceinline__ SeedSpans seed_spans(const OpParams& P, int64_t cc) {
     SeedSpans r;
     const int64_t ob = gld(&P.offB[cc]);
     const int cnt = gld(&P.cntB[cc]);
-    const int lo = gld(&P.loB[cc]);
+    const int lo = seed_lo(gld(&P.loB[cc]));
     if (ob >= 0) {
         r.n[0] = min(lo, SEED_SLOT);
         r.n[1] = min(cnt - lo, SEED_SLOT - r.n[0]);
@@ -1032,7 +1036,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const uint8_t* tv = sp.t[k & 1];
             int j0 = 0, nb = sp.n[k & 1];
             const int64_t ob = gld(&P.offB[cc]);
-            if (ob < 0) {
+            if (ob < 0 && gld(&P.loB[cc]) < 0) {
                 // a replayed seed column is ordered by its own slabs: scan only
                 // the slabs whose chords can reach [zs, ze]
                 const int64_t a = -ob - 1;
@@ -1392,7 +1396,7 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
         const int64_t g = pl.g0 + threadIdx.x;
         if (gld(&P.cntI[pl.c]) > K2_DEFER_NI) {
             P.cntB[pl.c] = 0;
-            push_overflow(Q, ST_K2, g);
+            push_overflow(Q, ST_K2H, g);
         } else {
             LdsList U{&lds[threadIdx.x], CAP};
             float2* slot = P.B + g * SEED_SLOT;
@@ -1405,10 +1409,7 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
             gst(&P.loB[pl.c], o.nlo);
             gst(&P.hullB[2 * pl.c], o.hlo);
             gst(&P.hullB[2 * pl.c + 1], o.hhi);
-            if (np > SEED_SLOT) {
-                push_overflow(Q, ST_K2, g);
-                np = 0;  // counted by the replay
-            }
+            if (np > SEED_SLOT) push_overflow(Q, ST_K2, g);
         }
     }
     int tot;
@@ -1416,20 +1417,51 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     if ((threadIdx.x & 63) == 0 && tot > 0) atomicAdd(&Q.hdr->nseeds, (unsigned long long)tot);
 }
 
-// Replay of K2 for the deferred and overflowing columns: one wave per column,
+// Replay of K2 for columns with more seeds than a slot: one lane per column,
+// the same cover capacity (so the same seeds), written to the arena in one
+// allocation of the count the first traversal found.
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
+    __shared__ float2 lds[CAP * WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K2];
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if ((int64_t)blockIdx.x * WG >= cnt) return;  // whole block past the list
+    if (i >= cnt) return;
+    const int64_t g = Q.ovf[(int64_t)ST_K2 * Q.gcols + i];
+    const int s = find_shape(Q, g);
+    const OpParams P = make_op(Q, Q.shapes[s]);
+    const int64_t c = g - Q.sbase[s];
+    const int want = gld(&P.cntB[c]);
+    const int lo = gld(&P.loB[c]);
+    const int64_t pos = arena_alloc(P, want);
+    if (pos < 0) return;  // the arena demand is counted
+    LdsList U{&lds[threadIdx.x], CAP};
+    float2* d = P.arena + pos;
+    uint8_t* t = P.arena_tag + pos;
+    SeedSink o = sink_make(d, t, d + lo, t + lo, 0, lo, want - lo, seed_split(P, c));
+    const int np = k2_column(P, c, U, o);
+    if (np != want || o.nlo != lo) {
+        set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+        return;
+    }
+    P.offB[c] = -(pos + 1);
+}
+
+// Replay of K2 for the columns deferred as heavy: one wave per column,
 // one z-slab per lane (count, wave scan, one arena allocation, fill).  I(c)
 // is staged in LDS when it fits.
 constexpr int ISH = 512;
 
 template <int CAP>
-__global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
+__global__ void __launch_bounds__(WG) k_seeds_heavy(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     __shared__ float2 ish[ISH];
     if (Q.hdr->abort) return;
-    const int cnt = Q.hdr->novf[ST_K2];
+    const int cnt = Q.hdr->novf[ST_K2H];
     const int lane = threadIdx.x;
     for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
-        const int64_t g = Q.ovf[(int64_t)ST_K2 * Q.gcols + e];
+        const int64_t g = Q.ovf[(int64_t)ST_K2H * Q.gcols + e];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
@@ -1501,7 +1533,7 @@ __global__ void __launch_bounds__(WG) k_seeds_fb(Pass Q) {
         if (lane == 0) {
             P.offB[c] = -(pos + 1);
             P.cntB[c] = tot;
-            P.loB[c] = totlo;
+            P.loB[c] = ~totlo;
             P.hullB[2 * c] = hlo;
             P.hullB[2 * c + 1] = hhi;
             atomicAdd(&Q.hdr->nseeds, (unsigned long long)tot);
@@ -1876,7 +1908,8 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(4);
     hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(5);
-    hipLaunchKernelGGL(k_seeds_fb<C2>, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
     DX_MARK(6);
     DX_MARK(7);
     DX_MARK(8);
