@@ -271,50 +271,44 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
         const float2 it = col_item<E>(P.z, b, m, k);
         return make_float2(it.x - h, it.y + h);
     };
-    // heads: u0, u1 of the list (valid while i < n, i + 1 < n), c0, c1 of
-    // the chords; reads past the end are clamped to the last entry
+    // Each stream keeps two heads (u0, u1 / c0, c1) and one element in
+    // flight (pu / pc), reloaded every step from clamped indices, so that the
+    // step is branch-free and every load has a whole step to arrive.  Reads
+    // past the end of a stream return a value that is never used.
     const int nl = n > 0 ? n - 1 : 0, cl = cnt - 1;
-    float2 u0 = make_float2(0.f, 0.f), u1 = u0;
-    if (n > 0) {
-        u0 = U.get(top);
-        u1 = U.get(top + min(1, nl));
-    }
-    float2 c0 = chord(0), c1 = chord(min(1, cl));
+    const float2 zero = make_float2(0.f, 0.f);
+    float2 u0 = n > 0 ? U.get(top) : zero;
+    float2 u1 = n > 0 ? U.get(top + min(1, nl)) : zero;
+    float2 pu = n > 0 ? U.get(top + min(2, nl)) : zero;
+    float2 c0 = chord(0), c1 = chord(min(1, cl)), pc = chord(min(2, cl));
     int i = 0, j = 0, k = 0;
-    // the first interval in start order opens the output
-    float2 cur;
-    if (n > 0 && u0.x <= c0.x) {
-        cur = u0;
-        u0 = u1;
-        ++i;
-        if (i < n) u1 = U.get(top + min(i + 1, nl));
-    } else {
-        cur = c0;
-        c0 = c1;
-        ++j;
-        if (j < cnt) c1 = chord(min(j + 1, cl));
-    }
+    bool first = true, bad = false;
+    float2 cur = zero;
     while (i < n || j < cnt) {
         const bool takeU = j >= cnt || (i < n && u0.x <= c0.x);
         const float2 v = takeU ? u0 : c0;
-        if (takeU) {
-            u0 = u1;
-            ++i;
-            u1 = U.get(top + min(i + 1, nl));
-        } else {
-            c0 = c1;
-            ++j;
-            c1 = chord(min(j + 1, cl));
+        u0 = takeU ? u1 : u0;
+        u1 = takeU ? pu : u1;
+        c0 = takeU ? c0 : c1;
+        c1 = takeU ? c1 : pc;
+        i += takeU ? 1 : 0;
+        j += takeU ? 0 : 1;
+        if (n > 0) pu = U.get(top + min(i + 2, nl));
+        pc = chord(min(j + 2, cl));
+        // v extends the open interval, or closes it and opens the next
+        const bool extend = !first && v.x <= cur.y;
+        if (!extend && !first) {
+            if (k > top + i || k >= U.cap) {
+                bad = true;
+                break;
+            }
+            U.set(k, cur);
+            ++k;
         }
-        if (v.x <= cur.y) {
-            cur.y = fmaxf(cur.y, v.y);
-        } else {
-            if (k > top + i || k >= U.cap) return -1;
-            U.set(k++, cur);
-            cur = v;
-        }
+        cur = extend ? make_float2(cur.x, fmaxf(cur.y, v.y)) : v;
+        first = false;
     }
-    if (k >= U.cap) return -1;
+    if (bad || k >= U.cap) return -1;
     U.set(k++, cur);
     return k;
 }
