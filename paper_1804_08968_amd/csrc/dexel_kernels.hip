@@ -265,48 +265,49 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // merge step to arrive.
 template <bool E, class L>
 __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int m, int cnt, float h) {
-    const int top = U.cap - n;
+    const int top = U.cap - n, last = U.cap - 1;
     for (int i = n - 1; i >= 0; --i) U.set(top + i, U.get(i));
     auto chord = [&](int k) {
         const float2 it = col_item<E>(P.z, b, m, k);
         return make_float2(it.x - h, it.y + h);
     };
     // Each stream keeps two heads (u0, u1 / c0, c1) and one element in
-    // flight (pu / pc), reloaded every step from clamped indices, so that the
-    // step is branch-free and every load has a whole step to arrive.  Reads
-    // past the end of a stream return a value that is never used.
-    const int nl = n > 0 ? n - 1 : 0, cl = cnt - 1;
-    const float2 zero = make_float2(0.f, 0.f);
-    float2 u0 = n > 0 ? U.get(top) : zero;
-    float2 u1 = n > 0 ? U.get(top + min(1, nl)) : zero;
-    float2 pu = n > 0 ? U.get(top + min(2, nl)) : zero;
+    // flight (pu / pc), reloaded every step from clamped indices, so that a
+    // step has no branch but the one that closes an output interval, and
+    // every load has a whole step to arrive.  Reads past the end of a stream
+    // return values that are never used.  Every step consumes one element,
+    // so the loop runs n + cnt - 1 times after the first.
+    const int cl = cnt - 1;
+    float2 u0 = U.get(min(top, last)), u1 = U.get(min(top + 1, last)), pu = U.get(min(top + 2, last));
     float2 c0 = chord(0), c1 = chord(min(1, cl)), pc = chord(min(2, cl));
     int i = 0, j = 0, k = 0;
-    bool first = true, bad = false;
-    float2 cur = zero;
-    while (i < n || j < cnt) {
-        const bool takeU = j >= cnt || (i < n && u0.x <= c0.x);
-        const float2 v = takeU ? u0 : c0;
+    bool bad = false;
+    auto advance = [&](bool takeU) {
         u0 = takeU ? u1 : u0;
         u1 = takeU ? pu : u1;
         c0 = takeU ? c0 : c1;
         c1 = takeU ? c1 : pc;
         i += takeU ? 1 : 0;
         j += takeU ? 0 : 1;
-        if (n > 0) pu = U.get(top + min(i + 2, nl));
+        pu = U.get(min(top + i + 2, last));
         pc = chord(min(j + 2, cl));
-        // v extends the open interval, or closes it and opens the next
-        const bool extend = !first && v.x <= cur.y;
-        if (!extend && !first) {
-            if (k > top + i || k >= U.cap) {
-                bad = true;
-                break;
-            }
-            U.set(k, cur);
+    };
+    bool takeU = n > 0 && u0.x <= c0.x;
+    float2 cur = takeU ? u0 : c0;
+    advance(takeU);
+    for (int step = n + cnt - 1; step > 0; --step) {
+        takeU = j >= cnt || (i < n && u0.x <= c0.x);
+        const float2 v = takeU ? u0 : c0;
+        advance(takeU);
+        // v extends the open interval, or closes it and opens the next; a
+        // write may take the slot of an entry already read, never one still
+        // to be read
+        const bool close = !(v.x <= cur.y);
+        if (close) {
+            if (k <= top + i && k < U.cap) U.set(k, cur); else bad = true;
             ++k;
         }
-        cur = extend ? make_float2(cur.x, fmaxf(cur.y, v.y)) : v;
-        first = false;
+        cur = close ? v : make_float2(cur.x, fmaxf(cur.y, v.y));
     }
     if (bad || k >= U.cap) return -1;
     U.set(k++, cur);
