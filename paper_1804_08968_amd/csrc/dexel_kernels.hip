@@ -792,28 +792,27 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    if (j + q >= nb) break;
+                    // one branch per seed: most chords are inside the union
                     const int t = tq[q];
                     float h;
                     if (TAB) {
                         h = tab[t];
-                        if (h < 0.0f) continue;
                     } else {
                         const int d2 = t * t + dy2;
-                        if (d2 > P.d2max) continue;
-                        h = gld(&P.H[d2]);
+                        h = d2 <= P.d2max ? gld(&P.H[d2]) : -1.0f;
                     }
                     const float lo = pq[q].x - h, hi = pq[q].y + h;
-                    if (n >= 1 && n <= 2 && u0.x <= lo && hi <= u0.y) continue;
-                    if (n == 2 && u1.x <= lo && hi <= u1.y) continue;
-                    n = lv_insert(U, n, lo, hi);
-                    if (n < 0) {
-                        ok = false;
-                        break;
-                    }
-                    if (n <= 2) {
-                        u0 = U.get(0);
-                        if (n == 2) u1 = U.get(1);
+                    const bool inside = (n >= 1 && n <= 2 && u0.x <= lo && hi <= u0.y) ||
+                                        (n == 2 && u1.x <= lo && hi <= u1.y);
+                    if (ok && j + q < nb && h >= 0.0f && !inside) {
+                        n = lv_insert(U, n, lo, hi);
+                        if (n < 0) {
+                            ok = false;
+                            n = 0;
+                        } else if (n <= 2) {
+                            u0 = U.get(0);
+                            if (n == 2) u1 = U.get(1);
+                        }
                     }
                 }
             }
