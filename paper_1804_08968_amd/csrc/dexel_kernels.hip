@@ -560,22 +560,32 @@ template <class Ptr, class L>
 __device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U, int* n,
                                            float a, float e, float h1, int t, SeedSink& o) {
     if (in_I(Ip, ni, i0, a - h1, e + h1)) return;
-    // parts of [a, e] not covered by U (closures)
+    // parts of [a, e] not covered by U (closures): one candidate piece per
+    // step, [p, q], ending at the next cover interval or at e
     int idx = lv_lower_hi(U, *n, a);
     float p = a;
-    bool done = false;
-    while (idx < *n) {
-        const float2 u = U.get(idx);
-        if (u.x > e) break;
-        if (u.x > p) {
-            if (!in_I(Ip, ni, i0, p - h1, u.x + h1)) k2_emit(p, u.x, h1, t, o);
+    bool more = true;
+    while (more) {
+        float q = e, pn = p;
+        bool cand;
+        if (idx < *n) {
+            const float2 u = U.get(idx);
+            if (u.x > e) {
+                cand = p < e || a == e;
+                more = false;
+            } else {
+                q = u.x;
+                cand = u.x > p;
+                more = u.y < e;
+                pn = fmaxf(p, u.y);
+                ++idx;
+            }
+        } else {
+            cand = p < e || a == e;
+            more = false;
         }
-        if (u.y >= e) { done = true; break; }
-        p = fmaxf(p, u.y);
-        ++idx;
-    }
-    if (!done && (p < e || a == e)) {
-        if (!in_I(Ip, ni, i0, p - h1, e + h1)) k2_emit(p, e, h1, t, o);
+        if (cand && !in_I(Ip, ni, i0, p - h1, q + h1)) k2_emit(p, q, h1, t, o);
+        p = pn;
     }
     const int nn = lv_insert(U, *n, a, e);
     if (nn >= 0) *n = nn;
