@@ -24,9 +24,13 @@ struct WsHeader {
 };
 static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
-// Overflow lists: K1, K1b and K3 replays, K2 seed lists longer than the slot
-// (ST_K2) and K2 columns deferred as heavy (ST_K2H).
-enum Stage { ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3, ST_K2H = 4, NSTAGE = 5 };
+// Overflow lists: columns whose per-lane list overflowed in K1, K1b, K2 (seed
+// slot) and K3, replayed one lane per column; and columns deferred as heavy
+// in K2, K1b and K3, replayed one wave per column (z slabs).
+enum Stage {
+    ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3,
+    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, NSTAGE = 7
+};
 
 // Seed slots per column: the seeds of a column are written at
 // B[g * SEED_SLOT ...] (g = global column); a column with more seeds is

@@ -102,11 +102,12 @@ constexpr int CAP_FB = 128;  // LDS list capacity of the replay kernels' first t
 // K2 defers a column to its replay kernel when I(c) has more intervals than
 // this, K3 when V0(c) has; CAP_Z is the per-lane list capacity of the z-slab
 // replays.
-constexpr int K2_DEFER_NI = 8;
+constexpr int K2_DEFER_NI = 16;
 // Entries (float2) after the seeds of a replayed column: slab range and the
 // per-slab offsets of both groups (2 x 65 int32).
 constexpr int SEED_META = 1 + 65;
-constexpr int K3_DEFER_N = 8;
+constexpr int K3_DEFER_N = 16;
+constexpr int CAP_MID = 48;  // LDS list capacity of the one-lane-per-column replays of K1b and K3
 constexpr int CAP_Z = 32;
 
 // ---------------------------------------------------------------------------
@@ -1301,27 +1302,62 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     LdsList L1{&lds[CAP * WG + threadIdx.x], CAP};
     int res = 0;
     int n = valid ? k1b_column(P, pl.c, L0, L1, &res) : 0;
+    if (defer) push_overflow(Q, ST_K1BH, pl.g0 + threadIdx.x);
+    if (n < 0) push_overflow(Q, ST_K1B, pl.g0 + threadIdx.x);
     if (n < 0 || defer) {
-        push_overflow(Q, ST_K1B, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
     }
     emit_wave(P, pl.c, valid, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
 }
 
-// Replay of K1b: one wave per column, one z-slab per lane; lane 0 stitches
+// Replay of K1b for columns whose lists overflowed: one lane per column, a
+// CAP_MID-entry LDS list first, then arena lists sized from an upper bound.
+__global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
+    __shared__ float2 lds[2 * CAP_MID * WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K1B];
+    if ((int64_t)blockIdx.x * WG >= cnt) return;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + i];
+    const int s = find_shape(Q, g);
+    const OpParams P = make_op(Q, Q.shapes[s]);
+    const int64_t c = g - Q.sbase[s];
+    {
+        LdsList L0{&lds[threadIdx.x], CAP_MID};
+        LdsList L1{&lds[CAP_MID * WG + threadIdx.x], CAP_MID};
+        int res = 0;
+        const int n = k1b_column(P, c, L0, L1, &res);
+        if (n >= 0) {
+            emit_lane(P, c, res ? L1 : L0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+            return;
+        }
+    }
+    const int64_t bound = k1b_bound(P, c);
+    const int64_t pos = arena_alloc(P, 2 * bound);
+    if (pos < 0) return;  // the arena demand is counted
+    const int cap = (int)min<int64_t>(bound, 0x7fffffff);
+    MemList M0{(float2*)(P.arena + pos), cap}, M1{P.arena + pos + bound, cap};
+    int res = 0;
+    const int n = k1b_column(P, c, M0, M1, &res);
+    if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
+    emit_lane(P, c, res ? M1 : M0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+}
+
+// Replay of K1b for heavy columns: one wave per column, one z-slab per lane; lane 0 stitches
 // the slab lists (intervals cut at a slab boundary touch there) into an arena
 // list and emits it.  If a slab list overflows, lane 0 evaluates the column
 // alone with arena lists sized from an upper bound.
-__global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
+__global__ void __launch_bounds__(WG) k_neighbour_heavy(Pass Q) {
     __shared__ float2 lds[2 * CAP_Z * WG];
     __shared__ int nsh[WG];
     __shared__ int rsh[WG];
     if (Q.hdr->abort) return;
-    const int cnt = Q.hdr->novf[ST_K1B];
+    const int cnt = Q.hdr->novf[ST_K1BH];
     const int lane = threadIdx.x;
     for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
-        const int64_t g = Q.ovf[(int64_t)ST_K1B * Q.gcols + e];
+        const int64_t g = Q.ovf[(int64_t)ST_K1BH * Q.gcols + e];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
@@ -1558,27 +1594,58 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     bool valid = pl.valid && !defer;
     LdsList U{&lds[threadIdx.x], CAP};
     int n = k3_column<true>(P, pl.c, valid, U, tab);
+    if (defer) push_overflow(Q, ST_K3H, pl.g0 + threadIdx.x);
+    if (n < 0) push_overflow(Q, ST_K3, pl.g0 + threadIdx.x);
     if (n < 0 || defer) {
-        push_overflow(Q, ST_K3, pl.g0 + threadIdx.x);
         valid = false;
         n = 0;
     }
     emit_wave(P, pl.c, valid, U, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
 }
 
-// Replay of K3: one wave per column, one z-slab per lane; lane 0 stitches the
+// Replay of K3 for columns whose list overflowed: one lane per column, a
+// CAP_MID-entry LDS list first, then an arena list sized from an upper bound.
+__global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
+    __shared__ float2 lds[CAP_MID * WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K3];
+    if ((int64_t)blockIdx.x * WG >= cnt) return;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t g = Q.ovf[(int64_t)ST_K3 * Q.gcols + i];
+    const int s = find_shape(Q, g);
+    const OpParams P = make_op(Q, Q.shapes[s]);
+    const int64_t c = g - Q.sbase[s];
+    {
+        LdsList L{&lds[threadIdx.x], CAP_MID};
+        const int n = k3_column<false>(P, c, true, L, nullptr);
+        if (n >= 0) {
+            emit_lane(P, c, L, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+            return;
+        }
+    }
+    const int64_t bound = k3_bound(P, c);
+    const int64_t pos = arena_alloc(P, bound);
+    if (pos < 0) return;  // the arena demand is counted
+    MemList M{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
+    const int n = k3_column<false>(P, c, true, M, nullptr);
+    if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
+    emit_lane(P, c, M, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+}
+
+// Replay of K3 for heavy columns: one wave per column, one z-slab per lane; lane 0 stitches the
 // slab lists into an arena list and emits it.  If a slab list overflows, lane
 // 0 evaluates the column alone with an arena list sized from an upper bound.
-__global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
+__global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
     __shared__ float2 lds[CAP_Z * WG];
     __shared__ float tab[256];
     __shared__ float2 env[256];
     __shared__ int nsh[WG];
     if (Q.hdr->abort) return;
-    const int cnt = Q.hdr->novf[ST_K3];
+    const int cnt = Q.hdr->novf[ST_K3H];
     const int lane = threadIdx.x;
     for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
-        const int64_t g = Q.ovf[(int64_t)ST_K3 * Q.gcols + e];
+        const int64_t g = Q.ovf[(int64_t)ST_K3H * Q.gcols + e];
         const int s = find_shape(Q, g);
         const OpParams P = make_op(Q, Q.shapes[s]);
         const int64_t c = g - Q.sbase[s];
@@ -1908,7 +1975,8 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(2);
     hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
     DX_MARK(3);
-    hipLaunchKernelGGL(k_neighbour_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
     DX_MARK(4);
     hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(5);
@@ -1920,7 +1988,8 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(9);
     hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(10);
-    hipLaunchKernelGGL(k_union_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
     DX_MARK(11);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
@@ -1933,10 +2002,10 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
 
 hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant) {
     switch (variant) {
-        case 1: return pass_variant<24, 16, 32, 24>(p, s, ev);
-        case 2: return pass_variant<64, 32, 64, 48>(p, s, ev);
+        case 1: return pass_variant<40, 8, 8, 8>(p, s, ev);
+        case 2: return pass_variant<40, 16, 16, 16>(p, s, ev);
         case 3: return pass_variant<32, 16, 40, 16>(p, s, ev);
-        default: return pass_variant<40, 32, 48, 32>(p, s, ev);
+        default: return pass_variant<40, 12, 12, 8>(p, s, ev);
     }
 }
 
