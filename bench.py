@@ -105,7 +105,8 @@ def kernel_bytes(stage, ncols, n_in, st):
     lst_v0 = 12 * ncols + 8 * v0
     lst_i = 12 * ncols + 8 * iv
     return {
-        "row_offset": inp + lst_v0,
+        "column_gaps": inp + 4 * ncols,
+        "row_offset": inp + 4 * ncols + lst_v0,
         "neighbour": lst_v0 + lst_i,
         "seeds": inp + lst_i + 20 * ncols + 9 * seeds,
         "y_union": lst_v0 + 20 * ncols + 9 * seeds + 12 * ncols + 8 * res,

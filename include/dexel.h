@@ -168,14 +168,14 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
                             size_t ws_bytes, void* stream, int32_t reps, int32_t* chosen, float* ms);
 
 /* Profiling.  When enabled, every pass of every later call records HIP
- * events on its stream around each of its DEXEL_NPROF launch groups: row
- * offset, its global-memory replay, neighbour intersection, its replay,
- * extrusion seeds, their replay, three unused groups, y dilation with
- * per-column union, its replay, result scan, compaction copy.
+ * events on its stream around each of its DEXEL_NPROF launch groups: column
+ * gaps, row offset, its global-memory replay, neighbour intersection, its
+ * replay, extrusion seeds, their replay, y dilation with per-column union,
+ * its replay, result scan, compaction copy.
  * dexel_profile_read waits for the recorded events and returns the
  * accumulated milliseconds per group and the number of passes (a dilation or
  * erosion is one pass, open/close two); reset != 0 clears the accumulators. */
-#define DEXEL_NPROF 13
+#define DEXEL_NPROF 11
 dexel_status dexel_profile_enable(dexel_ctx* ctx, int on);
 dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset);
 

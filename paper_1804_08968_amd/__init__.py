@@ -59,7 +59,9 @@ class Engine:
         self.device = torch.device("cuda", self.device_index)
         self.ctx = dexel_ctx_create(self.device_index)
         self._ws = None
-        self._hint = 0
+        # capacity hint (intervals) that the last successful call of offset()
+        # or batch_offset() used; Plan and BatchPlan size their workspace with it
+        self.last_hint = 0
 
     def close(self):
         if self.ctx is not None:
@@ -79,15 +81,17 @@ class Engine:
         return self._ws
 
     def offset(self, grid: DeviceGrid, r: float, op: str = "dilate", stream=None,
-               out_cap: int | None = None, validate: bool = False, max_tries: int = 8):
-        """Run one op synchronously; returns a new DeviceGrid (retries on
-        workspace or output capacity)."""
+               out_cap: int | None = None, validate: bool = False, max_tries: int = 8,
+               hint: int = 0):
+        """Run one op synchronously; returns a new DeviceGrid.  Retries on
+        workspace or output capacity; `hint` is the first capacity hint (0:
+        the library's default for this input), and each retry starts from
+        this call's own need, never from another call's."""
         code = OPS[op]
         nseg = grid.nseg
         view = grid.view(nseg)
         ncols = grid.nx * grid.ny
         cap = out_cap if out_cap is not None else nseg + ncols + 1024
-        hint = self._hint
         flags = DEXEL_FLAG_SYNC | (DEXEL_FLAG_VALIDATE if validate else 0)
         for _ in range(max_tries):
             nbytes = dexel_workspace_size(self.ctx, view, r, code, hint)
@@ -99,14 +103,16 @@ class Engine:
             out = make_out(grid.nx, grid.ny, col, z, nout, status)
             st = dexel_offset(self.ctx, view, r, code, out, ws, stream, flags)
             if st == DEXEL_OK:
+                self.last_hint = hint
                 return DeviceGrid(grid.nx, grid.ny, col, z)
             if st == DEXEL_ERR_WORKSPACE:
                 need = dexel_workspace_need(self.ctx, ws)
                 if need <= 0:
                     raise DexelError(st, dexel_last_error(self.ctx))
+                # a call stops at the first stage that runs out, so a later
+                # stage may need more than `need`: grow at least 1.5x per try
                 base = hint if hint > 0 else nseg + 2 * ncols + 1024
-                hint = max(int(need * 1.25) + 1024, 2 * base)
-                self._hint = max(self._hint, hint)
+                hint = max(int(need * 1.25) + 1024, base + base // 2)
                 continue
             if st == DEXEL_ERR_CAPACITY:
                 cap = int(nout.item()) + 1
@@ -138,7 +144,8 @@ class Plan:
         self.nout = torch.zeros(1, dtype=torch.int64, device=dev)
         self.status_t = torch.zeros(1, dtype=torch.int32, device=dev)
         self.out = make_out(grid.nx, grid.ny, self.col, self.z, self.nout, self.status_t)
-        self.ws_bytes = dexel_workspace_size(engine.ctx, self.view, self.r, self.code, engine._hint)
+        self.ws_bytes = dexel_workspace_size(engine.ctx, self.view, self.r, self.code,
+                                             engine.last_hint)
         engine.workspace(self.ws_bytes)
 
     def enqueue(self, stream=None, flags: int = 0) -> None:
@@ -177,7 +184,8 @@ def _items(grids, radii, ops, outs):
     return arr
 
 
-def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: int = 8):
+def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: int = 8,
+                 hint: int = 0):
     """Offset many shapes in one enqueue (dexel_batch_offset); returns a list
     of DeviceGrids.  Retries with a larger workspace or larger outputs."""
     grids = list(grids)
@@ -185,7 +193,6 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
     ops = list(ops)
     dev = engine.device
     caps = [g.nseg + g.nx * g.ny + 1024 for g in grids]
-    hint = engine._hint
     for _ in range(max_tries):
         outs = [(torch.empty(g.nx * g.ny + 1, dtype=torch.int64, device=dev),
                  torch.empty(2 * max(c, 1), dtype=torch.float32, device=dev),
@@ -196,12 +203,14 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
         ws = engine.workspace(nbytes)
         st = dexel_batch_offset(engine.ctx, items, ws, stream, DEXEL_FLAG_SYNC)
         if st == DEXEL_OK:
+            engine.last_hint = hint
             return [DeviceGrid(g.nx, g.ny, o[0], o[1]) for g, o in zip(grids, outs)]
         if st == DEXEL_ERR_WORKSPACE:
             need = dexel_workspace_need(engine.ctx, ws)
-            base = hint if hint > 0 else sum(caps)
-            hint = max(int(need * 1.25) + 1024, 2 * base)
-            engine._hint = max(engine._hint, hint)
+            if need <= 0:
+                raise DexelError(st, dexel_last_error(engine.ctx))
+            base = hint if hint > 0 else sum(g.nseg + 2 * g.nx * g.ny for g in grids) + 1024
+            hint = max(int(need * 1.25) + 1024, base + base // 2)
             continue
         if st == DEXEL_ERR_CAPACITY:
             for i, o in enumerate(outs):
@@ -232,7 +241,7 @@ class BatchPlan:
                       torch.zeros(1, dtype=torch.int32, device=dev))
                      for g, n in zip(self.grids, self.nseg_out)]
         self.items = _items(self.grids, self.radii, self.ops, self.outs)
-        self.ws_bytes = dexel_batch_workspace_size(engine.ctx, self.items, engine._hint)
+        self.ws_bytes = dexel_batch_workspace_size(engine.ctx, self.items, engine.last_hint)
         engine.workspace(self.ws_bytes)
 
     def enqueue(self, stream=None, flags: int = 0) -> None:

@@ -95,14 +95,14 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
             "dexel_autotune", "dexel_status_string", "dexel_last_error"]
 NVARIANT = 4
-NPROF = 13
-PROFILE_STAGES = ["row_offset", "row_offset_replay", "neighbour", "neighbour_replay",
-                  "seeds", "seeds_replay", "unused6", "unused7",
-                  "unused8", "y_union", "y_union_replay", "result_scan", "compact"]
+NPROF = 11
+PROFILE_STAGES = ["column_gaps", "row_offset", "row_offset_replay", "neighbour",
+                  "neighbour_replay", "seeds", "seeds_replay", "y_union", "y_union_replay",
+                  "result_scan", "compact"]
 # main HIP kernel of each profiled group (as rocprofv3 names it)
-PROFILE_KERNELS = ["k_row_offset", "k_row_offset_fb", "k_neighbour", "k_neighbour_fb",
-                   "k_seeds", "k_seeds_fb", "-", "-",
-                   "-", "k_union", "k_union_fb", "k_scan", "k_copy_out"]
+PROFILE_KERNELS = ["k_col_gaps", "k_row_offset", "k_row_offset_fb", "k_neighbour",
+                   "k_neighbour_fb", "k_seeds", "k_seeds_fb", "k_union", "k_union_fb", "k_scan",
+                   "k_copy_out"]
 
 
 class DexelError(RuntimeError):

@@ -60,7 +60,7 @@ void radius_params(float r, int* R, int* d2max) {
 // Workspace layout of one call (a batch of items; a single op is a batch of one).
 struct Layout {
     size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
-    size_t offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC;
+    size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table
@@ -105,6 +105,8 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.lut_off.resize(n);
     for (size_t i = 0; i < n; ++i) L.lut_off[i] = take(sizeof(float) * (size_t)(items[i].d2max + 1));
     L.luts = n ? L.lut_off[0] : o;
+    L.gap = take(4 * g);
+    L.ends = take(16 * g);
     L.offA = take(8 * g);
     L.cntA = take(4 * g);
     L.offI = take(8 * g);
@@ -296,6 +298,8 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.d2max = ii.d2max;
             S.index = i;
             S.H = (const float*)(w + L.lut_off[i]);
+            S.gap = (float*)(w + L.gap) + gbase;
+            S.ends = (float4*)(w + L.ends) + gbase;
             S.offA = (int64_t*)(w + L.offA) + gbase;
             S.cntA = (int32_t*)(w + L.cntA) + gbase;
             S.offI = (int64_t*)(w + L.offI) + gbase;
@@ -555,11 +559,19 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
     int best = 0;
     float best_ms = 0.f;
     dexel_status result = DEXEL_OK;
+    bool any = false;
     for (int v = 0; v < dexel::NVARIANT && result == DEXEL_OK; ++v) {
-        // one untimed run (also checks the workspace and outputs fit)
+        // one untimed run (also checks the workspace and outputs fit); a
+        // variant that does not fit the caller's workspace or outputs is
+        // skipped (time -1)
         result = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, 0, v);
         if (result != DEXEL_OK) break;
         result = sync_status(ctx, s, n, items);
+        if (result == DEXEL_ERR_WORKSPACE || result == DEXEL_ERR_CAPACITY) {
+            if (ms) ms[v] = -1.0f;
+            result = DEXEL_OK;
+            continue;
+        }
         if (result != DEXEL_OK) break;
         if (hipEventRecord(e0, s) != hipSuccess) { result = DEXEL_ERR_HIP; break; }
         for (int k = 0; k < reps && result == DEXEL_OK; ++k)
@@ -573,14 +585,20 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
         (void)hipEventElapsedTime(&t, e0, e1);
         t /= (float)reps;
         if (ms) ms[v] = t;
-        if (v == 0 || t < best_ms) {
+        if (!any || t < best_ms) {
             best = v;
             best_ms = t;
+            any = true;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->profile = prof;
+    if (result != DEXEL_OK) return result;
+    if (!any) return fail(ctx, DEXEL_ERR_WORKSPACE, "no kernel variant fits the workspace");
+    // leave the outputs as the chosen variant computes them
+    result = enqueue_batch(ctx, n, items, info, ws, ws_bytes, s, 0, best);
+    if (result == DEXEL_OK) result = sync_status(ctx, s, n, items);
     if (result != DEXEL_OK) return result;
     ctx->tuned[batch_signature(n, items)] = best;
     if (chosen) *chosen = best;

@@ -53,6 +53,10 @@ struct Shape {
     int32_t d2max;            // floor(r^2)
     int32_t index;            // item index (status slot)
     const float* H;           // H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..d2max
+    // per input column (k_col_gaps): largest gap, an upper bound; first and
+    // last item (x, y of the first, x, y of the last; unset if empty)
+    float* gap;
+    float4* ends;
     int64_t* offA; int32_t* cntA;
     int64_t* offI; int32_t* cntI;
     // seed position (see SEED_SLOT), count, size of the low group, and two
@@ -115,10 +119,10 @@ hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t 
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s);
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
-// Profiled intervals of one pass, one per launch group: row offset, its
-// replay, neighbour intersection, its replay, seeds, their replay, three
-// unused groups, y dilation + union, its replay, result scan, compaction.
-constexpr int NPROF = 13;
+// Profiled intervals of one pass, one per launch group: column gaps, row
+// offset, its replay, neighbour intersection, its replay, seeds, their
+// replay, y dilation + union, its replay, result scan, compaction.
+constexpr int NPROF = 11;
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
 // variant: kernel variant (per-lane LDS list capacities), 0..NVARIANT-1.
 constexpr int NVARIANT = 4;

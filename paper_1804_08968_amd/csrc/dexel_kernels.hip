@@ -68,6 +68,7 @@ __device__ __forceinline__ int32_t gld(const int32_t* p) { return *(const DX_GLO
 __device__ __forceinline__ uint8_t gld(const uint8_t* p) { return *(const DX_GLOBAL uint8_t*)p; }
 __device__ __forceinline__ void gst(float2* p, float2 v) { *(DX_GLOBAL f2v*)p = f2v{v.x, v.y}; }
 __device__ __forceinline__ void gst(float4* p, float4 v) { *(DX_GLOBAL f4v*)p = f4v{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ void gst(float* p, float v) { *(DX_GLOBAL float*)p = v; }
 __device__ __forceinline__ void gst(int64_t* p, int64_t v) { *(DX_GLOBAL int64_t*)p = v; }
 __device__ __forceinline__ void gst(int32_t* p, int32_t v) { *(DX_GLOBAL int32_t*)p = v; }
 __device__ __forceinline__ void gst(uint8_t* p, uint8_t v) { *(DX_GLOBAL uint8_t*)p = v; }
@@ -85,6 +86,8 @@ struct OpParams {
     const float* H;
     WsHeader* hdr;
     int64_t cap;
+    const float* gap;
+    const float4* ends;
     int64_t* offA; int32_t* cntA; float2* A;
     int64_t* offI; int32_t* cntI; float2* I;
     int64_t* offB; int32_t* cntB; int32_t* loB; float2* B; uint8_t* tagB; float4* hullB;
@@ -98,7 +101,6 @@ constexpr int WG = 64;
 // (typically heavy) replayed columns are spread over many waves instead of
 // being packed 64 to a wave and run in lockstep.
 constexpr int FALLBACK_BLOCKS = 1024;
-constexpr int CAP_FB = 128;  // LDS list capacity of the replay kernels' first tier
 // K2 defers a column to its replay kernel when I(c) has more intervals than
 // this, K3 when V0(c) has; CAP_Z is the per-lane list capacity of the z-slab
 // replays.
@@ -260,55 +262,82 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // column into the canonical list U of size n (chords and U both sorted by
 // start).  U is first moved to the top of its buffer and the merged list is
 // written from the bottom; a write may take the slot of an entry already
-// read, never one still to be read.  Returns the new size, or -1 if the
-// merged list would overtake the unread entries or exceed the capacity.
-// Two heads of each input are kept in registers so that every load has one
-// merge step to arrive.
+// read (or held in a register), never one still to be read.  Returns the new
+// size, or -1 if the merged list would overtake the unread entries or exceed
+// the capacity.
+//
+// Every step consumes exactly one chord (the U entries that start first are
+// taken in an inner loop), so the column's items are loaded a group of
+// MERGE_AHEAD steps ahead: the loads of the next group are issued before the
+// current group is processed, and the only wait is at the end of a group.
+// Loads past the end of the column are clamped to its last item and never
+// used.
+constexpr int MERGE_AHEAD = 8;
+
 template <bool E, class L>
 __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int m, int cnt, float h) {
     const int top = U.cap - n, last = U.cap - 1;
     for (int i = n - 1; i >= 0; --i) U.set(top + i, U.get(i));
-    auto chord = [&](int k) {
-        const float2 it = col_item<E>(P.z, b, m, k);
-        return make_float2(it.x - h, it.y + h);
-    };
-    // Each stream keeps two heads (u0, u1 / c0, c1) and one element in
-    // flight (pu / pc), reloaded every step from clamped indices, so that a
-    // step has no branch but the one that closes an output interval, and
-    // every load has a whole step to arrive.  Reads past the end of a stream
-    // return values that are never used.  Every step consumes one element,
-    // so the loop runs n + cnt - 1 times after the first.
-    const int cl = cnt - 1;
-    float2 u0 = U.get(min(top, last)), u1 = U.get(min(top + 1, last)), pu = U.get(min(top + 2, last));
-    float2 c0 = chord(0), c1 = chord(min(1, cl)), pc = chord(min(2, cl));
-    int i = 0, j = 0, k = 0;
-    bool bad = false;
-    auto advance = [&](bool takeU) {
-        u0 = takeU ? u1 : u0;
-        u1 = takeU ? pu : u1;
-        c0 = takeU ? c0 : c1;
-        c1 = takeU ? c1 : pc;
-        i += takeU ? 1 : 0;
-        j += takeU ? 0 : 1;
-        pu = U.get(min(top + i + 2, last));
-        pc = chord(min(j + 2, cl));
-    };
-    bool takeU = n > 0 && u0.x <= c0.x;
-    float2 cur = takeU ? u0 : c0;
-    advance(takeU);
-    for (int step = n + cnt - 1; step > 0; --step) {
-        takeU = j >= cnt || (i < n && u0.x <= c0.x);
-        const float2 v = takeU ? u0 : c0;
-        advance(takeU);
-        // v extends the open interval, or closes it and opens the next; a
-        // write may take the slot of an entry already read, never one still
-        // to be read
-        const bool close = !(v.x <= cur.y);
-        if (close) {
+    // the caller guarantees m >= 1 (a complemented empty column is the one
+    // chord (-inf, inf), never merged)
+    const float2* zc = P.z + b;
+    auto raw = [&](int j) { return gld(&zc[min(j, m - 1)]); };
+    float2 c0 = raw(0), c1 = raw(1), c2 = raw(2), c3 = raw(3);
+    float2 c4 = raw(4), c5 = raw(5), c6 = raw(6), c7 = raw(7);
+    float2 u0 = U.get(min(top, last));  // next unread entry of U
+    float prevy = -DX_INF;              // E: end of the previous item
+    float2 cur = make_float2(0.f, 0.f);  // the open output interval
+    int i = 0, k = 0;
+    bool open = false, bad = false;
+    auto push = [&](float2 v) {
+        const bool ext = open && v.x <= cur.y;
+        if (open && !ext) {
             if (k <= top + i && k < U.cap) U.set(k, cur); else bad = true;
             ++k;
         }
-        cur = close ? v : make_float2(cur.x, fmaxf(cur.y, v.y));
+        cur = ext ? make_float2(cur.x, fmaxf(cur.y, v.y)) : v;
+        open = true;
+    };
+    auto step = [&](const float2 it, int j) {
+        if (j >= cnt) return;
+        float2 c;
+        if (E) {
+            c = make_float2(prevy - h, (j < m ? it.x : DX_INF) + h);
+            prevy = it.y;
+        } else {
+            c = make_float2(it.x - h, it.y + h);
+        }
+        while (i < n && u0.x <= c.x) {
+            push(u0);
+            ++i;
+            u0 = U.get(min(top + i, last));
+        }
+        push(c);
+    };
+    for (int j = 0; j < cnt; j += MERGE_AHEAD) {
+        const float2 n0 = raw(j + 8), n1 = raw(j + 9), n2 = raw(j + 10), n3 = raw(j + 11);
+        const float2 n4 = raw(j + 12), n5 = raw(j + 13), n6 = raw(j + 14), n7 = raw(j + 15);
+        step(c0, j);
+        step(c1, j + 1);
+        step(c2, j + 2);
+        step(c3, j + 3);
+        step(c4, j + 4);
+        step(c5, j + 5);
+        step(c6, j + 6);
+        step(c7, j + 7);
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+        c4 = n4;
+        c5 = n5;
+        c6 = n6;
+        c7 = n7;
+    }
+    while (i < n) {
+        push(u0);
+        ++i;
+        u0 = U.get(min(top + i, last));
     }
     if (bad || k >= U.cap) return -1;
     U.set(k++, cur);
@@ -318,10 +347,15 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
 // K1: V0 = union over |dx| <= R of the chords [a - H[dx^2], b + H[dx^2]] of
 // the row's columns x + dx, nearest columns first (largest chords first).
 // Within a column the chord starts and the chord ends are both
-// non-decreasing (disjoint sorted intervals, one half-width), so while the
-// partial union is a single interval [L, E] only a leading run of chords
-// starting below L and a trailing run ending above E can change it, and are
-// inserted; otherwise the column's chords are merged with the list.
+// non-decreasing (disjoint sorted intervals, one half-width h), so:
+// * if no gap of the column exceeds 2h, its chords chain into the single
+//   interval [first start - h, last end + h] (rounding is monotone, so every
+//   chord start stays at or below the previous chord's end in float too),
+//   which is inserted alone (all such hulls first);
+// * else, while the partial union is a single interval [L, E], only a
+//   leading run of chords starting below L and a trailing run ending above E
+//   can change it, and are inserted;
+// * otherwise the column's chords are merged with the list.
 // Visit v of a row window, nearest columns first: x, x-1, x+1, x-2, x+2, ...
 __device__ __forceinline__ int visit_col(int x, int v) {
     const int t = (v + 1) >> 1;
@@ -334,15 +368,55 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
     int n = 0;
-    // column pointers of the next visit are loaded one visit ahead
+    // Pass 1: the columns whose gaps are all within 2h contribute their hull
+    // alone, read from the column summary (coalesced across the wave).  On
+    // most inputs this leaves the union a single interval, so that pass 2
+    // takes the short path for nearly every column.  The union does not
+    // depend on the order its chords are inserted in.
+    {
+        float gp = gld(&P.gap[row + x]);
+        float4 en = gld(&P.ends[row + x]);
+        bool inr = true;
+        for (int v = 0; v <= 2 * P.R; ++v) {
+            const int t = (v + 1) >> 1;
+            const float h = gld(&P.H[t * t]);
+            const float gc = gp;
+            const float4 ec4 = en;
+            const bool inc = inr;
+            if (v < 2 * P.R) {
+                const int xn = visit_col(x, v + 1);
+                inr = xn >= 0 && xn < P.nx;
+                if (inr) {
+                    gp = gld(&P.gap[row + xn]);
+                    en = gld(&P.ends[row + xn]);
+                }
+            }
+            const bool empty = gc < 0.f;
+            // an empty column has no chord, its complement the whole line;
+            // a complemented column's hull is the whole line too
+            if (!inc || (empty && !E) || !(empty || gc <= 2.f * h)) continue;
+            const float lo = E ? -DX_INF : ec4.x - h;
+            const float hi = E ? DX_INF : ec4.w + h;
+            n = lv_insert(U, n, lo, hi);
+            if (n < 0) return -1;
+        }
+    }
+    // Pass 2: the other columns.  Column pointers and summaries of the next
+    // visit are loaded one visit ahead.
     int64_t b = 0, e = 0;
+    float gp = 0.f;
+    float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
     bool inr = true;
     b = gld(&P.col_ptr[row + x]);
     e = gld(&P.col_ptr[row + x + 1]);
+    gp = gld(&P.gap[row + x]);
+    en = gld(&P.ends[row + x]);
     for (int v = 0; v <= 2 * P.R; ++v) {
         const int t = (v + 1) >> 1;
         const float h = gld(&P.H[t * t]);
         const int64_t bc = b, ec = e;
+        const float gc = gp;
+        const float4 ec4 = en;
         const bool inc = inr;
         if (v < 2 * P.R) {
             const int xn = visit_col(x, v + 1);
@@ -350,21 +424,30 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
             if (inr) {
                 b = gld(&P.col_ptr[row + xn]);
                 e = gld(&P.col_ptr[row + xn + 1]);
+                gp = gld(&P.gap[row + xn]);
+                en = gld(&P.ends[row + xn]);
             }
         }
         if (!inc) continue;
         const int m = (int)(ec - bc);
         const int cnt = E ? m + 1 : m;
-        if (cnt == 0) continue;
+        // empty columns and hulls were handled in pass 1
+        if (m == 0 || gc <= 2.f * h) continue;
         if (n != 1) {
             n = merge_column<E>(P, U, n, bc, m, cnt, h);
             if (n < 0) return -1;
             continue;
         }
+        // the first and last items, from the column summary
+        float2 f, l;
+        if (E) {
+            f = make_float2(-DX_INF, ec4.x);
+            l = make_float2(ec4.w, DX_INF);
+        } else {
+            f = make_float2(ec4.x, ec4.y);
+            l = make_float2(ec4.z, ec4.w);
+        }
         const float2 u = U.get(0);
-        // the first and last items are loaded together
-        const float2 f = col_item<E>(P.z, bc, m, 0);
-        const float2 l = col_item<E>(P.z, bc, m, cnt - 1);
         int k0 = 0, k1 = cnt;
         if (f.x - h < u.x) {
             k0 = 1;
@@ -374,8 +457,8 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
             k1 = cnt - 1;
             while (k1 > k0 && col_item<E>(P.z, bc, m, k1 - 1).y + h > u.y) --k1;
         }
-        // candidates: items [0, k0) then [k1, cnt); the next item is
-        // loaded before the current one is inserted
+        // candidates: items [0, k0) then [k1, cnt); the next item is loaded
+        // before the current one is inserted
         const int nc = k0 + (cnt - k1);
         int hint = 0;
         float2 nxt = k0 > 0 ? f : l;
@@ -609,15 +692,18 @@ __device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, SeedSink& o
     while (tmax >= 0 && tmax * tmax + 1 > P.d2max) --tmax;
     // column pointers of the next visit are loaded one visit ahead
     int64_t b = 0, e = 0;
+    float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
     bool inr = tmax >= 0;
     if (inr) {
         b = gld(&P.col_ptr[row + x]);
         e = gld(&P.col_ptr[row + x + 1]);
+        en = gld(&P.ends[row + x]);
     }
     for (int v = 0; v <= 2 * tmax; ++v) {
         const int t = (v + 1) >> 1;
         const float h1 = gld(&P.H[t * t + 1]);
         const int64_t bc = b, ec = e;
+        const float4 ec4 = en;
         const bool inc = inr;
         if (v < 2 * tmax) {
             const int xn = visit_col(x, v + 1);
@@ -625,15 +711,22 @@ __device__ int k2_column_e(const OpParams& P, int64_t c, const L& U, SeedSink& o
             if (inr) {
                 b = gld(&P.col_ptr[row + xn]);
                 e = gld(&P.col_ptr[row + xn + 1]);
+                en = gld(&P.ends[row + xn]);
             }
         }
         if (!inc) continue;
         const int m = (int)(ec - bc);
         const int cnt = E ? m + 1 : m;
         if (cnt == 0) continue;
-        // the first and last items are loaded together
-        const float2 f = col_item<E>(P.z, bc, m, 0);
-        const float2 l = col_item<E>(P.z, bc, m, cnt - 1);
+        // the first and last items, from the column summary
+        float2 f, l;
+        if (E) {
+            f = make_float2(-DX_INF, m > 0 ? ec4.x : DX_INF);
+            l = make_float2(m > 0 ? ec4.w : -DX_INF, DX_INF);
+        } else {
+            f = make_float2(ec4.x, ec4.y);
+            l = make_float2(ec4.z, ec4.w);
+        }
         auto item = [&](int k) {
             return k == 0 ? f : (k == cnt - 1 ? l : col_item<E>(P.z, bc, m, k));
         };
@@ -1152,8 +1245,9 @@ __device__ void emit_lane(const OpParams& P, int64_t c, const L& U, int n, int c
 
 // Carve `len` intervals from the arena: their position, or -1 (and a
 // workspace error) if they do not fit.  The counter advances either way, so
-// after a failed call it holds the arena size every replayed column together
-// would need.
+// after a failed call it holds the arena size the replayed columns asked for
+// (a column in the growing tier asks once more per overflow, so this can
+// still fall short; the host grows its retries geometrically).
 __device__ int64_t arena_alloc(const OpParams& P, int64_t len) {
     const unsigned long long base = atomicAdd(&P.hdr->arena, (unsigned long long)len);
     const unsigned long long end = base + (unsigned long long)len;
@@ -1197,6 +1291,8 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.H = S.H;
     p.hdr = Q.hdr;
     p.cap = Q.cap;
+    p.gap = S.gap;
+    p.ends = S.ends;
     p.offA = S.offA; p.cntA = S.cntA; p.A = Q.A;
     p.offI = S.offI; p.cntI = S.cntI; p.I = Q.I;
     p.offB = S.offB; p.cntB = S.cntB; p.B = Q.B;
@@ -1244,6 +1340,75 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
 using LdsList = LV<WG>;
 using MemList = LV<1>;
 
+// Arena tier of the replays, for a column that overflowed its LDS lists:
+// evaluate it into `nl` arena lists of ARENA_FIRST entries each, 4x longer
+// after each overflow up to the column's upper bound `bound`.  The arena then
+// holds about what the column needs, not its bound, which at large radii is
+// orders of magnitude more (an abandoned attempt stays allocated: together
+// at most a third of the last one).  `eval(M0, M1)` evaluates and emits the
+// column and returns -1 on overflow.  If the arena runs out, the call ends
+// with a workspace error and the demand counted so far.
+constexpr int64_t ARENA_FIRST = 256;
+
+template <class F>
+__device__ void arena_eval(const OpParams& P, int nl, int64_t bound, F eval) {
+    int64_t len = min<int64_t>(bound, ARENA_FIRST);
+    for (;;) {
+        const int64_t pos = arena_alloc(P, nl * len);
+        if (pos < 0) return;  // the arena demand is counted
+        const int cap = (int)min<int64_t>(len, 0x7fffffff);
+        const MemList M0{P.arena + pos, cap};
+        const MemList M1{P.arena + pos + (nl > 1 ? len : 0), cap};
+        if (eval(M0, M1) >= 0) return;
+        if (len >= bound) {  // the bound does not hold: never expected
+            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+            return;
+        }
+        len = min<int64_t>(bound, 4 * len);
+    }
+}
+
+// Summary of every input column of the pass, 16 lanes per column: its
+// first and last item, and its largest gap: between consecutive intervals
+// for a dilation, the intervals' own lengths for an erosion (the gaps of the
+// complement).  The gap is stored one float step above the largest float
+// difference (0 if that is 0: equal floats), so that it bounds every exact
+// gap from above; -1 marks an empty column.  K1 reads these per-column arrays with coalesced loads
+// instead of two scattered item loads per visited column.
+constexpr int GAP_LANES = 16;
+
+__global__ void __launch_bounds__(WG) k_col_gaps(Pass Q) {
+    if (Q.hdr->abort) return;
+    const int64_t g = (int64_t)blockIdx.x * (WG / GAP_LANES) + threadIdx.x / GAP_LANES;
+    const int l = threadIdx.x % GAP_LANES;
+    const int s = find_shape(Q, g);
+    const OpParams P = make_op(Q, Q.shapes[s]);
+    const int64_t c = g - Q.sbase[s];
+    const bool valid = c < P.ncols;
+    float G = 0.f;
+    int m = 0;
+    if (valid) {
+        const int64_t b = gld(&P.col_ptr[c]);
+        m = (int)(gld(&P.col_ptr[c + 1]) - b);
+        if (l == 0 && m > 0) {
+            const float2 f = gld(&P.z[b]), e = gld(&P.z[b + m - 1]);
+            gst(&Q.shapes[s].ends[c], make_float4(f.x, f.y, e.x, e.y));
+        }
+        if (P.erode) {
+            for (int i = l; i < m; i += GAP_LANES) {
+                const float2 v = gld(&P.z[b + i]);
+                G = fmaxf(G, v.y - v.x);
+            }
+        } else {
+            for (int i = l; i + 1 < m; i += GAP_LANES)
+                G = fmaxf(G, gld(&P.z[b + i + 1]).x - gld(&P.z[b + i]).y);
+        }
+    }
+#pragma unroll
+    for (int d = GAP_LANES / 2; d > 0; d >>= 1) G = fmaxf(G, __shfl_xor(G, d, 64));
+    if (valid && l == 0) gst(&Q.shapes[s].gap[c], m == 0 ? -1.f : (G > 0.f ? nextafterf(G, DX_INF) : 0.f));
+}
+
 template <int CAP>
 __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     __shared__ float2 lds[CAP * WG];
@@ -1261,31 +1426,32 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     emit_wave(P, pl.c, valid, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
 }
 
+// Replay of K1 for columns whose list overflowed: one lane per column over the
+// full grid, a CAP_MID-entry LDS list first, then the growing arena tier.
 __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
-    __shared__ float2 lds[CAP_FB * WG];
+    __shared__ float2 lds[CAP_MID * WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K1];
-    for (int i = threadIdx.x * gridDim.x + blockIdx.x; i < cnt; i += gridDim.x * WG) {
-        const int64_t g = Q.ovf[(int64_t)ST_K1 * Q.gcols + i];
-        const int s = find_shape(Q, g);
-        const OpParams P = make_op(Q, Q.shapes[s]);
-        const int64_t c = g - Q.sbase[s];
-        {
-            LdsList L{&lds[threadIdx.x], CAP_FB};
-            const int n = k1_column(P, c, L);
-            if (n >= 0) {
-                emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
-                continue;
-            }
+    if ((int64_t)blockIdx.x * WG >= cnt) return;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    if (i >= cnt) return;
+    const int64_t g = Q.ovf[(int64_t)ST_K1 * Q.gcols + i];
+    const int s = find_shape(Q, g);
+    const OpParams P = make_op(Q, Q.shapes[s]);
+    const int64_t c = g - Q.sbase[s];
+    {
+        LdsList L{&lds[threadIdx.x], CAP_MID};
+        const int n = k1_column(P, c, L);
+        if (n >= 0) {
+            emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
+            return;
         }
-        const int64_t bound = k1_bound(P, c);
-        const int64_t pos = arena_alloc(P, bound);
-        if (pos < 0) continue;  // keep counting the arena demand
-        MemList U{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
-        const int n = k1_column(P, c, U);
-        if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
-        emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
     }
+    arena_eval(P, 1, k1_bound(P, c), [&](const MemList& U, const MemList&) {
+        const int n = k1_column(P, c, U);
+        if (n >= 0) emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
+        return n;
+    });
 }
 
 template <int CAP>
@@ -1312,7 +1478,7 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
 }
 
 // Replay of K1b for columns whose lists overflowed: one lane per column, a
-// CAP_MID-entry LDS list first, then arena lists sized from an upper bound.
+// CAP_MID-entry LDS list first, then the growing arena tier.
 __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
     __shared__ float2 lds[2 * CAP_MID * WG];
     if (Q.hdr->abort) return;
@@ -1334,21 +1500,18 @@ __global__ void __launch_bounds__(WG) k_neighbour_fb(Pass Q) {
             return;
         }
     }
-    const int64_t bound = k1b_bound(P, c);
-    const int64_t pos = arena_alloc(P, 2 * bound);
-    if (pos < 0) return;  // the arena demand is counted
-    const int cap = (int)min<int64_t>(bound, 0x7fffffff);
-    MemList M0{(float2*)(P.arena + pos), cap}, M1{P.arena + pos + bound, cap};
-    int res = 0;
-    const int n = k1b_column(P, c, M0, M1, &res);
-    if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
-    emit_lane(P, c, res ? M1 : M0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+    arena_eval(P, 2, k1b_bound(P, c), [&](const MemList& M0, const MemList& M1) {
+        int res = 0;
+        const int n = k1b_column(P, c, M0, M1, &res);
+        if (n >= 0) emit_lane(P, c, res ? M1 : M0, n, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+        return n;
+    });
 }
 
 // Replay of K1b for heavy columns: one wave per column, one z-slab per lane; lane 0 stitches
 // the slab lists (intervals cut at a slab boundary touch there) into an arena
 // list and emits it.  If a slab list overflows, lane 0 evaluates the column
-// alone with arena lists sized from an upper bound.
+// alone in the growing arena tier.
 __global__ void __launch_bounds__(WG) k_neighbour_heavy(Pass Q) {
     __shared__ float2 lds[2 * CAP_Z * WG];
     __shared__ int nsh[WG];
@@ -1392,15 +1555,12 @@ __global__ void __launch_bounds__(WG) k_neighbour_heavy(Pass Q) {
         const bool fail = __any(n < 0);
         if (lane != 0) continue;
         if (fail) {
-            const int64_t bound = k1b_bound(P, c);
-            const int64_t pos = arena_alloc(P, 2 * bound);
-            if (pos < 0) continue;  // keep counting the arena demand
-            const int cap = (int)min<int64_t>(bound, 0x7fffffff);
-            MemList M0{(float2*)(P.arena + pos), cap}, M1{P.arena + pos + bound, cap};
-            int r2 = 0;
-            const int nn = k1b_column(P, c, M0, M1, &r2);
-            if (nn < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); continue; }
-            emit_lane(P, c, r2 ? M1 : M0, nn, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+            arena_eval(P, 2, k1b_bound(P, c), [&](const MemList& M0, const MemList& M1) {
+                int r2 = 0;
+                const int nn = k1b_column(P, c, M0, M1, &r2);
+                if (nn >= 0) emit_lane(P, c, r2 ? M1 : M0, nn, 0, &Q.hdr->bumpI, P.offI, P.cntI, P.I);
+                return nn;
+            });
             continue;
         }
         int64_t tot = 0;
@@ -1604,7 +1764,7 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
 }
 
 // Replay of K3 for columns whose list overflowed: one lane per column, a
-// CAP_MID-entry LDS list first, then an arena list sized from an upper bound.
+// CAP_MID-entry LDS list first, then the growing arena tier.
 __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
     __shared__ float2 lds[CAP_MID * WG];
     if (Q.hdr->abort) return;
@@ -1624,18 +1784,16 @@ __global__ void __launch_bounds__(WG) k_union_fb(Pass Q) {
             return;
         }
     }
-    const int64_t bound = k3_bound(P, c);
-    const int64_t pos = arena_alloc(P, bound);
-    if (pos < 0) return;  // the arena demand is counted
-    MemList M{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
-    const int n = k3_column<false>(P, c, true, M, nullptr);
-    if (n < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); return; }
-    emit_lane(P, c, M, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+    arena_eval(P, 1, k3_bound(P, c), [&](const MemList& M, const MemList&) {
+        const int n = k3_column<false>(P, c, true, M, nullptr);
+        if (n >= 0) emit_lane(P, c, M, n, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+        return n;
+    });
 }
 
 // Replay of K3 for heavy columns: one wave per column, one z-slab per lane; lane 0 stitches the
 // slab lists into an arena list and emits it.  If a slab list overflows, lane
-// 0 evaluates the column alone with an arena list sized from an upper bound.
+// 0 evaluates the column alone in the growing arena tier.
 __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
     __shared__ float2 lds[CAP_Z * WG];
     __shared__ float tab[256];
@@ -1690,13 +1848,11 @@ __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
         const bool fail = __any(n < 0);
         if (lane != 0) continue;
         if (fail) {
-            const int64_t bound = k3_bound(P, c);
-            const int64_t pos = arena_alloc(P, bound);
-            if (pos < 0) continue;  // keep counting the arena demand
-            MemList M{(float2*)(P.arena + pos), (int)min<int64_t>(bound, 0x7fffffff)};
-            const int nn = k3_column<false>(P, c, true, M, nullptr);
-            if (nn < 0) { set_error(Q.hdr, DEXEL_ERR_WORKSPACE); continue; }
-            emit_lane(P, c, M, nn, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+            arena_eval(P, 1, k3_bound(P, c), [&](const MemList& M, const MemList&) {
+                const int nn = k3_column<false>(P, c, true, M, nullptr);
+                if (nn >= 0) emit_lane(P, c, M, nn, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+                return nn;
+            });
             continue;
         }
         int64_t tot = 0;
@@ -1958,8 +2114,9 @@ hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s) {
 }
 
 // Kernel variants: per-lane LDS list capacities of K1, K1b (each of two
-// lists), K2 and K3.  Larger lists replay fewer columns from global memory;
-// smaller ones leave room for more resident waves per CU.  The host picks
+// lists), K2 and K3.  Larger lists replay fewer columns; smaller ones leave
+// room for more resident waves per CU (the default, variant 0, has small
+// lists; variant 1 large ones for shapes with long lists).  The host picks
 // one per call (default, forced, or autotuned).
 template <int C1, int C1B, int C2, int C3>
 static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
@@ -1969,42 +2126,41 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
 #define DX_MARK(i) \
     if (ev && (e = hipEventRecord(ev[i], s)) != hipSuccess) return e
     DX_MARK(0);
-    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
-    hipLaunchKernelGGL(k_row_offset_fb, gf, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
     DX_MARK(2);
-    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
     DX_MARK(3);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    DX_MARK(4);
     hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
-    DX_MARK(4);
-    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(5);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
+    DX_MARK(6);
     hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
     hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
-    DX_MARK(6);
     DX_MARK(7);
-    DX_MARK(8);
-    DX_MARK(9);
     hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
-    DX_MARK(10);
+    DX_MARK(8);
     hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
-    DX_MARK(11);
+    DX_MARK(9);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
-    DX_MARK(12);
+    DX_MARK(10);
     hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
-    DX_MARK(13);
+    DX_MARK(11);
 #undef DX_MARK
     return hipGetLastError();
 }
 
 hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant) {
     switch (variant) {
-        case 1: return pass_variant<40, 8, 8, 8>(p, s, ev);
+        case 1: return pass_variant<40, 32, 48, 32>(p, s, ev);
         case 2: return pass_variant<40, 16, 16, 16>(p, s, ev);
-        case 3: return pass_variant<32, 16, 40, 16>(p, s, ev);
+        case 3: return pass_variant<24, 12, 12, 8>(p, s, ev);
         default: return pass_variant<40, 12, 12, 8>(p, s, ev);
     }
 }

@@ -219,9 +219,8 @@ def test_engine_retries_to_exact_result(engine, oracle_lib):
     dg = dx.DeviceGrid.from_host(hg)
     fresh = dx.Engine(0)
     try:
-        fresh._hint = 32
         print("[case] engine retry", flush=True)
-        res = fresh.offset(dg, 3.0, "dilate", out_cap=1)
+        res = fresh.offset(dg, 3.0, "dilate", out_cap=1, hint=32)
         col, z = res.to_host()
         ref = oracle_lib.run(hg, 3.0, "dilate", "f32model")
         assert np.array_equal(col, ref.col_ptr)
