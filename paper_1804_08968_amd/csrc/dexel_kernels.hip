@@ -362,6 +362,23 @@ __device__ __forceinline__ int visit_col(int x, int v) {
     return v == 0 ? x : ((v & 1) ? x - t : x + t);
 }
 
+// Offset of visit v (0 .. 2R) in the order of the row offset's second pass:
+// x - q, x + q, x, then x -+ 1, x -+ 2, ... without q, for q = max(1, R/4).
+// Neighbouring columns of a solid with through-channels tend to share the
+// channel's gaps, so their partial union keeps every gap until a column far
+// enough away fills it; merging the pair at +-q first closes most gaps at
+// once, and the later columns take the short single-interval path.
+__device__ __forceinline__ int pass2_offset(int v, int R) {
+    if (R == 0) return 0;
+    const int q = max(1, R >> 2);
+    if (v < 2) return v ? q : -q;
+    if (v == 2) return 0;
+    const int k = v - 3;
+    int t = (k >> 1) + 1;
+    if (t >= q) ++t;
+    return (k & 1) ? t : -t;
+}
+
 template <bool E, class L>
 __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
     int x, y;
@@ -401,25 +418,29 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
             if (n < 0) return -1;
         }
     }
-    // Pass 2: the other columns.  Column pointers and summaries of the next
-    // visit are loaded one visit ahead.
+    // Pass 2: the other columns, in the order of pass2_offset.  Column
+    // pointers and summaries of the next visit are loaded one visit ahead.
     int64_t b = 0, e = 0;
     float gp = 0.f;
     float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
-    bool inr = true;
-    b = gld(&P.col_ptr[row + x]);
-    e = gld(&P.col_ptr[row + x + 1]);
-    gp = gld(&P.gap[row + x]);
-    en = gld(&P.ends[row + x]);
+    int dn = pass2_offset(0, P.R);
+    bool inr = x + dn >= 0 && x + dn < P.nx;
+    if (inr) {
+        b = gld(&P.col_ptr[row + x + dn]);
+        e = gld(&P.col_ptr[row + x + dn + 1]);
+        gp = gld(&P.gap[row + x + dn]);
+        en = gld(&P.ends[row + x + dn]);
+    }
     for (int v = 0; v <= 2 * P.R; ++v) {
-        const int t = (v + 1) >> 1;
+        const int t = abs(dn);
         const float h = gld(&P.H[t * t]);
         const int64_t bc = b, ec = e;
         const float gc = gp;
         const float4 ec4 = en;
         const bool inc = inr;
         if (v < 2 * P.R) {
-            const int xn = visit_col(x, v + 1);
+            dn = pass2_offset(v + 1, P.R);
+            const int xn = x + dn;
             inr = xn >= 0 && xn < P.nx;
             if (inr) {
                 b = gld(&P.col_ptr[row + xn]);
@@ -497,13 +518,26 @@ __device__ int k1b_column(const OpParams& P, int64_t c, const L& L0, const L& L1
     col_xy(P, c, &x, &y);
     L0.set(0, make_float2(-DX_INF, DX_INF));
     int n = 1, cur = 0;
+    // the list of the next row (y - dy, then y + dy, dy = 1 .. R) is located
+    // one row ahead
+    int64_t noff = 0;
+    int ncnt = -1;
+    auto fetch = [&](int q) {  // row q = 2 (dy - 1) + s
+        const int yy = (q & 1) ? y + (q >> 1) + 1 : y - (q >> 1) - 1;
+        const bool in = yy >= 0 && yy < P.ny;
+        const int64_t cc = (int64_t)(in ? yy : y) * P.nx + x;
+        noff = in ? gld(&P.offA[cc]) : 0;
+        ncnt = in ? gld(&P.cntA[cc]) : -1;
+    };
+    if (P.R >= 1) fetch(0);
     for (int dy = 1; dy <= P.R && n > 0; ++dy) {
         for (int s = 0; s < 2 && n > 0; ++s) {
-            const int yy = s ? y + dy : y - dy;
-            if (yy < 0 || yy >= P.ny) continue;
-            const int64_t cc = (int64_t)yy * P.nx + x;
-            const float2* J = P.A + gld(&P.offA[cc]);
-            const int m = gld(&P.cntA[cc]);
+            const int q = 2 * (dy - 1) + s;
+            const int64_t off = noff;
+            const int m = ncnt;
+            if (q + 1 < 2 * P.R) fetch(q + 1);
+            if (m < 0) continue;  // row outside the grid
+            const float2* J = P.A + off;
             const L& S = cur ? L1 : L0;
             const L& D = cur ? L0 : L1;
             int i = 0, j = 0, k = 0;
@@ -795,11 +829,10 @@ struct SeedSpans {
     int n[2];
 };
 
-__device__ __forceinline__ SeedSpans seed_spans(const OpParams& P, int64_t cc) {
+// From the column's seed offset, count and (encoded) low-group size.
+__device__ __forceinline__ SeedSpans seed_spans_of(const OpParams& P, int64_t ob, int cnt, int lov) {
     SeedSpans r;
-    const int64_t ob = gld(&P.offB[cc]);
-    const int cnt = gld(&P.cntB[cc]);
-    const int lo = seed_lo(gld(&P.loB[cc]));
+    const int lo = seed_lo(lov);
     if (ob >= 0) {
         r.n[0] = min(lo, SEED_SLOT);
         r.n[1] = min(cnt - lo, SEED_SLOT - r.n[0]);
@@ -817,6 +850,10 @@ __device__ __forceinline__ SeedSpans seed_spans(const OpParams& P, int64_t cc) {
         r.t[1] = P.arena_tag + a + lo;
     }
     return r;
+}
+
+__device__ __forceinline__ SeedSpans seed_spans(const OpParams& P, int64_t cc) {
+    return seed_spans_of(P, gld(&P.offB[cc]), gld(&P.cntB[cc]), gld(&P.loB[cc]));
 }
 
 template <bool TAB, class L>
