@@ -10,8 +10,15 @@ chained request (open/close on the previous result of its session) becomes
 eligible once that result is complete.  Completion times come from HIP
 events, relative to an event recorded when the server starts.
 
-mode="plain" serves one request at a time with a single-item call on one
-stream (the comparison point).
+Admission order (continuous mode, policy="sjf"): among the requests that are
+the earliest waiting one of their session, smallest estimated work first,
+with the estimate divided by 1 + wait / age_s so that a long-waiting large
+request is eventually admitted.  The work estimate is (input intervals +
+columns) x (1 + r), the row window the kernels walk per column.
+policy="fifo" admits in arrival order.
+
+mode="plain" serves one request at a time in arrival order with a
+single-item call on one stream (the comparison point).
 """
 from __future__ import annotations
 
@@ -54,11 +61,16 @@ class Done:
 
 class Server:
     def __init__(self, engine: Engine, pool, budget_bytes: int = 64 << 30, max_batch: int = 16,
-                 slots: int = 2, mode: str = "continuous", work_cap_cols: int = 4 << 20):
+                 slots: int = 2, mode: str = "continuous", work_cap_cols: int = 4 << 20,
+                 policy: str = "sjf", age_s: float = 2.0):
         self.engine = engine
         self.pool = list(pool)
         self.budget = int(budget_bytes)
         self.mode = mode
+        if policy not in ("sjf", "fifo"):
+            raise ValueError(f"unknown admission policy {policy!r}")
+        self.policy = "fifo" if mode == "plain" else policy
+        self.age_s = float(age_s)
         self.max_batch = 1 if mode == "plain" else int(max_batch)
         self.slots = 1 if mode == "plain" else int(slots)
         # A batch holds at most this many columns (one request always fits):
@@ -154,7 +166,20 @@ class Server:
                 members, mem_b, keep = [], 0, []
                 cols_b = 0
                 held = set()           # sessions with an earlier request still waiting
-                for req in waiting:
+                order = waiting
+                if self.policy == "sjf":
+                    first = {}
+                    for req in waiting:    # waiting is in arrival order
+                        first.setdefault(req.session, req.id)
+
+                    def prio(req):
+                        g = (session_last.get(req.session, self.pool[req.shape]) if req.chain
+                             else self.pool[req.shape])
+                        work = (g.nseg_cached + g.nx * g.ny) * (1.0 + req.r)
+                        return work / (1.0 + (now - req.arrival) / self.age_s)
+                    heads = sorted((q for q in waiting if first[q.session] == q.id), key=prio)
+                    order = heads + [q for q in waiting if first[q.session] != q.id]
+                for req in order:
                     if (len(members) >= self.max_batch or req.session in session_busy
                             or req.session in held):
                         keep.append(req)   # full batch, or keep the session's order
@@ -179,7 +204,7 @@ class Server:
                     mem_b += fp
                     cols_b += grid_in.nx * grid_in.ny
                     session_busy.add(req.session)
-                waiting = keep
+                waiting = sorted(keep, key=lambda q: (q.arrival, q.id))
                 if members:
                     slot = free_slots.pop()
                     stream = self.streams[slot]
