@@ -1505,8 +1505,9 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     LdsList L1{&lds[CAP * WG + threadIdx.x], CAP};
     int res = 0;
     int n = valid ? k1b_column(P, pl.c, L0, L1, &res) : 0;
-    if (defer) push_overflow(Q, ST_K1BH, pl.g0 + threadIdx.x);
-    if (n < 0) push_overflow(Q, ST_K1B, pl.g0 + threadIdx.x);
+    // a column whose lists overflow is long enough to be worth a whole wave:
+    // the slab replay splits its serial chain over 64 lanes
+    if (defer || n < 0) push_overflow(Q, ST_K1BH, pl.g0 + threadIdx.x);
     if (n < 0 || defer) {
         valid = false;
         n = 0;
