@@ -829,6 +829,17 @@ struct SeedSpans {
     int n[2];
 };
 
+// Tags p[0..3] of a seed tag array, from the two aligned dwords holding them
+// (bits 8q .. 8q+7 of the result are tag q).  The two dwords may cover up to
+// 7 bytes around the four tags: every tag array lies inside the workspace,
+// 256-byte aligned and followed by another region, so the reads stay in it;
+// tags past a group's end are never used.
+__device__ __forceinline__ uint64_t tags4(const uint8_t* p) {
+    const uintptr_t a = (uintptr_t)p & ~(uintptr_t)3;
+    const uint32_t w0 = (uint32_t)gld((const int32_t*)a), w1 = (uint32_t)gld((const int32_t*)(a + 4));
+    return ((((uint64_t)w1) << 32) | w0) >> (8 * ((uintptr_t)p & 3));
+}
+
 // From the column's seed offset, count and (encoded) low-group size.
 __device__ __forceinline__ SeedSpans seed_spans_of(const OpParams& P, int64_t ob, int cnt, int lov) {
     SeedSpans r;
@@ -921,15 +932,16 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             const float2* sv = sp.s[k & 1];
             const uint8_t* tv = sp.t[k & 1];
             const int nb = sp.n[k & 1];
-            // seeds in groups of four: the loads of a group are in flight together
+            // seeds in groups of four: the loads of a group are in flight
+            // together, its four tags in two dword loads
             for (int j = 0; j < nb && ok; j += 4) {
                 int tq[4];
                 float2 pq[4];
+                const uint64_t tw = tags4(tv + j);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int jj = min(j + q, nb - 1);
-                    tq[q] = gld(&tv[jj]);
-                    pq[q] = gld(&sv[jj]);
+                    tq[q] = (int)((tw >> (8 * q)) & 0xff);
+                    pq[q] = gld(&sv[min(j + q, nb - 1)]);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -1198,11 +1210,11 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             for (int j = j0; j < nb && busy; j += 4) {
                 int tq[4];
                 float2 pq[4];
+                const uint64_t tw = tags4(tv + j);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int jj = min(j + q, nb - 1);
-                    tq[q] = gld(&tv[jj]);
-                    pq[q] = gld(&sv[jj]);
+                    tq[q] = (int)((tw >> (8 * q)) & 0xff);
+                    pq[q] = gld(&sv[min(j + q, nb - 1)]);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
