@@ -595,7 +595,9 @@ __device__ __forceinline__ bool in_I(Ptr Ip, int ni, float2 i0, float lo, float 
 // upwards and group 1 fills dhi downwards, both within cap entries in total.
 // Linear mode (cap == 0): each group fills its own region upwards within
 // cap_lo / cap_hi entries.  Hulls per group: x, y of the chords at |dy| = 1,
-// z, w of the pieces.
+// z, w of the pieces.  In slot mode the 1-byte tags are collected in wlo /
+// whi and stored as whole aligned dwords (the slot's tags are 32-byte
+// aligned), the last partial dword of each group by sink_flush.
 struct SeedSink {
     float2* dlo;
     uint8_t* tlo;
@@ -605,6 +607,7 @@ struct SeedSink {
     float zsplit;
     int nlo, nhi;
     float4 hlo, hhi;
+    uint32_t wlo, whi;
 };
 
 __device__ __forceinline__ SeedSink sink_make(float2* dlo, uint8_t* tlo, float2* dhi, uint8_t* thi,
@@ -620,6 +623,7 @@ __device__ __forceinline__ SeedSink sink_make(float2* dlo, uint8_t* tlo, float2*
     o.zsplit = zsplit;
     o.nlo = o.nhi = 0;
     o.hlo = o.hhi = make_float4(DX_INF, -DX_INF, DX_INF, -DX_INF);
+    o.wlo = o.whi = 0;
     return o;
 }
 
@@ -636,11 +640,20 @@ __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, SeedS
     if (o.cap > 0) {
         if (o.nlo + o.nhi < o.cap) {
             if (hi) {
+                // group 1 entry k is byte 3 - k % 4 of the dword ending at thi - (k & ~3)
                 gst(&o.dhi[-o.nhi], v);
-                gst(&o.thi[-o.nhi], (uint8_t)t);
+                o.whi |= (uint32_t)t << (8 * (3 - (o.nhi & 3)));
+                if ((o.nhi & 3) == 3) {
+                    gst((int32_t*)(o.thi - o.nhi), (int32_t)o.whi);
+                    o.whi = 0;
+                }
             } else {
                 gst(&o.dlo[o.nlo], v);
-                gst(&o.tlo[o.nlo], (uint8_t)t);
+                o.wlo |= (uint32_t)t << (8 * (o.nlo & 3));
+                if ((o.nlo & 3) == 3) {
+                    gst((int32_t*)(o.tlo + o.nlo - 3), (int32_t)o.wlo);
+                    o.wlo = 0;
+                }
             }
         }
     } else if (hi) {
@@ -659,6 +672,15 @@ __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, SeedS
         hull_add(&o.hlo, p, q, h1);
         ++o.nlo;
     }
+}
+
+// Slot mode: store the tags of each group's last partial dword, byte by byte
+// (the two groups may share that dword).  A column with more pieces than the
+// slot is recomputed into the arena, so its slot tags are not needed.
+__device__ __forceinline__ void sink_flush(SeedSink& o) {
+    if (o.cap <= 0 || o.nlo + o.nhi > o.cap) return;
+    for (int i = o.nlo & ~3; i < o.nlo; ++i) gst(&o.tlo[i], (uint8_t)(o.wlo >> (8 * (i & 3))));
+    for (int i = o.nhi & ~3; i < o.nhi; ++i) gst(&o.thi[-i], (uint8_t)(o.whi >> (8 * (3 - (i & 3)))));
 }
 
 // Split height of column c: the middle of the finite extent of I(c) (0 if
@@ -1654,6 +1676,7 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
             SeedSink o = sink_make(slot, tslot, slot + SEED_SLOT - 1, tslot + SEED_SLOT - 1, SEED_SLOT,
                                    0, 0, seed_split(P, pl.c));
             np = k2_column(P, pl.c, U, o);
+            sink_flush(o);
             gst(&P.offB[pl.c], g * SEED_SLOT);
             gst(&P.cntB[pl.c], np);
             gst(&P.loB[pl.c], o.nlo);
