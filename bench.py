@@ -32,14 +32,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1804_08968_amd", "csrc", "dexel_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1804_08968_amd", "csrc", f)
+              for f in ("dexel_kernels.hip", "dexel_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_close_r16_hbm_traffic.txt")
 
 
 def kernels_sha256():
+    """SHA-256 over the kernel source and the internal header it includes."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):

@@ -35,7 +35,7 @@ enum Stage {
 // Seed slots per column: the seeds of a column are written at
 // B[g * SEED_SLOT ...] (g = global column); a column with more seeds is
 // recomputed into the workspace arena and its offset stored as -(pos + 1).
-constexpr int SEED_SLOT = 32;
+constexpr int SEED_SLOT = 64;
 
 // One shape of one pass, in device memory.  Per-column arrays are already
 // offset to the shape's first global column, so kernels index them with the
