@@ -110,6 +110,25 @@ def test_dense_columns_fallback(engine, oracle_lib):
         check(engine, oracle_lib, g, 2.0, op, label="dense")
 
 
+def test_long_lists_grow_the_arena(engine, oracle_lib):
+    """About 1500 short, well separated intervals per column: the row unions
+    hold 1500 and more intervals, past every LDS list and past the arena
+    tier's first lists, which then grow (256, 1024, 4096 entries) up to the
+    column's bound.  The default workspace is too small for that arena, so
+    the engine's retry from the reported need is exercised too."""
+    rng = np.random.default_rng(11)
+    nx, ny = 8, 4
+    cols = []
+    for _ in range(nx * ny):
+        base = 10.0 * np.arange(1500) + rng.uniform(0.0, 3.0, 1500)
+        a = base.astype(np.float32).astype(np.float64)
+        b = (base + 0.5).astype(np.float32).astype(np.float64)
+        cols.append(list(zip(a, b)))
+    g = grid_from_columns(nx, ny, cols)
+    for op in ("dilate", "erode", "close"):
+        check(engine, oracle_lib, g, 1.5, op, label="long lists")
+
+
 @pytest.mark.parametrize("r", [2.0, 8.0])
 @pytest.mark.parametrize("op", ["dilate", "erode"])
 def test_c2_full(engine, oracle_lib, r, op):
