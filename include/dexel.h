@@ -138,6 +138,26 @@ dexel_status dexel_offset(dexel_ctx* ctx, const dexel_grid_view* in, float r, in
                           dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream,
                           uint32_t flags);
 
+/* Per-column Boolean operations (CSG) of two grids of the same nx, ny
+ * (Sec. 2, item (3): CSG carried out directly in dexel space).  The shell of
+ * Sec. 4, "3D Printing", is DEXEL_CSG_DIFFERENCE of a dilation and an erosion
+ * of the same shape.  The operations are the regularised ones of solid
+ * modelling: the result is the closure of the interior of the set
+ * operation, so input intervals of zero length are ignored, touching result
+ * pieces form one interval, and no piece of zero length is produced.
+ * Endpoints are copied from the inputs, never computed.
+ *
+ * `a`, `b`: canonical grids (as for dexel_offset); `out`: same nx, ny, with
+ * cap_seg intervals of room (the result has at most nseg(a) + nseg(b)); on
+ * overflow out->status is DEXEL_ERR_CAPACITY and *out->nseg_out the need.
+ * `ws`: device memory of dexel_csg_workspace_size bytes, 256-byte aligned,
+ * used during the call only.  DEXEL_FLAG_SYNC as for dexel_offset;
+ * DEXEL_FLAG_VALIDATE is not supported (DEXEL_ERR_UNSUPPORTED). */
+typedef enum { DEXEL_CSG_UNION = 0, DEXEL_CSG_INTERSECT = 1, DEXEL_CSG_DIFFERENCE = 2 } dexel_csg_op;
+dexel_status dexel_csg_workspace_size(dexel_ctx* ctx, const dexel_grid_view* a, size_t* bytes);
+dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_grid_view* b, int32_t op,
+                       dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
 /* Workspace for dexel_batch_offset over `items` (the largest single-item
  * need, since items share the workspace in sequence). */
 dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,

@@ -18,7 +18,8 @@ from .binding import (  # noqa: F401
     dexel_grid_view, dexel_last_error, dexel_offset, dexel_profile_enable, dexel_profile_read,
     dexel_status_string, dexel_workspace_need, dexel_workspace_size, dexel_workspace_stats,
     make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES, NVARIANT, dexel_autotune,
-    dexel_set_variant,
+    dexel_set_variant, CSG_OPS, DEXEL_CSG_DIFFERENCE, DEXEL_CSG_INTERSECT, DEXEL_CSG_UNION,
+    dexel_csg, dexel_csg_workspace_size,
 )
 
 
@@ -119,6 +120,34 @@ class Engine:
                 continue
             raise DexelError(st, dexel_last_error(self.ctx))
         raise DexelError(DEXEL_ERR_WORKSPACE, "retries exhausted")
+
+
+    def csg(self, a: DeviceGrid, b: DeviceGrid, op: str, stream=None) -> DeviceGrid:
+        """Per-column regularised union / intersection / difference of two
+        grids of the same size (dexel_csg), synchronously."""
+        code = CSG_OPS[op]
+        if (a.nx, a.ny) != (b.nx, b.ny):
+            raise ValueError("grids differ in size")
+        va, vb = a.view(a.nseg), b.view(b.nseg)
+        ncols = a.nx * a.ny
+        cap = a.nseg + b.nseg + 1
+        ws = self.workspace(dexel_csg_workspace_size(self.ctx, va))
+        col = torch.empty(ncols + 1, dtype=torch.int64, device=self.device)
+        z = torch.empty(2 * cap, dtype=torch.float32, device=self.device)
+        nout = torch.zeros(1, dtype=torch.int64, device=self.device)
+        status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        out = make_out(a.nx, a.ny, col, z, nout, status)
+        st = dexel_csg(self.ctx, va, vb, code, out, ws, stream, DEXEL_FLAG_SYNC)
+        if st != DEXEL_OK:
+            raise DexelError(st, dexel_last_error(self.ctx))
+        return DeviceGrid(a.nx, a.ny, col, z)
+
+    def shell(self, grid: DeviceGrid, r: float) -> DeviceGrid:
+        """Shell of thickness about 2r around the surface: the dilation minus
+        the erosion (Sec. 4, "3D Printing"), three library calls on the device."""
+        d = self.offset(grid, r, "dilate")
+        e = self.offset(grid, r, "erode")
+        return self.csg(d, e, "difference")
 
 
 class Plan:

@@ -32,6 +32,9 @@ DEXEL_DILATE, DEXEL_ERODE, DEXEL_OPEN, DEXEL_CLOSE = 0, 1, 2, 3
 OPS = {"dilate": DEXEL_DILATE, "erode": DEXEL_ERODE, "open": DEXEL_OPEN, "close": DEXEL_CLOSE}
 DEXEL_FLAG_SYNC = 1
 DEXEL_FLAG_VALIDATE = 2
+DEXEL_CSG_UNION, DEXEL_CSG_INTERSECT, DEXEL_CSG_DIFFERENCE = 0, 1, 2
+CSG_OPS = {"union": DEXEL_CSG_UNION, "intersect": DEXEL_CSG_INTERSECT,
+           "difference": DEXEL_CSG_DIFFERENCE}
 
 
 class dexel_grid_view(ctypes.Structure):
@@ -73,6 +76,11 @@ lib.dexel_batch_workspace_size.restype = c_int
 lib.dexel_batch_offset.argtypes = [c_void_p, c_int32, _P(dexel_batch_item), c_void_p, c_size_t,
                                    c_void_p, c_uint32]
 lib.dexel_batch_offset.restype = c_int
+lib.dexel_csg_workspace_size.argtypes = [c_void_p, _P(dexel_grid_view), _P(c_size_t)]
+lib.dexel_csg_workspace_size.restype = c_int
+lib.dexel_csg.argtypes = [c_void_p, _P(dexel_grid_view), _P(dexel_grid_view), c_int32,
+                          _P(dexel_grid_out), c_void_p, c_size_t, c_void_p, ctypes.c_uint32]
+lib.dexel_csg.restype = c_int
 lib.dexel_profile_enable.argtypes = [c_void_p, c_int]
 lib.dexel_profile_enable.restype = c_int
 lib.dexel_profile_read.argtypes = [c_void_p, _P(ctypes.c_double), _P(c_int64), c_int]
@@ -93,7 +101,8 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_workspace_need", "dexel_dilate", "dexel_erode", "dexel_offset",
             "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_profile_enable",
             "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
-            "dexel_autotune", "dexel_status_string", "dexel_last_error"]
+            "dexel_autotune", "dexel_status_string", "dexel_last_error",
+            "dexel_csg_workspace_size", "dexel_csg"]
 NVARIANT = 4
 NPROF = 11
 PROFILE_STAGES = ["column_gaps", "row_offset", "row_offset_replay", "neighbour",
@@ -182,6 +191,19 @@ def dexel_dilate(ctx, view, r, out, ws, stream=None, flags: int = 0) -> int:
 def dexel_erode(ctx, view, r, out, ws, stream=None, flags: int = 0) -> int:
     return lib.dexel_erode(ctx, ctypes.byref(view), float(r), ctypes.byref(out), _ptr(ws),
                            int(ws.numel()), _stream_ptr(stream), int(flags))
+
+
+def dexel_csg_workspace_size(ctx, view: dexel_grid_view) -> int:
+    b = c_size_t()
+    st = lib.dexel_csg_workspace_size(ctx, ctypes.byref(view), ctypes.byref(b))
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    return int(b.value)
+
+
+def dexel_csg(ctx, a, b, op, out, ws: torch.Tensor, stream=None, flags: int = 0) -> int:
+    return lib.dexel_csg(ctx, ctypes.byref(a), ctypes.byref(b), int(op), ctypes.byref(out), _ptr(ws),
+                         int(ws.numel()), _stream_ptr(stream), int(flags))
 
 
 def dexel_batch_workspace_size(ctx, items, cap_hint: int = 0) -> int:

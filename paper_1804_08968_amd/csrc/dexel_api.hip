@@ -652,6 +652,81 @@ dexel_status dexel_workspace_stats(dexel_ctx* ctx, const void* ws, int64_t* stat
     return DEXEL_OK;
 }
 
+// Workspace of dexel_csg: header, counts, scan, block sums (256-byte aligned).
+static size_t csg_layout(int64_t ncols, size_t* cnt, size_t* scan, size_t* bsum) {
+    size_t o = align_up(sizeof(WsHeader));
+    *cnt = o;
+    o = align_up(o + 4 * (size_t)ncols);
+    *scan = o;
+    o = align_up(o + 8 * (size_t)(ncols + 1));
+    *bsum = o;
+    o = align_up(o + 8 * (size_t)((ncols + 1023) / 1024 + 2));
+    return o;
+}
+
+dexel_status dexel_csg_workspace_size(dexel_ctx* ctx, const dexel_grid_view* a, size_t* bytes) {
+    if (!ctx || !bytes) return DEXEL_ERR_INVALID;
+    dexel_status st = check_view(ctx, a);
+    if (st != DEXEL_OK) return st;
+    size_t c, q, b;
+    *bytes = csg_layout((int64_t)a->nx * a->ny, &c, &q, &b);
+    return DEXEL_OK;
+}
+
+dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_grid_view* b, int32_t op,
+                       dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    ctx->err.clear();
+    dexel_status st = check_view(ctx, a);
+    if (st != DEXEL_OK) return st;
+    st = check_view(ctx, b);
+    if (st != DEXEL_OK) return st;
+    if (!out) return fail(ctx, DEXEL_ERR_INVALID, "null output");
+    if (a->nx != b->nx || a->ny != b->ny || out->nx != a->nx || out->ny != a->ny)
+        return fail(ctx, DEXEL_ERR_INVALID, "the two inputs and the output must have the same nx, ny");
+    if (op < DEXEL_CSG_UNION || op > DEXEL_CSG_DIFFERENCE) return fail(ctx, DEXEL_ERR_INVALID, "unknown CSG op");
+    if (flags & ~(DEXEL_FLAG_SYNC | DEXEL_FLAG_VALIDATE)) return fail(ctx, DEXEL_ERR_INVALID, "unknown flags");
+    if (flags & DEXEL_FLAG_VALIDATE)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "dexel_csg does not validate its inputs");
+    if (!out->col_ptr || !out->nseg_out || !out->status)
+        return fail(ctx, DEXEL_ERR_INVALID, "null output col_ptr, nseg_out or status");
+    if (out->cap_seg < 0 || (out->cap_seg > 0 && !out->z))
+        return fail(ctx, DEXEL_ERR_INVALID, "bad output capacity or null output z");
+    if (((uintptr_t)out->z) % 8 != 0) return fail(ctx, DEXEL_ERR_INVALID, "output z must be 8-byte aligned");
+    if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
+    if (((uintptr_t)ws) % 256 != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
+    const int64_t ncols = (int64_t)a->nx * a->ny;
+    size_t o_cnt, o_scan, o_bsum;
+    if (csg_layout(ncols, &o_cnt, &o_scan, &o_bsum) > ws_bytes)
+        return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than dexel_csg_workspace_size");
+    HIP_TRY(hipSetDevice(ctx->device));
+    char* w = (char*)ws;
+    dexel::CsgArgs g{};
+    g.a_ptr = a->col_ptr;
+    g.a_z = (const float2*)a->z;
+    g.b_ptr = b->col_ptr;
+    g.b_z = (const float2*)b->z;
+    g.ncols = ncols;
+    g.op = op;
+    g.hdr = (WsHeader*)w;
+    g.cnt = (int32_t*)(w + o_cnt);
+    g.scan = (int64_t*)(w + o_scan);
+    g.bsum = (int64_t*)(w + o_bsum);
+    g.out_ptr = out->col_ptr;
+    g.out_z = (float2*)out->z;
+    g.cap = out->cap_seg;
+    g.out_nseg = out->nseg_out;
+    g.out_status = out->status;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(dexel::launch_csg(g, s));
+    if (!(flags & DEXEL_FLAG_SYNC)) return DEXEL_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t dst = 0;
+    HIP_TRY(hipMemcpy(&dst, out->status, sizeof(dst), hipMemcpyDeviceToHost));
+    if (dst != 0) return fail(ctx, (dexel_status)dst, "device status " + std::to_string(dst));
+    return DEXEL_OK;
+}
+
 const char* dexel_status_string(dexel_status s) {
     switch (s) {
         case DEXEL_OK: return "ok";

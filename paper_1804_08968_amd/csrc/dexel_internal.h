@@ -129,4 +129,27 @@ constexpr int NVARIANT = 4;
 hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant);
 hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s);
 
+// Per-column Boolean operation of two grids (dexel_csg).  Workspace: header,
+// counts [ncols], scan [ncols + 1], block sums.
+enum CsgOp { CSG_UNION = 0, CSG_INTERSECT = 1, CSG_DIFFERENCE = 2 };
+struct CsgArgs {
+    const int64_t* a_ptr;
+    const float2* a_z;
+    const int64_t* b_ptr;
+    const float2* b_z;
+    int64_t ncols;
+    int32_t op;
+    int32_t pad;
+    WsHeader* hdr;
+    int32_t* cnt;
+    int64_t* scan;
+    int64_t* bsum;
+    int64_t* out_ptr;
+    float2* out_z;
+    int64_t cap;
+    int64_t* out_nseg;
+    int32_t* out_status;
+};
+hipError_t launch_csg(const CsgArgs& a, hipStream_t s);
+
 }  // namespace dexel

@@ -2171,6 +2171,141 @@ hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// per-column Boolean operations (CSG)
+// ---------------------------------------------------------------------------
+//
+// Regularised union, intersection and difference of two canonical grids,
+// column by column (CSG in dexel space, Sec. 2 item (3); the shell of Sec. 4
+// "3D Printing" is the difference of a dilation and an erosion).  One lane
+// per column sweeps both sorted lists once.  Input intervals of zero length
+// have no interior and are skipped; touching result pieces are one interval;
+// no piece of zero length is emitted.  Endpoints are copied, never computed.
+// The sweep runs once to count (then a scan) and once to write.
+
+template <int OP, bool WRITE>
+__device__ int csg_column(const CsgArgs& A, int64_t c, float2* dst) {
+    const int64_t a0 = gld(&A.a_ptr[c]), a1 = gld(&A.a_ptr[c + 1]);
+    const int64_t b0 = gld(&A.b_ptr[c]), b1 = gld(&A.b_ptr[c + 1]);
+    const float2* az = A.a_z + a0;
+    const float2* bz = A.b_z + b0;
+    const int na = (int)(a1 - a0), nb = (int)(b1 - b0);
+    const float2 none = make_float2(DX_INF, DX_INF);
+    int k = 0;
+    auto put = [&](float lo, float hi) {
+        if (WRITE) gst(&dst[k], make_float2(lo, hi));
+        ++k;
+    };
+    if (OP == CSG_UNION) {
+        // merge by start; a piece starting at or before the open interval's
+        // end extends it
+        int i = 0, j = 0;
+        float2 va = na > 0 ? gld(&az[0]) : none, vb = nb > 0 ? gld(&bz[0]) : none;
+        float2 cur = make_float2(0.f, 0.f);
+        bool open = false;
+        while (i < na || j < nb) {
+            const bool takeA = j >= nb || (i < na && va.x <= vb.x);
+            const float2 v = takeA ? va : vb;
+            if (takeA) {
+                ++i;
+                va = i < na ? gld(&az[i]) : none;
+            } else {
+                ++j;
+                vb = j < nb ? gld(&bz[j]) : none;
+            }
+            if (!(v.x < v.y)) continue;
+            if (open && v.x <= cur.y) {
+                cur.y = fmaxf(cur.y, v.y);
+            } else {
+                if (open) put(cur.x, cur.y);
+                cur = v;
+                open = true;
+            }
+        }
+        if (open) put(cur.x, cur.y);
+    } else if (OP == CSG_INTERSECT) {
+        // overlap of the current pair; the piece ending first is done
+        int i = 0, j = 0;
+        float2 va = na > 0 ? gld(&az[0]) : none, vb = nb > 0 ? gld(&bz[0]) : none;
+        while (i < na && j < nb) {
+            const float lo = fmaxf(va.x, vb.x), hi = fminf(va.y, vb.y);
+            if (lo < hi) put(lo, hi);
+            if (va.y < vb.y) {
+                ++i;
+                va = i < na ? gld(&az[i]) : none;
+            } else {
+                ++j;
+                vb = j < nb ? gld(&bz[j]) : none;
+            }
+        }
+    } else {
+        // A minus B: each interval of A, cut by the intervals of B over it
+        int j = 0;
+        for (int i = 0; i < na; ++i) {
+            const float2 va = gld(&az[i]);
+            if (!(va.x < va.y)) continue;
+            float lo = va.x;
+            while (j < nb && gld(&bz[j]).y <= lo) ++j;
+            for (int q = j; q < nb; ++q) {
+                const float2 vb = gld(&bz[q]);
+                if (!(vb.x < va.y)) break;
+                if (!(vb.x < vb.y)) continue;
+                if (vb.x > lo) put(lo, vb.x);
+                lo = fmaxf(lo, vb.y);
+            }
+            if (lo < va.y) put(lo, va.y);
+        }
+    }
+    return k;
+}
+
+template <int OP>
+__device__ __forceinline__ int csg_count(const CsgArgs& A, int64_t c) {
+    return csg_column<OP, false>(A, c, nullptr);
+}
+
+constexpr int CSG_T = 256;
+
+__global__ void __launch_bounds__(CSG_T) k_csg_count(CsgArgs A) {
+    const int64_t c = (int64_t)blockIdx.x * CSG_T + threadIdx.x;
+    if (c >= A.ncols) return;
+    int n;
+    if (A.op == CSG_UNION) n = csg_count<CSG_UNION>(A, c);
+    else if (A.op == CSG_INTERSECT) n = csg_count<CSG_INTERSECT>(A, c);
+    else n = csg_count<CSG_DIFFERENCE>(A, c);
+    gst(&A.cnt[c], n);
+}
+
+// Output column pointers always; intervals when the total fits the capacity;
+// column 0's lane writes the end pointer, the count and the status.
+__global__ void __launch_bounds__(CSG_T) k_csg_write(CsgArgs A) {
+    const int64_t c = (int64_t)blockIdx.x * CSG_T + threadIdx.x;
+    if (c >= A.ncols) return;
+    const int64_t total = gld(&A.scan[A.ncols]);
+    const int64_t off = gld(&A.scan[c]);
+    gst(&A.out_ptr[c], off);
+    if (c == 0) {
+        gst(&A.out_ptr[A.ncols], total);
+        gst(A.out_nseg, total);
+        gst(A.out_status, total > A.cap ? (int32_t)DEXEL_ERR_CAPACITY : (int32_t)DEXEL_OK);
+    }
+    if (total > A.cap) return;
+    float2* dst = A.out_z + off;
+    if (A.op == CSG_UNION) csg_column<CSG_UNION, true>(A, c, dst);
+    else if (A.op == CSG_INTERSECT) csg_column<CSG_INTERSECT, true>(A, c, dst);
+    else csg_column<CSG_DIFFERENCE, true>(A, c, dst);
+}
+
+hipError_t launch_csg(const CsgArgs& a, hipStream_t s) {
+    const unsigned nb = (unsigned)((a.ncols + CSG_T - 1) / CSG_T);
+    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, a.hdr, (int32_t*)nullptr, 0);
+    hipLaunchKernelGGL(k_csg_count, dim3(nb), dim3(CSG_T), 0, s, a);
+    hipError_t e = scan_counts(a.cnt, a.ncols, a.bsum, a.scan, a.hdr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_csg_write, dim3(nb), dim3(CSG_T), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s) {
     hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, hdr, shape_status, nitems);
     return hipGetLastError();

@@ -66,7 +66,8 @@ def test_constants_match_binding():
     for name in ("DEXEL_OK", "DEXEL_ERR_INVALID", "DEXEL_ERR_NOT_CANONICAL", "DEXEL_ERR_CAPACITY",
                  "DEXEL_ERR_WORKSPACE", "DEXEL_ERR_HIP", "DEXEL_ERR_UNSUPPORTED", "DEXEL_DILATE",
                  "DEXEL_ERODE", "DEXEL_OPEN", "DEXEL_CLOSE", "DEXEL_FLAG_SYNC",
-                 "DEXEL_FLAG_VALIDATE"):
+                 "DEXEL_FLAG_VALIDATE", "DEXEL_CSG_UNION", "DEXEL_CSG_INTERSECT",
+                 "DEXEL_CSG_DIFFERENCE"):
         assert name in c, name
         assert getattr(binding, name) == c[name], name
     assert c["DEXEL_NVARIANT"] == binding.NVARIANT
@@ -111,6 +112,8 @@ def test_null_arguments_rejected_on_host(lib):
     assert b.lib.dexel_set_variant(None, 0) == inv
     assert b.lib.dexel_profile_enable(None, 1) == inv
     assert b.lib.dexel_autotune(None, 0, None, None, 0, None, 1, None, None) == inv
+    assert b.lib.dexel_csg_workspace_size(None, ctypes.byref(view), ctypes.byref(nbytes)) == inv
+    assert b.lib.dexel_csg(None, ctypes.byref(view), ctypes.byref(view), 0, None, None, 0, None, 0) == inv
     b.lib.dexel_ctx_destroy(None)          # no-op
 
 
