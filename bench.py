@@ -7,7 +7,7 @@ intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
 method's own scalability experiments.  One step = one closing of the whole
 grid, input resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell] [--no-cpu-baseline]
 
 value   = input intervals offset per second (intervals of the input grid per
           operation, summed over the step's operations, divided by the step
@@ -82,6 +82,9 @@ WORKLOADS = {
                ops=[("dilate", 3.0)]),
     "c4": dict(desc="batched dilation of 64 primitive soups (sides log-uniform 128..1024, "
                     "20..300 spheres/boxes, per-shape radius U[2,32])", ops=[]),
+    "shell": dict(desc="shell (dilation minus erosion, then a per-column difference) r=4 of the "
+                       "512x512 soup of 1350 spheres/boxes, the grid size and radius of the paper's "
+                       "shell figure", ops=[]),
     "c5": dict(desc="served stream of dilate/erode/open/close requests (r U[1,24], 30% chained "
                     "on the session's previous result) over 16 seeded shapes, sides log-uniform "
                     "256..2048, half primitive soups, half gyroids; Poisson arrivals at 0.5, 0.9 "
@@ -157,6 +160,139 @@ def cpu_baseline(grid, ops, budget_s=20.0):
             "sample": f"{op} r={r} on a {n}x{n} tile of output columns ({ncols_s} columns, "
                       f"{segs:.0f} input-interval equivalents at {per_col:.2f} per column), "
                       f"{dt:.2f} s"}
+
+
+def csg_bytes(ncols, na, nb, nout):
+    """Algorithmic bytes of one dexel_csg: both inputs read once, the output
+    written once (CSR offsets 8 B per column, intervals 8 B), per-column
+    counts written and read (4 B each) and the scan written and read (8 B)."""
+    return 3 * 8 * (ncols + 1) + 8 * (na + nb + nout) + 2 * 4 * ncols + 2 * 8 * (ncols + 1)
+
+
+def run_shell(args, dx, torch):
+    """shell: dilation, erosion and the per-column difference of the 512^2
+    soup at r = 4, all on the device, inputs resident in HBM."""
+    import oracle
+    from oracle import csg as ocsg
+    r = 4.0
+    t0 = time.perf_counter()
+    grid = make_grid("c2")
+    eng = dx.Engine(0)
+    dg = dx.DeviceGrid.from_host(grid)
+    ncols = grid.nx * grid.ny
+    pd_, pe_ = dx.Plan(eng, dg, r, "dilate"), dx.Plan(eng, dg, r, "erode")
+    variants = [pd_.autotune(reps=2)[0], pe_.autotune(reps=2)[0]]
+    pass_stats = []
+    for p in (pd_, pe_):
+        p.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+        pass_stats.append((dg.nseg, dx.dexel_workspace_stats(eng.ctx, eng.workspace(p.ws_bytes))))
+    nd, ne = pd_.nseg_out, pe_.nseg_out
+    va = dx.make_view(grid.nx, grid.ny, pd_.col, pd_.z, nd)
+    vb = dx.make_view(grid.nx, grid.ny, pe_.col, pe_.z, ne)
+    cap = nd + ne + 1
+    col = torch.empty(ncols + 1, dtype=torch.int64, device="cuda")
+    z = torch.empty(2 * cap, dtype=torch.float32, device="cuda")
+    nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = dx.make_out(grid.nx, grid.ny, col, z, nout, status)
+    ws_csg = torch.empty(dx.dexel_csg_workspace_size(eng.ctx, va), dtype=torch.uint8, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+
+    def step(i=None):
+        pd_.enqueue()
+        pe_.enqueue()
+        if i is not None:
+            ev[i][0].record()
+        st = dx.dexel_csg(eng.ctx, va, vb, dx.DEXEL_CSG_DIFFERENCE, out, ws_csg, None, 0)
+        if i is not None:
+            ev[i][1].record()
+        if st != dx.DEXEL_OK:
+            raise RuntimeError(f"dexel_csg enqueue failed: {st}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    dx.dexel_profile_enable(eng.ctx, False)
+    prof_ms, _ = dx.dexel_profile_read(eng.ctx, reset=True)
+    for p in (pd_, pe_):
+        if p.status() != 0:
+            raise RuntimeError(f"device status {p.status()}")
+    if int(status.item()) != 0:
+        raise RuntimeError(f"dexel_csg status {int(status.item())}")
+    nshell = int(nout.item())
+    ms_step = (te - ts) * 1000.0 / args.steps
+    csg_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    stages = dx.PROFILE_STAGES
+    per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
+    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
+    dom = max(modelled, key=per_step.get)
+    dom_ms = per_step[dom] / 2.0
+    dom_bytes = sum(kernel_bytes(dom, ncols, n_in, st) for n_in, st in pass_stats) / 2.0
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    cb = csg_bytes(ncols, nd, ne, nshell)
+    csg_gbs = cb / (csg_ms / 1000.0) / 1e9
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": grid.nseg / (ms_step / 1000.0),
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"shell: {WORKLOADS['shell']['desc']}", "grid": f"{grid.nx}x{grid.ny}",
+                   "nseg_in": grid.nseg, "r": r, "nseg_dilation": nd, "nseg_erosion": ne,
+                   "nseg_shell": nshell},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)], "kernel_ms": round(dom_ms, 4),
+                     "bytes_per_launch": int(dom_bytes)},
+        "csg": {"bound": "hbm", "achieved": round(csg_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(csg_gbs / HBM_PEAK_GBS, 5), "kernels": "k_csg_count, scan, k_csg_write",
+                "ms_per_call": round(csg_ms, 4), "bytes_per_call": int(cb)},
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "variants": variants,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's shell on a square tile of output columns, grown until
+        # it takes a few seconds
+        n, best = 8, None
+        while True:
+            x0, y0 = grid.nx // 2 - n // 2, grid.ny // 2 - n // 2
+            cols = (np.arange(y0, y0 + n)[:, None] * grid.nx + np.arange(x0, x0 + n)[None, :]).ravel()
+            tc = time.perf_counter()
+            cd, zd = oracle.offset_columns(grid, r, "dilate", "f64", cols=cols)
+            ce, ze = oracle.offset_columns(grid, r, "erode", "f64", cols=cols)
+            od, oe = np.concatenate([[0], np.cumsum(cd)]), np.concatenate([[0], np.cumsum(ce)])
+            for k in range(cols.size):
+                ocsg.column_op(zd[2 * od[k]: 2 * od[k + 1]], ze[2 * oe[k]: 2 * oe[k + 1]], "difference")
+            dt = time.perf_counter() - tc
+            best = (cols.size, dt, n)
+            if dt * 4 > args.cpu_budget or n >= min(grid.nx, grid.ny):
+                break
+            n *= 2
+        nc, dt, n = best
+        per_col = grid.nseg / float(ncols)
+        line["cpu_baseline"] = {"value": nc * per_col / dt, "unit": "input segments/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"shell r={r} on a {n}x{n} tile of output columns ({nc} "
+                                          f"columns, {nc * per_col:.0f} input-interval equivalents), "
+                                          f"{dt:.2f} s"}
+    print(json.dumps(line), flush=True)
+    eng.close()
 
 
 def pct(v, q):
@@ -396,6 +532,8 @@ def main():
         return run_batch(args, dx, torch)
     if args.workload == "c5":
         return run_serving(args, dx, torch)
+    if args.workload == "shell":
+        return run_shell(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)
