@@ -355,7 +355,8 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
 // * else, while the partial union is a single interval [L, E], only a
 //   leading run of chords starting below L and a trailing run ending above E
 //   can change it, and are inserted;
-// * otherwise the column's chords are merged with the list.
+// * otherwise the column's chords are merged with the list (in an erosion,
+//   a one-interval column against a union of two rays only moves the rays).
 // Visit v of a row window, nearest columns first: x, x-1, x+1, x-2, x+2, ...
 __device__ __forceinline__ int visit_col(int x, int v) {
     const int t = (v + 1) >> 1;
@@ -454,6 +455,24 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
         const int cnt = E ? m + 1 : m;
         // empty columns and hulls were handled in pass 1
         if (m == 0 || gc <= 2.f * h) continue;
+        // erosion of a one-interval column [a, b]: its complement is the two
+        // rays (-inf, a] and [b, +inf); while the partial union is two rays
+        // too, the chords (-inf, a + h] and [b - h, +inf) only move the rays'
+        // ends, and the rays merge into the whole line once they meet
+        if (E && m == 1 && n == 2) {
+            const float2 u0 = U.get(0), u1 = U.get(1);
+            if (u0.x == -DX_INF && u1.y == DX_INF) {
+                const float lo = fmaxf(u0.y, ec4.x + h), hi = fminf(u1.x, ec4.w - h);
+                if (hi <= lo) {
+                    U.set(0, make_float2(-DX_INF, DX_INF));
+                    n = 1;
+                } else {
+                    U.set(0, make_float2(-DX_INF, lo));
+                    U.set(1, make_float2(hi, DX_INF));
+                }
+                continue;
+            }
+        }
         if (n != 1) {
             n = merge_column<E>(P, U, n, bc, m, cnt, h);
             if (n < 0) return -1;
