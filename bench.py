@@ -7,7 +7,7 @@ intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
 method's own scalability experiments.  One step = one closing of the whole
 grid, input resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices] [--no-cpu-baseline]
 
 value   = input intervals offset per second (intervals of the input grid per
           operation, summed over the step's operations, divided by the step
@@ -82,6 +82,9 @@ WORKLOADS = {
                ops=[("dilate", 3.0)]),
     "c4": dict(desc="batched dilation of 64 primitive soups (sides log-uniform 128..1024, "
                     "20..300 spheres/boxes, per-shape radius U[2,32])", ops=[]),
+    "slices": dict(desc="2D offsets (disk dilation of a slice of parallel segments) r=16 of the 2048 "
+                        "rows of the 2048x2048 gyroid lattice as 2048 separate 2048x1 slices, one "
+                        "batched enqueue", ops=[]),
     "shell": dict(desc="shell (dilation minus erosion, then a per-column difference) r=4 of the "
                        "512x512 soup of 1350 spheres/boxes, the grid size and radius of the paper's "
                        "shell figure", ops=[]),
@@ -291,6 +294,94 @@ def run_shell(args, dx, torch):
                                 "sample": f"shell r={r} on a {n}x{n} tile of output columns ({nc} "
                                           f"columns, {nc * per_col:.0f} input-interval equivalents), "
                                           f"{dt:.2f} s"}
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
+def run_slices(args, dx, torch):
+    """slices: the 2D method of Sec. 3.2 on many slices in one batch."""
+    import oracle
+    from synth import gen
+    r = 16.0
+    t0 = time.perf_counter()
+    g = gen.gyroid_grid(0)
+    nx, ny = g.nx, g.ny
+    eng = dx.Engine(0)
+    cp = torch.as_tensor(g.col_ptr, dtype=torch.int64).cuda()
+    z = torch.as_tensor(g.z.reshape(-1), dtype=torch.float32).cuda()
+    slices = []
+    for y in range(ny):
+        b0, b1 = int(g.col_ptr[y * nx]), int(g.col_ptr[(y + 1) * nx])
+        col = (cp[y * nx:(y + 1) * nx + 1] - b0).contiguous()
+        zz = z[2 * b0: 2 * b1] if b1 > b0 else torch.zeros(2, dtype=torch.float32, device="cuda")
+        slices.append(dx.DeviceGrid(nx, 1, col, zz))
+    bp = dx.BatchPlan(eng, slices, [r] * ny, ["dilate"] * ny)
+    chosen, _ = bp.autotune(reps=2)
+    print(f"[bench] slices ready ({time.perf_counter() - t0:.1f} s), variant {chosen}", file=sys.stderr,
+          flush=True)
+    bp.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+    st = dx.dexel_workspace_stats(eng.ctx, eng.workspace(bp.ws_bytes))
+    for _ in range(args.warmup):
+        bp.enqueue()
+    torch.cuda.synchronize()
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        bp.enqueue()
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    dx.dexel_profile_enable(eng.ctx, False)
+    prof_ms, _ = dx.dexel_profile_read(eng.ctx, reset=True)
+    bad = [s_ for s_ in bp.statuses() if s_ != 0]
+    if bad:
+        raise RuntimeError(f"device status {bad[0]}")
+    ms_step = (te - ts) * 1000.0 / args.steps
+    stages = dx.PROFILE_STAGES
+    per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
+    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
+    dom = max(modelled, key=per_step.get)
+    ncols = nx * ny
+    dom_bytes = kernel_bytes(dom, ncols, g.nseg, st)
+    achieved = dom_bytes / (per_step[dom] / 1000.0) / 1e9
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": g.nseg / (ms_step / 1000.0),
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"slices: {WORKLOADS['slices']['desc']}", "slices": ny,
+                   "columns_per_slice": nx, "nseg_in": g.nseg, "r": r,
+                   "nseg_out": sum(o for o in bp.nseg_out)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)],
+                     "kernel_ms": round(per_step[dom], 4), "bytes_per_launch": int(dom_bytes)},
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "variant": chosen,
+    }
+    if not args.no_cpu_baseline:
+        done, segs, tc = 0, 0, time.perf_counter()
+        for y in range(ny):
+            b0, b1 = int(g.col_ptr[y * nx]), int(g.col_ptr[(y + 1) * nx])
+            h = oracle.Grid(nx, 1, g.col_ptr[y * nx:(y + 1) * nx + 1] - b0,
+                            np.asarray(g.z, dtype=np.float64).reshape(-1)[2 * b0: 2 * b1])
+            oracle.offset(h, r, "dilate", "f64")
+            done += 1
+            segs += b1 - b0
+            if time.perf_counter() - tc > args.cpu_budget / 2:
+                break
+        dt = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": segs / dt, "unit": "input segments/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"the first {done} slices in full ({segs} intervals), {dt:.2f} s"}
     print(json.dumps(line), flush=True)
     eng.close()
 
@@ -534,6 +625,8 @@ def main():
         return run_serving(args, dx, torch)
     if args.workload == "shell":
         return run_shell(args, dx, torch)
+    if args.workload == "slices":
+        return run_slices(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)

@@ -142,6 +142,18 @@ class Engine:
             raise DexelError(st, dexel_last_error(self.ctx))
         return DeviceGrid(a.nx, a.ny, col, z)
 
+    def offset_slices(self, slices, r: float, op: str = "dilate", stream=None):
+        """2D offsets of many dexel slices (Sec. 3.2: parallel segments on a
+        1D grid, offset by a disk), all in one batched enqueue.  A slice is a
+        DeviceGrid with ny == 1: the ball restricted to the slice's plane is
+        the disk and there is no other row, so the 3D kernels compute the 2D
+        offset exactly.  Returns one DeviceGrid per slice."""
+        slices = list(slices)
+        for g in slices:
+            if g.ny != 1:
+                raise ValueError("a slice is an nx x 1 grid")
+        return batch_offset(self, slices, [r] * len(slices), [op] * len(slices), stream=stream)
+
     def shell(self, grid: DeviceGrid, r: float) -> DeviceGrid:
         """Shell of thickness about 2r around the surface: the dilation minus
         the erosion (Sec. 4, "3D Printing"), three library calls on the device."""

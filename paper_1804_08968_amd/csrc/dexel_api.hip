@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -63,13 +64,14 @@ struct Layout {
     size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
-    std::vector<size_t> lut_off;  // per item: byte offset of its radius table
+    std::vector<size_t> lut_off;  // per item: byte offset of its radius table (shared per radius)
 };
 
 struct ItemInfo {
     int64_t ncols;
     int R, d2max;
     bool chain;
+    uint32_t rbits;  // the radius' float bits: items of one radius share its table
 };
 
 int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
@@ -103,7 +105,16 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.sbase1 = take(8 * (n + 1));
     L.sbase2 = take(8 * (n + 1));
     L.lut_off.resize(n);
-    for (size_t i = 0; i < n; ++i) L.lut_off[i] = take(sizeof(float) * (size_t)(items[i].d2max + 1));
+    std::map<uint32_t, size_t> lut_of_radius;
+    for (size_t i = 0; i < n; ++i) {
+        auto f = lut_of_radius.find(items[i].rbits);
+        if (f != lut_of_radius.end()) {
+            L.lut_off[i] = f->second;
+        } else {
+            L.lut_off[i] = take(sizeof(float) * (size_t)(items[i].d2max + 1));
+            lut_of_radius[items[i].rbits] = L.lut_off[i];
+        }
+    }
     L.luts = n ? L.lut_off[0] : o;
     L.gap = take(4 * g);
     L.ends = take(16 * g);
@@ -215,6 +226,7 @@ dexel_status check_items(dexel_ctx* ctx, int32_t n, const dexel_batch_item* item
         ii.ncols = (int64_t)it.in.nx * it.in.ny;
         radius_params(it.r, &ii.R, &ii.d2max);
         ii.chain = is_chain(it.op);
+        ii.rbits = float_bits(it.r);
         info->push_back(ii);
     }
     return DEXEL_OK;
@@ -384,7 +396,9 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     int64_t* zbase = (int64_t*)(w + L.zbase);
 
     HIP_TRY(dexel::launch_init_call(p1.hdr, p1.shape_status, n, s));
+    std::set<size_t> filled;  // shared radius tables already copied
     for (int32_t i = 0; i < n; ++i) {
+        if (!filled.insert(L.lut_off[i]).second) continue;
         float* lut = lut_for(ctx, items[i].r, info[i].d2max);
         HIP_TRY(hipMemcpyAsync(w + L.lut_off[i], lut, sizeof(float) * (size_t)(info[i].d2max + 1),
                                hipMemcpyHostToDevice, s));

@@ -148,3 +148,29 @@ def test_c2_r32_sampled(engine, oracle_lib, op):
 def test_gyroid_small_close(engine, oracle_lib):
     g = gen.gyroid_grid(0, n=128, height=256.0)
     check(engine, oracle_lib, g, 16.0, "close", label="gyroid128 close")
+
+
+@pytest.mark.parametrize("op", ["dilate", "erode", "close"])
+def test_slices_2d(engine, oracle_lib, op):
+    """2D offsets of many slices (nx x 1 grids, Sec. 3.2) in one batched
+    enqueue, each bit-exact against the oracle's float32 model of that slice
+    and within tolerance of FP64."""
+    rng = np.random.default_rng(21)
+    hosts = []
+    for k in range(24):
+        nx = int(rng.integers(1, 300))
+        hosts.append(random_grid(rng, nx, 1, 300.0, max_per_col=6, p_empty=0.3))
+    import paper_1804_08968_amd as dx
+    r = 6.5
+    print(f"[case] slices {op} r={r} n={len(hosts)}", flush=True)
+    outs = engine.offset_slices([dx.DeviceGrid.from_host(h) for h in hosts], r, op)
+    k = 2 if op in ("open", "close") else 1
+    for h, o in zip(hosts, outs):
+        col, z = o.to_host()
+        z = z.astype(np.float64)
+        ref32 = oracle_lib.run(h, r, op, "f32model")
+        assert np.array_equal(col, ref32.col_ptr)
+        assert np.array_equal(z, ref32.z)
+        ref = oracle_lib.run(h, r, op, "f64")
+        res = compare_columns(np.diff(ref.col_ptr), ref.z, np.diff(col), z, r, k=k)
+        assert res["failed"] == 0, res
