@@ -193,6 +193,27 @@ def primitives_grid(seed: int, n: int = 512, count: int = 1350, smin: float = 4.
                                    "size_range": [smin, smax]})
 
 
+def primitive_records(seed: int, n: int = 512, count: int = 1350, smin: float = 4.0,
+                      smax: float = 64.0, height: float | None = None) -> np.ndarray:
+    """The primitives of ``primitives_grid`` with the same arguments (same
+    random draws), as records (kind, a0, a1, a2, b0, b1, b2): kind 0 = ball
+    (a = centre, b0 = radius), kind 1 = box (a = low corner, b = high corner)."""
+    rng = np.random.default_rng(seed)
+    height = float(n if height is None else height)
+    kind = rng.random(count) < 0.5
+    centres = np.column_stack([rng.uniform(0, n, count), rng.uniform(0, n, count),
+                               rng.uniform(0, height, count)])
+    sizes = rng.uniform(smin, smax, size=(count, 3))
+    rec = np.zeros((count, 7), np.float64)
+    rec[kind, 0] = 0.0
+    rec[kind, 1:4] = centres[kind]
+    rec[kind, 4] = sizes[kind, 0] / 2.0
+    rec[~kind, 0] = 1.0
+    rec[~kind, 1:4] = centres[~kind] - sizes[~kind] / 2.0
+    rec[~kind, 4:7] = centres[~kind] + sizes[~kind] / 2.0
+    return rec
+
+
 def _gyroid_rows(args):
     """Canonical CSR of gyroid rows [yb, ye) (worker for gyroid_grid)."""
     n, H, period, t, ph, yb, ye = args
