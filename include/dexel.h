@@ -158,6 +158,29 @@ dexel_status dexel_csg_workspace_size(dexel_ctx* ctx, const dexel_grid_view* a, 
 dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_grid_view* b, int32_t op,
                        dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* Dexelisation of analytic primitives into an nx x ny grid (Sec. 1 and Sec.
+ * 3.1, "Dexel Representation": the intersections of a solid with parallel
+ * rays from a uniform 2D grid).  The rays are the z-parallel lines through
+ * the cell centres (x + 0.5, y + 0.5).  `prims` (device, 8-byte aligned)
+ * holds nprims records of 7 doubles (kind, a0, a1, a2, b0, b1, b2):
+ *   DEXEL_PRIM_BALL: centre a, radius b0; meets the ray of a cell whose
+ *     squared lateral distance rho2 to the centre is below b0^2, in the
+ *     closed chord [a2 - h, a2 + h], h = sqrt(b0^2 - rho2);
+ *   DEXEL_PRIM_BOX: corners a <= b; meets the rays of the cells with
+ *     ceil(a0 - 0.5) <= x <= floor(b0 - 0.5) and ceil(a1 - 0.5) <= y <=
+ *     floor(b1 - 0.5) (the cell centre lies in the footprint), in [a2, b2].
+ * Chord ends are computed in float64 (each operation rounded once), rounded
+ * once to float32, and merged per column where they overlap or touch; the
+ * result is canonical.  Values must be finite and within float32 range.  A
+ * column may hold at most 64 intervals (else DEXEL_ERR_UNSUPPORTED in
+ * out->status); an unknown kind gives DEXEL_ERR_INVALID there.  `out` and
+ * `ws` (dexel_dexelize_workspace_size bytes, 256-byte aligned) as for
+ * dexel_csg; DEXEL_FLAG_VALIDATE is not supported. */
+typedef enum { DEXEL_PRIM_BALL = 0, DEXEL_PRIM_BOX = 1 } dexel_prim_kind;
+dexel_status dexel_dexelize_workspace_size(dexel_ctx* ctx, int32_t nx, int32_t ny, size_t* bytes);
+dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double* prims, int32_t nprims,
+                            dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags);
+
 /* Workspace for dexel_batch_offset over `items` (the largest single-item
  * need, since items share the workspace in sequence). */
 dexel_status dexel_batch_workspace_size(dexel_ctx* ctx, int32_t n, const dexel_batch_item* items,

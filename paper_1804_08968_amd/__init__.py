@@ -19,7 +19,8 @@ from .binding import (  # noqa: F401
     dexel_status_string, dexel_workspace_need, dexel_workspace_size, dexel_workspace_stats,
     make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES, NVARIANT, dexel_autotune,
     dexel_set_variant, CSG_OPS, DEXEL_CSG_DIFFERENCE, DEXEL_CSG_INTERSECT, DEXEL_CSG_UNION,
-    dexel_csg, dexel_csg_workspace_size,
+    dexel_csg, dexel_csg_workspace_size, DEXEL_PRIM_BALL, DEXEL_PRIM_BOX, dexel_dexelize,
+    dexel_dexelize_workspace_size,
 )
 
 
@@ -153,6 +154,28 @@ class Engine:
             if g.ny != 1:
                 raise ValueError("a slice is an nx x 1 grid")
         return batch_offset(self, slices, [r] * len(slices), [op] * len(slices), stream=stream)
+
+    def dexelize(self, nx: int, ny: int, prims, stream=None, max_tries: int = 4) -> DeviceGrid:
+        """Dexel grid of the union of balls and boxes (dexel_dexelize).
+        prims: (n, 7) records (kind, a0, a1, a2, b0, b1, b2), host or device."""
+        p = torch.as_tensor(prims, dtype=torch.float64).reshape(-1, 7).to(self.device).contiguous()
+        ncols = int(nx) * int(ny)
+        ws = self.workspace(dexel_dexelize_workspace_size(self.ctx, nx, ny))
+        cap = max(1024, 2 * ncols)
+        for _ in range(max_tries):
+            col = torch.empty(ncols + 1, dtype=torch.int64, device=self.device)
+            z = torch.empty(2 * cap, dtype=torch.float32, device=self.device)
+            nout = torch.zeros(1, dtype=torch.int64, device=self.device)
+            status = torch.zeros(1, dtype=torch.int32, device=self.device)
+            out = make_out(nx, ny, col, z, nout, status)
+            st = dexel_dexelize(self.ctx, nx, ny, p, out, ws, stream, DEXEL_FLAG_SYNC)
+            if st == DEXEL_OK:
+                return DeviceGrid(nx, ny, col, z)
+            if st == DEXEL_ERR_CAPACITY:
+                cap = int(nout.item()) + 1
+                continue
+            raise DexelError(st, dexel_last_error(self.ctx))
+        raise DexelError(DEXEL_ERR_CAPACITY, "retries exhausted")
 
     def shell(self, grid: DeviceGrid, r: float) -> DeviceGrid:
         """Shell of thickness about 2r around the surface: the dilation minus

@@ -35,6 +35,7 @@ DEXEL_FLAG_VALIDATE = 2
 DEXEL_CSG_UNION, DEXEL_CSG_INTERSECT, DEXEL_CSG_DIFFERENCE = 0, 1, 2
 CSG_OPS = {"union": DEXEL_CSG_UNION, "intersect": DEXEL_CSG_INTERSECT,
            "difference": DEXEL_CSG_DIFFERENCE}
+DEXEL_PRIM_BALL, DEXEL_PRIM_BOX = 0, 1
 
 
 class dexel_grid_view(ctypes.Structure):
@@ -81,6 +82,11 @@ lib.dexel_csg_workspace_size.restype = c_int
 lib.dexel_csg.argtypes = [c_void_p, _P(dexel_grid_view), _P(dexel_grid_view), c_int32,
                           _P(dexel_grid_out), c_void_p, c_size_t, c_void_p, ctypes.c_uint32]
 lib.dexel_csg.restype = c_int
+lib.dexel_dexelize_workspace_size.argtypes = [c_void_p, c_int32, c_int32, _P(c_size_t)]
+lib.dexel_dexelize_workspace_size.restype = c_int
+lib.dexel_dexelize.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_int32, _P(dexel_grid_out),
+                               c_void_p, c_size_t, c_void_p, ctypes.c_uint32]
+lib.dexel_dexelize.restype = c_int
 lib.dexel_profile_enable.argtypes = [c_void_p, c_int]
 lib.dexel_profile_enable.restype = c_int
 lib.dexel_profile_read.argtypes = [c_void_p, _P(ctypes.c_double), _P(c_int64), c_int]
@@ -102,7 +108,8 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_profile_enable",
             "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
             "dexel_autotune", "dexel_status_string", "dexel_last_error",
-            "dexel_csg_workspace_size", "dexel_csg"]
+            "dexel_csg_workspace_size", "dexel_csg", "dexel_dexelize_workspace_size",
+            "dexel_dexelize"]
 NVARIANT = 4
 NPROF = 11
 PROFILE_STAGES = ["column_gaps", "row_offset", "row_offset_replay", "neighbour",
@@ -204,6 +211,23 @@ def dexel_csg_workspace_size(ctx, view: dexel_grid_view) -> int:
 def dexel_csg(ctx, a, b, op, out, ws: torch.Tensor, stream=None, flags: int = 0) -> int:
     return lib.dexel_csg(ctx, ctypes.byref(a), ctypes.byref(b), int(op), ctypes.byref(out), _ptr(ws),
                          int(ws.numel()), _stream_ptr(stream), int(flags))
+
+
+def dexel_dexelize_workspace_size(ctx, nx: int, ny: int) -> int:
+    b = c_size_t()
+    st = lib.dexel_dexelize_workspace_size(ctx, int(nx), int(ny), ctypes.byref(b))
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    return int(b.value)
+
+
+def dexel_dexelize(ctx, nx, ny, prims: torch.Tensor, out, ws: torch.Tensor, stream=None,
+                   flags: int = 0) -> int:
+    """prims: float64 device tensor of shape (n, 7)."""
+    n = 0 if prims is None else int(prims.numel() // 7)
+    return lib.dexel_dexelize(ctx, int(nx), int(ny), _ptr(prims) if n else None, n,
+                              ctypes.byref(out), _ptr(ws), int(ws.numel()), _stream_ptr(stream),
+                              int(flags))
 
 
 def dexel_batch_workspace_size(ctx, items, cap_hint: int = 0) -> int:

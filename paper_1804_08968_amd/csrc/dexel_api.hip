@@ -741,6 +741,68 @@ dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_gri
     return DEXEL_OK;
 }
 
+dexel_status dexel_dexelize_workspace_size(dexel_ctx* ctx, int32_t nx, int32_t ny, size_t* bytes) {
+    if (!ctx || !bytes) return DEXEL_ERR_INVALID;
+    if (nx <= 0 || ny <= 0) return fail(ctx, DEXEL_ERR_INVALID, "nx and ny must be >= 1");
+    if ((int64_t)nx * ny >= ((int64_t)1 << 31) - 64)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "nx * ny must be below 2^31");
+    size_t c, q, b;
+    *bytes = csg_layout((int64_t)nx * ny, &c, &q, &b);
+    return DEXEL_OK;
+}
+
+dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double* prims, int32_t nprims,
+                            dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    ctx->err.clear();
+    if (nx <= 0 || ny <= 0) return fail(ctx, DEXEL_ERR_INVALID, "nx and ny must be >= 1");
+    if ((int64_t)nx * ny >= ((int64_t)1 << 31) - 64)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "nx * ny must be below 2^31");
+    if (nprims < 0 || (nprims > 0 && !prims)) return fail(ctx, DEXEL_ERR_INVALID, "bad primitive list");
+    if (!out) return fail(ctx, DEXEL_ERR_INVALID, "null output");
+    if (out->nx != nx || out->ny != ny) return fail(ctx, DEXEL_ERR_INVALID, "output nx, ny differ");
+    if (flags & ~(DEXEL_FLAG_SYNC | DEXEL_FLAG_VALIDATE)) return fail(ctx, DEXEL_ERR_INVALID, "unknown flags");
+    if (flags & DEXEL_FLAG_VALIDATE)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "dexel_dexelize has no input to validate");
+    if (!out->col_ptr || !out->nseg_out || !out->status)
+        return fail(ctx, DEXEL_ERR_INVALID, "null output col_ptr, nseg_out or status");
+    if (out->cap_seg < 0 || (out->cap_seg > 0 && !out->z))
+        return fail(ctx, DEXEL_ERR_INVALID, "bad output capacity or null output z");
+    if (((uintptr_t)out->z) % 8 != 0) return fail(ctx, DEXEL_ERR_INVALID, "output z must be 8-byte aligned");
+    if (((uintptr_t)prims) % 8 != 0) return fail(ctx, DEXEL_ERR_INVALID, "primitives must be 8-byte aligned");
+    if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
+    if (((uintptr_t)ws) % 256 != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
+    const int64_t ncols = (int64_t)nx * ny;
+    size_t o_cnt, o_scan, o_bsum;
+    if (csg_layout(ncols, &o_cnt, &o_scan, &o_bsum) > ws_bytes)
+        return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than dexel_dexelize_workspace_size");
+    HIP_TRY(hipSetDevice(ctx->device));
+    char* w = (char*)ws;
+    dexel::DexArgs g{};
+    g.prims = prims;
+    g.nprims = nprims;
+    g.nx = nx;
+    g.ny = ny;
+    g.ncols = ncols;
+    g.hdr = (WsHeader*)w;
+    g.cnt = (int32_t*)(w + o_cnt);
+    g.scan = (int64_t*)(w + o_scan);
+    g.bsum = (int64_t*)(w + o_bsum);
+    g.out_ptr = out->col_ptr;
+    g.out_z = (float2*)out->z;
+    g.cap = out->cap_seg;
+    g.out_nseg = out->nseg_out;
+    g.out_status = out->status;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(dexel::launch_dexelize(g, s));
+    if (!(flags & DEXEL_FLAG_SYNC)) return DEXEL_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t dst = 0;
+    HIP_TRY(hipMemcpy(&dst, out->status, sizeof(dst), hipMemcpyDeviceToHost));
+    if (dst != 0) return fail(ctx, (dexel_status)dst, "device status " + std::to_string(dst));
+    return DEXEL_OK;
+}
+
 const char* dexel_status_string(dexel_status s) {
     switch (s) {
         case DEXEL_OK: return "ok";

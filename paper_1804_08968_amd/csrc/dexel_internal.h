@@ -152,4 +152,25 @@ struct CsgArgs {
 };
 hipError_t launch_csg(const CsgArgs& a, hipStream_t s);
 
+// Dexelisation of balls and boxes (dexel_dexelize).  Same workspace layout
+// as dexel_csg.
+struct DexArgs {
+    const double* prims;  // [nprims * 7] records (kind, a0, a1, a2, b0, b1, b2)
+    int32_t nprims;
+    int32_t nx, ny;
+    int32_t pad;
+    int64_t ncols;
+    WsHeader* hdr;
+    int32_t* cnt;
+    int64_t* scan;
+    int64_t* bsum;
+    int64_t* out_ptr;
+    float2* out_z;
+    int64_t cap;
+    int64_t* out_nseg;
+    int32_t* out_status;
+};
+constexpr int DEX_CAP = 64;  // most intervals one column may hold
+hipError_t launch_dexelize(const DexArgs& a, hipStream_t s);
+
 }  // namespace dexel

@@ -2325,6 +2325,107 @@ hipError_t launch_csg(const CsgArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// dexelisation of analytic primitives
+// ---------------------------------------------------------------------------
+//
+// The rays of a dexel structure are the z-parallel lines through the cell
+// centres (x + 0.5, y + 0.5) (Sec. 1; Sec. 3.1, "Dexel Representation").  A
+// ball (centre c, radius R) meets the ray of a cell when rho2 = (x + 0.5 -
+// cx)^2 + (y + 0.5 - cy)^2 is below R^2, in [cz - h, cz + h] with
+// h = sqrt(R^2 - rho2); a box [a, b] meets the rays of the cells with
+// ceil(ax - 0.5) <= x <= floor(bx - 0.5) (and likewise in y) in [az, bz].
+// Chord ends are computed in float64, each operation rounded once (no
+// contraction into fused multiply-adds), then rounded once to float32 and
+// merged into the column's canonical list (overlapping or touching
+// intervals join).  One lane per column, every primitive tested in turn
+// (the record loads are the same for the whole wave).  Run once to count,
+// once to write.
+
+// The chord of primitive record q on the ray of cell (x, y); false if none
+// (and *bad set for an unknown kind).
+__device__ bool dex_chord(const double* q, int x, int y, float* lo, float* hi, bool* bad) {
+#pragma clang fp contract(off)
+    const double kind = q[0];
+    const double px = (double)x + 0.5, py = (double)y + 0.5;
+    if (kind == 0.0) {
+        const double dx = px - q[1], dy = py - q[2];
+        const double rho2 = dx * dx + dy * dy;
+        const double R2 = q[4] * q[4];
+        if (!(rho2 < R2)) return false;
+        const double h = sqrt(R2 - rho2);
+        *lo = (float)(q[3] - h);
+        *hi = (float)(q[3] + h);
+        return true;
+    }
+    if (kind == 1.0) {
+        if (!((double)x >= ceil(q[1] - 0.5) && (double)x <= floor(q[4] - 0.5) &&
+              (double)y >= ceil(q[2] - 0.5) && (double)y <= floor(q[5] - 0.5)))
+            return false;
+        *lo = (float)q[3];
+        *hi = (float)q[6];
+        return true;
+    }
+    *bad = true;
+    return false;
+}
+
+template <bool WRITE>
+__global__ void __launch_bounds__(WG) k_dexelize(DexArgs A) {
+    __shared__ float2 lds[DEX_CAP * WG];
+    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const bool live = c < A.ncols;
+    const int y = live ? (int)(c / A.nx) : 0;
+    const int x = live ? (int)(c - (int64_t)y * A.nx) : 0;
+    LdsList U{&lds[threadIdx.x], DEX_CAP};
+    int n = 0;
+    bool bad = false, over = false;
+    for (int k = 0; k < A.nprims; ++k) {
+        float lo, hi;
+        if (!live || over) continue;
+        if (!dex_chord(A.prims + 7 * (int64_t)k, x, y, &lo, &hi, &bad)) continue;
+        const int m = lv_insert(U, n, lo, hi);
+        if (m < 0) over = true; else n = m;
+    }
+    if (!live) return;
+    if (bad) set_error(A.hdr, DEXEL_ERR_INVALID);
+    if (over) set_error(A.hdr, DEXEL_ERR_UNSUPPORTED);
+    if (!WRITE) {
+        gst(&A.cnt[c], over ? 0 : n);
+        return;
+    }
+    // after an error of the count pass the scan did not run: write nothing
+    if (A.hdr->abort) return;
+    const int64_t total = gld(&A.scan[A.ncols]);
+    const int64_t off = gld(&A.scan[c]);
+    gst(&A.out_ptr[c], off);
+    if (c == 0) {
+        gst(&A.out_ptr[A.ncols], total);
+        gst(A.out_nseg, total);
+    }
+    if (total > A.cap || over || bad) return;
+    for (int i = 0; i < n; ++i) gst(&A.out_z[off + i], U.get(i));
+}
+
+// The device status: an error of the count pass (unknown kind, a column past
+// DEX_CAP), else capacity.
+__global__ void k_dexelize_status(DexArgs A) {
+    const int st = A.hdr->status;
+    const int64_t total = A.scan[A.ncols];
+    A.out_status[0] = st != 0 ? st : (total > A.cap ? (int32_t)DEXEL_ERR_CAPACITY : (int32_t)DEXEL_OK);
+}
+
+hipError_t launch_dexelize(const DexArgs& a, hipStream_t s) {
+    const unsigned nb = (unsigned)((a.ncols + WG - 1) / WG);
+    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, a.hdr, (int32_t*)nullptr, 0);
+    hipLaunchKernelGGL(k_dexelize<false>, dim3(nb), dim3(WG), 0, s, a);
+    hipError_t e = scan_counts(a.cnt, a.ncols, a.bsum, a.scan, a.hdr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dexelize<true>, dim3(nb), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_dexelize_status, dim3(1), dim3(1), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s) {
     hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, hdr, shape_status, nitems);
     return hipGetLastError();

@@ -67,7 +67,7 @@ def test_constants_match_binding():
                  "DEXEL_ERR_WORKSPACE", "DEXEL_ERR_HIP", "DEXEL_ERR_UNSUPPORTED", "DEXEL_DILATE",
                  "DEXEL_ERODE", "DEXEL_OPEN", "DEXEL_CLOSE", "DEXEL_FLAG_SYNC",
                  "DEXEL_FLAG_VALIDATE", "DEXEL_CSG_UNION", "DEXEL_CSG_INTERSECT",
-                 "DEXEL_CSG_DIFFERENCE"):
+                 "DEXEL_CSG_DIFFERENCE", "DEXEL_PRIM_BALL", "DEXEL_PRIM_BOX"):
         assert name in c, name
         assert getattr(binding, name) == c[name], name
     assert c["DEXEL_NVARIANT"] == binding.NVARIANT
@@ -114,6 +114,8 @@ def test_null_arguments_rejected_on_host(lib):
     assert b.lib.dexel_autotune(None, 0, None, None, 0, None, 1, None, None) == inv
     assert b.lib.dexel_csg_workspace_size(None, ctypes.byref(view), ctypes.byref(nbytes)) == inv
     assert b.lib.dexel_csg(None, ctypes.byref(view), ctypes.byref(view), 0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_dexelize_workspace_size(None, 4, 4, ctypes.byref(nbytes)) == inv
+    assert b.lib.dexel_dexelize(None, 4, 4, None, 0, None, None, 0, None, 0) == inv
     b.lib.dexel_ctx_destroy(None)          # no-op
 
 

@@ -1,0 +1,125 @@
+"""GPU parity of dexel_dexelize (balls and boxes along cell-centre rays),
+through the C ABI.
+
+Chord ends are float64 operations rounded once each and then rounded once to
+float32 on both sides, so the bar is bit-exact: against the oracle
+(oracle/dexelize.py) on grids it finishes in seconds, and against the
+workload generator (which the CPU pins tie to the oracle) at full size.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dexelize as od
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _dx():
+    import paper_1804_08968_amd as dx
+    return dx
+
+
+def run(engine, nx, ny, prims):
+    col, z = engine.dexelize(nx, ny, np.asarray(prims, dtype=np.float64).reshape(-1, 7)).to_host()
+    return col, z.astype(np.float64)
+
+
+def random_prims(rng, n, count, smax):
+    prims = []
+    for _ in range(count):
+        if rng.random() < 0.5:
+            prims.append((od.BALL, *rng.uniform(-2, n + 2, 3), rng.uniform(0.3, smax), 0.0, 0.0))
+        else:
+            lo = rng.uniform(-2, n + 2, 3)
+            prims.append((od.BOX, *lo, *(lo + rng.uniform(0.0, 2 * smax, 3))))
+    return prims
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_sets(engine, seed):
+    """Several 64-column tiles with a ragged tail; footprints cross the border."""
+    rng = np.random.default_rng(seed)
+    nx, ny = 45, 23
+    prims = random_prims(rng, max(nx, ny), 40, 6.0)
+    print(f"[case] dexelize random seed {seed}", flush=True)
+    col, z = run(engine, nx, ny, prims)
+    rc, rz = od.dexelize(nx, ny, prims)
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z, rz)
+
+
+def test_exact_boundaries(engine):
+    """A ball whose radius reaches a neighbouring cell centre exactly (excluded:
+    the lateral test is strict), a box whose edges pass through cell centres
+    (included), a zero-height box, touching and overlapping chords."""
+    prims = [
+        (od.BALL, 2.5, 2.5, 0.0, 1.0, 0.0, 0.0),
+        (od.BOX, 4.5, 0.5, 3.0, 6.5, 1.5, 4.0),
+        (od.BOX, 0.5, 4.5, 7.0, 0.5, 4.5, 7.0),
+        (od.BOX, 4.5, 0.5, 4.0, 4.5, 0.5, 5.0),
+        (od.BALL, 5.5, 0.5, 6.0, 2.0, 0.0, 0.0),
+    ]
+    print("[case] dexelize boundaries", flush=True)
+    col, z = run(engine, 8, 6, prims)
+    rc, rz = od.dexelize(8, 6, prims)
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z, rz)
+    # the ball's only column is its own cell
+    c = 2 * 8 + 2
+    assert col[c + 1] - col[c] == 1 and list(z[2 * col[c]: 2 * col[c] + 2]) == [-1.0, 1.0]
+
+
+def test_empty(engine):
+    col, z = run(engine, 5, 3, np.zeros((0, 7)))
+    assert col.tolist() == [0] * 16
+
+
+def test_soup_full_size_equals_generator(engine):
+    """The 512^2 soup of 1350 primitives, built on the GPU, equals the
+    workload generator's grid bit for bit."""
+    rec = gen.primitive_records(0)
+    g = gen.primitives_grid(0)
+    print("[case] dexelize c2 soup", flush=True)
+    col, z = run(engine, 512, 512, rec)
+    assert np.array_equal(col, g.col_ptr)
+    assert np.array_equal(z, np.asarray(g.z, dtype=np.float64).reshape(-1))
+
+
+@pytest.mark.parametrize("i", [0, 7, 21])
+def test_batch_shapes_equal_generator(engine, i):
+    rng = np.random.default_rng(0)
+    for k in range(i + 1):   # the draws of batch_shapes(0), shape by shape
+        s = int(round(math.exp(rng.uniform(math.log(128), math.log(1024)))))
+        nprim = int(rng.integers(20, 301))
+        rng.uniform(2.0, 32.0)
+        sub = int(rng.integers(0, 2**31 - 1))
+    scale = s / 512.0
+    kw = dict(n=s, count=nprim, smin=4.0 * scale, smax=64.0 * scale, height=float(s))
+    g = gen.primitives_grid(sub, **kw)
+    print(f"[case] dexelize batch shape {i} side {s}", flush=True)
+    col, z = run(engine, s, s, gen.primitive_records(sub, **kw))
+    assert np.array_equal(col, g.col_ptr)
+    assert np.array_equal(z, np.asarray(g.z, dtype=np.float64).reshape(-1))
+
+
+def test_errors_reported(engine):
+    dx = _dx()
+    print("[case] dexelize errors", flush=True)
+    with pytest.raises(dx.DexelError) as e:
+        engine.dexelize(4, 4, [(7.0, 0, 0, 0, 1, 1, 1)])
+    assert e.value.status == dx.DEXEL_ERR_INVALID
+    # 70 separated boxes on one column: more than a column may hold
+    boxes = [(od.BOX, 0.0, 0.0, 10.0 * k, 1.0, 1.0, 10.0 * k + 1.0) for k in range(70)]
+    with pytest.raises(dx.DexelError) as e:
+        engine.dexelize(2, 2, boxes)
+    assert e.value.status == dx.DEXEL_ERR_UNSUPPORTED
+    # 60 fit; the engine retries past a small first capacity
+    boxes = [(od.BOX, 0.0, 0.0, 10.0 * k, 40.0, 40.0, 10.0 * k + 1.0) for k in range(60)]
+    col, z = run(engine, 40, 40, boxes)
+    rc, rz = od.dexelize(40, 40, boxes)
+    assert np.array_equal(col, rc) and np.array_equal(z, rz)
