@@ -7,7 +7,7 @@ intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
 method's own scalability experiments.  One step = one closing of the whole
 grid, input resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices|dexelize] [--no-cpu-baseline]
 
 value   = input intervals offset per second (intervals of the input grid per
           operation, summed over the step's operations, divided by the step
@@ -85,6 +85,8 @@ WORKLOADS = {
     "slices": dict(desc="2D offsets (disk dilation of a slice of parallel segments) r=16 of the 2048 "
                         "rows of the 2048x2048 gyroid lattice as 2048 separate 2048x1 slices, one "
                         "batched enqueue", ops=[]),
+    "dexelize": dict(desc="dexelisation on the GPU of a 2048x2048 soup of 5400 balls and boxes (sizes "
+                          "U[16,256], height 2048), rays through cell centres", ops=[]),
     "shell": dict(desc="shell (dilation minus erosion, then a per-column difference) r=4 of the "
                        "512x512 soup of 1350 spheres/boxes, the grid size and radius of the paper's "
                        "shell figure", ops=[]),
@@ -386,6 +388,103 @@ def run_slices(args, dx, torch):
     eng.close()
 
 
+# float64 operations of one ball test (two differences, three products, a sum,
+# a compare) and one box test (four differences, four roundings, four compares)
+DEX_FLOPS_PER_TEST = 7
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def dex_candidate_pairs(rec, n):
+    """(column, primitive) pairs whose column lies in the primitive's cell
+    bounding box (a ball's square of side 2R, a box's cell range), clipped to
+    the n x n grid: the tests an exact dexeliser with bounding-box culling
+    cannot skip."""
+    import numpy as np
+    rec = np.asarray(rec, dtype=np.float64)
+    ball = rec[:, 0] == 0.0
+    lo = np.where(ball[:, None], rec[:, 1:3] - rec[:, 4:5], rec[:, 1:3])
+    hi = np.where(ball[:, None], rec[:, 1:3] + rec[:, 4:5], rec[:, 4:6])
+    a = np.clip(np.ceil(lo - 0.5), 0, n - 1)
+    b = np.clip(np.floor(hi - 0.5), -1, n - 1)
+    w = np.maximum(b - a + 1, 0)
+    return int(np.sum(w[:, 0] * w[:, 1]))
+
+
+def run_dexelize(args, dx, torch):
+    """dexelize: primitives to a dexel grid on the device."""
+    from oracle import dexelize as od
+    from synth import gen
+    n, count = 2048, 5400
+    kw = dict(n=n, count=count, smin=16.0, smax=256.0, height=float(n))
+    rec = gen.primitive_records(7, **kw)
+    eng = dx.Engine(0)
+    prims = torch.as_tensor(rec, dtype=torch.float64).cuda().contiguous()
+    res = eng.dexelize(n, n, prims)          # sizes the output
+    nseg = res.nseg
+    ncols = n * n
+    col = torch.empty(ncols + 1, dtype=torch.int64, device="cuda")
+    z = torch.empty(2 * max(nseg, 1), dtype=torch.float32, device="cuda")
+    nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = dx.make_out(n, n, col, z, nout, status)
+    ws = torch.empty(dx.dexel_dexelize_workspace_size(eng.ctx, n, n), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        dx.dexel_dexelize(eng.ctx, n, n, prims, out, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        st = dx.dexel_dexelize(eng.ctx, n, n, prims, out, ws)
+        if st != dx.DEXEL_OK:
+            raise RuntimeError(f"dexel_dexelize enqueue failed: {st}")
+    e1.record()
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    if int(status.item()) != 0:
+        raise RuntimeError(f"dexel_dexelize status {int(status.item())}")
+    ms_step = (te - ts) * 1000.0 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    pairs = dex_candidate_pairs(rec, n)
+    tflops = pairs * DEX_FLOPS_PER_TEST / (ev_ms / 1000.0) / 1e12
+    line = {
+        "metric": "dexel intervals produced/sec",
+        "value": nseg / (ms_step / 1000.0),
+        "unit": "intervals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"dexelize: {WORKLOADS['dexelize']['desc']}", "grid": f"{n}x{n}",
+                   "primitives": count, "nseg_out": nseg},
+        "roofline": {"bound": "alu", "achieved": round(tflops, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 5),
+                     "traffic": None, "kernel": "k_dexelize (count and write passes)",
+                     "kernel_ms": round(ev_ms, 4),
+                     "candidate_pairs": pairs, "flops_per_launch": int(pairs * DEX_FLOPS_PER_TEST)},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on whole grid rows until about half the CPU budget
+        prims_l = [tuple(p) for p in rec]
+        tc, rows, made = time.perf_counter(), 0, 0
+        y = n // 2
+        while time.perf_counter() - tc < args.cpu_budget / 2 and rows < n:
+            for x in range(n):
+                made += len(od.merge(od.column_intervals(x, y + rows, prims_l)))
+            rows += 1
+        dt = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": made / dt, "unit": "intervals/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{rows} grid rows from the middle ({rows * n} columns, {made} "
+                                          f"intervals), {dt:.2f} s, pure Python, one thread"}
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
 def pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q))
 
@@ -627,6 +726,8 @@ def main():
         return run_shell(args, dx, torch)
     if args.workload == "slices":
         return run_slices(args, dx, torch)
+    if args.workload == "dexelize":
+        return run_dexelize(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)

@@ -741,13 +741,22 @@ dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_gri
     return DEXEL_OK;
 }
 
+// The CSG layout (header, counts, scan) followed by the list of cell tiles
+// that the dexelisation redoes with the full per-column capacity.
+static size_t dex_layout(int32_t nx, int32_t ny, size_t* spill) {
+    size_t c, q, b;
+    const size_t o = csg_layout((int64_t)nx * ny, &c, &q, &b);
+    *spill = o;
+    return align_up(o + 4 * (size_t)dexel::dexelize_tiles(nx, ny));
+}
+
 dexel_status dexel_dexelize_workspace_size(dexel_ctx* ctx, int32_t nx, int32_t ny, size_t* bytes) {
     if (!ctx || !bytes) return DEXEL_ERR_INVALID;
     if (nx <= 0 || ny <= 0) return fail(ctx, DEXEL_ERR_INVALID, "nx and ny must be >= 1");
     if ((int64_t)nx * ny >= ((int64_t)1 << 31) - 64)
         return fail(ctx, DEXEL_ERR_UNSUPPORTED, "nx * ny must be below 2^31");
-    size_t c, q, b;
-    *bytes = csg_layout((int64_t)nx * ny, &c, &q, &b);
+    size_t sp;
+    *bytes = dex_layout(nx, ny, &sp);
     return DEXEL_OK;
 }
 
@@ -773,8 +782,9 @@ dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double
     if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
     if (((uintptr_t)ws) % 256 != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
     const int64_t ncols = (int64_t)nx * ny;
-    size_t o_cnt, o_scan, o_bsum;
-    if (csg_layout(ncols, &o_cnt, &o_scan, &o_bsum) > ws_bytes)
+    size_t o_cnt, o_scan, o_bsum, o_spill;
+    csg_layout(ncols, &o_cnt, &o_scan, &o_bsum);
+    if (dex_layout(nx, ny, &o_spill) > ws_bytes)
         return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than dexel_dexelize_workspace_size");
     HIP_TRY(hipSetDevice(ctx->device));
     char* w = (char*)ws;
@@ -793,6 +803,7 @@ dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double
     g.cap = out->cap_seg;
     g.out_nseg = out->nseg_out;
     g.out_status = out->status;
+    g.spill = (int32_t*)(w + o_spill);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(dexel::launch_dexelize(g, s));
     if (!(flags & DEXEL_FLAG_SYNC)) return DEXEL_OK;

@@ -169,8 +169,10 @@ struct DexArgs {
     int64_t cap;
     int64_t* out_nseg;
     int32_t* out_status;
+    int32_t* spill;       // [dexelize_tiles] tiles redone with DEX_CAP slots
 };
 constexpr int DEX_CAP = 64;  // most intervals one column may hold
+int64_t dexelize_tiles(int32_t nx, int32_t ny);
 hipError_t launch_dexelize(const DexArgs& a, hipStream_t s);
 
 }  // namespace dexel

@@ -2338,9 +2338,8 @@ hipError_t launch_csg(const CsgArgs& a, hipStream_t s) {
 // Chord ends are computed in float64, each operation rounded once (no
 // contraction into fused multiply-adds), then rounded once to float32 and
 // merged into the column's canonical list (overlapping or touching
-// intervals join).  One lane per column, every primitive tested in turn
-// (the record loads are the same for the whole wave).  Run once to count,
-// once to write.
+// intervals join).  One lane per column; each block first culls the
+// primitives against its cells (below).  Run once to count, once to write.
 
 // The chord of primitive record q on the ray of cell (x, y); false if none
 // (and *bad set for an unknown kind).
@@ -2370,41 +2369,191 @@ __device__ bool dex_chord(const double* q, int x, int y, float* lo, float* hi, b
     return false;
 }
 
-template <bool WRITE>
-__global__ void __launch_bounds__(WG) k_dexelize(DexArgs A) {
-    __shared__ float2 lds[DEX_CAP * WG];
-    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
-    const bool live = c < A.ncols;
-    const int y = live ? (int)(c / A.nx) : 0;
-    const int x = live ? (int)(c - (int64_t)y * A.nx) : 0;
-    LdsList U{&lds[threadIdx.x], DEX_CAP};
-    int n = 0;
-    bool bad = false, over = false;
-    for (int k = 0; k < A.nprims; ++k) {
-        float lo, hi;
-        if (!live || over) continue;
-        if (!dex_chord(A.prims + 7 * (int64_t)k, x, y, &lo, &hi, &bad)) continue;
-        const int m = lv_insert(U, n, lo, hi);
-        if (m < 0) over = true; else n = m;
+// May primitive record q hit a cell centre of the box [xlo, xhi] x [ylo, yhi]
+// (integer cell indices)?  Conservative, with the lane test's own float
+// operations: a ball is out when the squared float distance from its centre
+// to the nearest centre coordinate, in x or in y, is not below R^2 (rounding
+// is monotone, so every lane's rho2 is then not below R^2 either); a box is
+// out when its cell range misses the block's.  Unknown kinds are kept (the
+// lanes report them).
+__device__ bool dex_may_hit(const double* q, int xlo, int xhi, int ylo, int yhi) {
+#pragma clang fp contract(off)
+    const double kind = q[0];
+    if (kind == 0.0) {
+        const double R2 = q[4] * q[4];
+        const double pxl = (double)xlo + 0.5, pxh = (double)xhi + 0.5;
+        const double pyl = (double)ylo + 0.5, pyh = (double)yhi + 0.5;
+        const double cx = q[1], cy = q[2];
+        const double dx = cx < pxl ? pxl - cx : (cx > pxh ? cx - pxh : 0.0);
+        const double dy = cy < pyl ? pyl - cy : (cy > pyh ? cy - pyh : 0.0);
+        return dx * dx < R2 && dy * dy < R2;
     }
-    if (!live) return;
-    if (bad) set_error(A.hdr, DEXEL_ERR_INVALID);
-    if (over) set_error(A.hdr, DEXEL_ERR_UNSUPPORTED);
+    if (kind == 1.0)
+        return floor(q[4] - 0.5) >= (double)xlo && ceil(q[1] - 0.5) <= (double)xhi &&
+               floor(q[5] - 0.5) >= (double)ylo && ceil(q[2] - 0.5) <= (double)yhi;
+    return true;
+}
+
+// One block of DEX_WG lanes per tile of 64 x 4 cells (256 x 1 when the grid
+// has fewer than 4 rows), one lane per column.  The primitives are taken
+// DEX_WG at a time (the next chunk's records are loaded while the current
+// one is tested): each lane tests one against the tile's cell box, the
+// survivors' records are compacted into LDS (ballot, per-wave counts,
+// prefix), and every lane then runs the exact test on the survivors only,
+// in primitive order.
+//
+// Two tiers: the first pass over all tiles keeps each lane's list in
+// DEX_CAPL LDS slots (a small footprint, so several blocks share a CU); a
+// tile where some lane would need more is appended to a list (its lanes
+// write nothing) and redone whole by the second tier with DEX_CAP slots,
+// where running out is an error.  Both tiers compute every lane the same
+// way, so the redone lanes that had fit write what they would have written.
+constexpr int DEX_WG = 256;
+constexpr int DEX_CAPL = 12;
+using DexList = LV<DEX_WG>;
+
+__device__ __forceinline__ void dex_load(const DexArgs& A, int k, double* q) {
+    if (k < A.nprims) {
+        const double* r = A.prims + 7 * (int64_t)k;
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i] = r[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i] = 0.0;
+    }
+}
+
+__host__ __device__ __forceinline__ int dex_tile_h(int ny) { return ny >= 4 ? 4 : 1; }
+
+// Lane t of tile `tile`: its column's canonical list in U (n intervals);
+// returns false when the list ran past U.cap.  Every lane of the block must
+// call it (it synchronises the block).
+__device__ bool dex_tile(const DexArgs& A, int64_t tile, DexList U, double (*rec)[DEX_WG], int* wsum,
+                         int* x_out, int* y_out, bool* live_out, int* n_out, bool* bad) {
+    const int t = threadIdx.x, w = t / WG, l = t % WG;
+    const int th = dex_tile_h(A.ny), tw = DEX_WG / th;
+    const int ntx = (A.nx + tw - 1) / tw;
+    const int bx = (int)(tile % ntx), by = (int)(tile / ntx);
+    const int xlo = bx * tw, ylo = by * th;
+    const int xhi = min(xlo + tw, A.nx) - 1, yhi = min(ylo + th, A.ny) - 1;
+    const int x = xlo + t % tw, y = ylo + t / tw;
+    const bool live = x < A.nx && y < A.ny;
+    int n = 0;
+    bool over = false;
+    double q[7], qn[7];
+    dex_load(A, t, q);
+    for (int base = 0; base < A.nprims; base += DEX_WG) {
+        const bool keep = base + t < A.nprims && dex_may_hit(q, xlo, xhi, ylo, yhi);
+        dex_load(A, base + DEX_WG + t, qn);
+        const unsigned long long mask = __ballot(keep);
+        __syncthreads();  // the previous chunk's survivors have been read
+        if (l == 0) wsum[w] = __popcll(mask);
+        __syncthreads();
+        int pos = __popcll(mask & ((1ull << l) - 1ull)), nsurv = 0;
+#pragma unroll
+        for (int i = 0; i < DEX_WG / WG; ++i) {
+            pos += i < w ? wsum[i] : 0;
+            nsurv += wsum[i];
+        }
+        if (keep) {
+#pragma unroll
+            for (int i = 0; i < 7; ++i) rec[i][pos] = q[i];
+        }
+        __syncthreads();
+        if (live && !over) {
+            for (int j = 0; j < nsurv; ++j) {
+                double p[7];
+#pragma unroll
+                for (int i = 0; i < 7; ++i) p[i] = rec[i][j];
+                float lo, hi;
+                if (!dex_chord(p, x, y, &lo, &hi, bad)) continue;
+                const int m = lv_insert(U, n, lo, hi);
+                if (m < 0) {
+                    over = true;
+                    break;
+                }
+                n = m;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i] = qn[i];
+    }
+    *x_out = x;
+    *y_out = y;
+    *live_out = live;
+    *n_out = n;
+    return !over;
+}
+
+// The outputs of one lane: its count (count pass), or its CSR offset and
+// intervals (write pass).  `fits`: the list is whole.
+template <bool WRITE>
+__device__ void dex_emit(const DexArgs& A, int64_t c, DexList U, int n, bool fits, bool bad,
+                         bool own_ptr) {
     if (!WRITE) {
-        gst(&A.cnt[c], over ? 0 : n);
+        gst(&A.cnt[c], fits ? n : 0);
         return;
     }
     // after an error of the count pass the scan did not run: write nothing
     if (A.hdr->abort) return;
     const int64_t total = gld(&A.scan[A.ncols]);
     const int64_t off = gld(&A.scan[c]);
-    gst(&A.out_ptr[c], off);
-    if (c == 0) {
-        gst(&A.out_ptr[A.ncols], total);
-        gst(A.out_nseg, total);
+    if (own_ptr) {
+        gst(&A.out_ptr[c], off);
+        if (c == 0) {
+            gst(&A.out_ptr[A.ncols], total);
+            gst(A.out_nseg, total);
+        }
     }
-    if (total > A.cap || over || bad) return;
+    if (total > A.cap || !fits || bad) return;
     for (int i = 0; i < n; ++i) gst(&A.out_z[off + i], U.get(i));
+}
+
+// First tier: one block per tile.  The count pass appends the tiles that
+// ran out of slots to A.spill (count in hdr->novf[0]); the write pass finds
+// the same tiles running out and leaves their intervals to the second tier.
+template <bool WRITE>
+__global__ void __launch_bounds__(DEX_WG) k_dexelize(DexArgs A) {
+    __shared__ float2 lds[DEX_CAPL * DEX_WG];
+    __shared__ double rec[7][DEX_WG];    // the chunk's survivors, by field
+    __shared__ int wsum[DEX_WG / WG];
+    DexList U{&lds[threadIdx.x], DEX_CAPL};
+    int x, y, n;
+    bool live, bad = false;
+    const bool fits = dex_tile(A, blockIdx.x, U, rec, wsum, &x, &y, &live, &n, &bad);
+    const bool spilled = __syncthreads_or(live && !fits);
+    if (!WRITE && spilled && threadIdx.x == 0) {
+        const int k = atomicAdd(&A.hdr->novf[0], 1);
+        gst(&A.spill[k], (int32_t)blockIdx.x);
+    }
+    if (!live) return;
+    if (bad) set_error(A.hdr, DEXEL_ERR_INVALID);
+    const int64_t c = (int64_t)y * A.nx + x;
+    if (!WRITE && !fits) return;    // the second tier counts it
+    dex_emit<WRITE>(A, c, U, n, fits, bad, true);
+}
+
+// Second tier: the tiles listed by the first, DEX_CAP slots per lane; a
+// fixed grid walks the list.
+template <bool WRITE>
+__global__ void __launch_bounds__(DEX_WG) k_dexelize_full(DexArgs A) {
+    __shared__ float2 lds[DEX_CAP * DEX_WG];
+    __shared__ double rec[7][DEX_WG];
+    __shared__ int wsum[DEX_WG / WG];
+    const int ntiles = A.hdr->novf[0];
+    DexList U{&lds[threadIdx.x], DEX_CAP};
+    for (int i = blockIdx.x; i < ntiles; i += gridDim.x) {
+        const int64_t tile = gld(&A.spill[i]);
+        int x, y, n;
+        bool live, bad = false;
+        const bool fits = dex_tile(A, tile, U, rec, wsum, &x, &y, &live, &n, &bad);
+        if (live) {
+            if (bad) set_error(A.hdr, DEXEL_ERR_INVALID);
+            if (!fits) set_error(A.hdr, DEXEL_ERR_UNSUPPORTED);
+            dex_emit<WRITE>(A, (int64_t)y * A.nx + x, U, n, fits, bad, false);
+        }
+        __syncthreads();   // LDS is reused by the next tile
+    }
 }
 
 // The device status: an error of the count pass (unknown kind, a column past
@@ -2415,13 +2564,21 @@ __global__ void k_dexelize_status(DexArgs A) {
     A.out_status[0] = st != 0 ? st : (total > A.cap ? (int32_t)DEXEL_ERR_CAPACITY : (int32_t)DEXEL_OK);
 }
 
+int64_t dexelize_tiles(int32_t nx, int32_t ny) {
+    const int th = dex_tile_h(ny), tw = DEX_WG / th;
+    return (int64_t)((nx + tw - 1) / tw) * ((ny + th - 1) / th);
+}
+
 hipError_t launch_dexelize(const DexArgs& a, hipStream_t s) {
-    const unsigned nb = (unsigned)((a.ncols + WG - 1) / WG);
+    const unsigned nb = (unsigned)dexelize_tiles(a.nx, a.ny);
+    const unsigned nfull = nb < 1024u ? nb : 1024u;
     hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, a.hdr, (int32_t*)nullptr, 0);
-    hipLaunchKernelGGL(k_dexelize<false>, dim3(nb), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_dexelize<false>, dim3(nb), dim3(DEX_WG), 0, s, a);
+    hipLaunchKernelGGL(k_dexelize_full<false>, dim3(nfull), dim3(DEX_WG), 0, s, a);
     hipError_t e = scan_counts(a.cnt, a.ncols, a.bsum, a.scan, a.hdr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dexelize<true>, dim3(nb), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_dexelize<true>, dim3(nb), dim3(DEX_WG), 0, s, a);
+    hipLaunchKernelGGL(k_dexelize_full<true>, dim3(nfull), dim3(DEX_WG), 0, s, a);
     hipLaunchKernelGGL(k_dexelize_status, dim3(1), dim3(1), 0, s, a);
     return hipGetLastError();
 }

@@ -53,6 +53,71 @@ def test_random_sets(engine, seed):
     assert np.array_equal(z, rz)
 
 
+@pytest.mark.parametrize("nx,ny,count", [(130, 9, 700), (300, 1, 600), (70, 3, 300), (257, 5, 513)])
+def test_tiles_and_chunks(engine, nx, ny, count):
+    """Grids that cut the kernel's cell tiles (64 x 4, or 256 x 1 below 4
+    rows) raggedly, and lists of several primitive chunks with a ragged last
+    one."""
+    rng = np.random.default_rng(nx * 1000 + ny)
+    prims = []
+    for _ in range(count):   # centres and corners spread over this grid's own extent
+        x0, y0, z0 = rng.uniform(-2, nx + 2), rng.uniform(-2, ny + 2), rng.uniform(0, 40)
+        if rng.random() < 0.5:
+            prims.append((od.BALL, x0, y0, z0, rng.uniform(0.3, 5.0), 0.0, 0.0))
+        else:
+            prims.append((od.BOX, x0, y0, z0, *(np.array([x0, y0, z0]) + rng.uniform(0.0, 10.0, 3))))
+    print(f"[case] dexelize tiles {nx}x{ny} with {count} primitives", flush=True)
+    col, z = run(engine, nx, ny, prims)
+    rc, rz = od.dexelize(nx, ny, prims)
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z, rz)
+
+
+def test_culling_at_tile_edges(engine):
+    """Primitives centred in one cell tile that reach the nearest cell centre
+    of the next tile by a hair, or miss it by a hair: balls 1.25 from that
+    centre with radius 1.25 +- 2^-40 across the x edge (columns 63 | 64) and
+    the y edge (rows 3 | 4), and boxes whose high x corner is 64.5 +- 2^-40
+    (column 64's centre)."""
+    eps = 2.0 ** -40
+    prims = []
+    for k in range(12):
+        cz, r = 4.0 * k, 1.25 + (eps if k % 2 else -eps)
+        prims.append((od.BALL, 64.75, 1.5 + k % 3, cz, r, 0.0, 0.0))    # reaches column 63?
+        prims.append((od.BALL, 63.25, 5.5 + k % 3, cz, r, 0.0, 0.0))    # reaches column 64?
+        prims.append((od.BALL, 10.5 + k, 4.75, cz, r, 0.0, 0.0))        # reaches row 3?
+        prims.append((od.BOX, 60.0 + k % 3, 3.0 + k % 2, cz, 64.5 + (eps if k % 2 else -eps), 4.5, cz + 1.0))
+    print("[case] dexelize culling at tile edges", flush=True)
+    col, z = run(engine, 130, 9, prims)
+    rc, rz = od.dexelize(130, 9, prims)
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z, rz)
+    # the hair decides: the balls of odd k reach across the edge, those of even k do not
+    def ncol(x, y):
+        return int(rc[y * 130 + x + 1] - rc[y * 130 + x])
+    assert [ncol(63, y) for y in (1, 2)] == [2, 2]
+    assert [ncol(64, y) for y in (5, 6, 7)] == [2, 2, 2]
+    assert [ncol(10 + k, 3) for k in range(12)] == [k % 2 for k in range(12)]
+
+
+def test_deep_columns_beside_shallow_ones(engine):
+    """A stack of 30 thin boxes over a few cells among random primitives: the
+    cell tiles holding those columns need more list slots than the others
+    (they are redone at full capacity, neighbouring lanes included)."""
+    rng = np.random.default_rng(5)
+    nx, ny = 200, 11
+    prims = [(od.BALL, rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, 300), rng.uniform(0.5, 4.0), 0, 0)
+             for _ in range(300)]
+    prims += [(od.BOX, 60.0, 3.0, 10.0 * k, 70.0, 6.0, 10.0 * k + 2.0) for k in range(30)]
+    prims += [(od.BOX, 190.0, 9.0, 7.0 * k, 200.0, 11.0, 7.0 * k + 3.0) for k in range(40)]
+    print("[case] dexelize deep columns", flush=True)
+    col, z = run(engine, nx, ny, prims)
+    rc, rz = od.dexelize(nx, ny, prims)
+    assert int(np.max(np.diff(rc))) > 30
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z, rz)
+
+
 def test_exact_boundaries(engine):
     """A ball whose radius reaches a neighbouring cell centre exactly (excluded:
     the lateral test is strict), a box whose edges pass through cell centres
