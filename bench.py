@@ -613,21 +613,21 @@ def run_serving(args, dx, torch):
     from synth import gen
     rng = np.random.default_rng(0)
     t0 = time.perf_counter()
-    hosts = []
+    eng = dx.Engine(0)
+    pool = []
     for i in range(16):
         side = int(round(np.exp(rng.uniform(np.log(256), np.log(2048)))))
         sub = int(rng.integers(0, 2**31 - 1))
         if i % 2 == 0:
-            hosts.append(gen.primitives_grid(sub, n=side, count=int(rng.integers(20, 301)),
-                                             smin=4.0 * side / 512, smax=64.0 * side / 512,
-                                             height=float(side)))
+            # soups are dexelised on the device from their primitive records
+            rec = gen.primitive_records(sub, n=side, count=int(rng.integers(20, 301)),
+                                        smin=4.0 * side / 512, smax=64.0 * side / 512, height=float(side))
+            pool.append(eng.dexelize(side, side, rec))
         else:
-            hosts.append(gen.gyroid_grid(sub, n=side))
-    print(f"[bench] c5 pool: sides {[h.nx for h in hosts]}, "
-          f"{sum(h.nseg for h in hosts)} intervals ({time.perf_counter() - t0:.1f} s)",
+            pool.append(dx.DeviceGrid.from_host(gen.gyroid_grid(sub, n=side)))
+    print(f"[bench] c5 pool: sides {[g.nx for g in pool]}, "
+          f"{sum(g.nseg for g in pool)} intervals ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
-    eng = dx.Engine(0)
-    pool = [dx.DeviceGrid.from_host(h) for h in hosts]
     ops = ["dilate", "erode", "open", "close"]
 
     def make(n, rate, seed):
