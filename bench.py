@@ -7,7 +7,7 @@ intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
 method's own scalability experiments.  One step = one closing of the whole
 grid, input resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices|dexelize] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices|dexelize|tridexel] [--no-cpu-baseline]
 
 value   = input intervals offset per second (intervals of the input grid per
           operation, summed over the step's operations, divided by the step
@@ -87,6 +87,9 @@ WORKLOADS = {
                         "batched enqueue", ops=[]),
     "dexelize": dict(desc="dexelisation on the GPU of a 2048x2048 soup of 5400 balls and boxes (sizes "
                           "U[16,256], height 2048), rays through cell centres", ops=[]),
+    "tridexel": dict(desc="tri-dexel dilation r=8: the 512^3 soup of 1350 balls and boxes (the c2 primitives) "
+                          "dexelised on the GPU along x, y and z, and the three 512x512 grids dilated in one "
+                          "batched enqueue", ops=[]),
     "shell": dict(desc="shell (dilation minus erosion, then a per-column difference) r=4 of the "
                        "512x512 soup of 1350 spheres/boxes, the grid size and radius of the paper's "
                        "shell figure", ops=[]),
@@ -172,6 +175,125 @@ def csg_bytes(ncols, na, nb, nout):
     written once (CSR offsets 8 B per column, intervals 8 B), per-column
     counts written and read (4 B each) and the scan written and read (8 B)."""
     return 3 * 8 * (ncols + 1) + 8 * (na + nb + nout) + 2 * 4 * ncols + 2 * 8 * (ncols + 1)
+
+
+def run_tridexel(args, dx, torch):
+    """tridexel: dexelisation along the three axes and the dilation of each
+    direction, all on the device, the primitive records resident in HBM."""
+    import oracle
+    from synth import gen
+    n, r = 512, 8.0
+    rec = gen.primitive_records(0)           # the c2 soup's primitives
+    eng = dx.Engine(0)
+    prims = torch.as_tensor(rec, dtype=torch.float64).cuda().contiguous()
+    axes = ("x", "y", "z")
+    tri = eng.tridexel((n, n, n), prims)     # sizes the grids
+    calls = []
+    for a in axes:
+        g = tri[a]
+        nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ws = torch.empty(dx.dexel_dexelize_workspace_size(eng.ctx, g.nx, g.ny), dtype=torch.uint8, device="cuda")
+        calls.append((g, dx.make_out(g.nx, g.ny, g.col_ptr, g.z, nout, status), ws, dx.RAY_FLAGS[a], status))
+    nseg = {a: tri[a].nseg for a in axes}
+    n_in = sum(nseg.values())
+    ncols = sum(tri[a].nx * tri[a].ny for a in axes)
+    bp = dx.BatchPlan(eng, [tri[a] for a in axes], [r] * 3, ["dilate"] * 3)
+    chosen, var_ms = bp.autotune(reps=2)
+    bp.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+    stats = dx.dexel_workspace_stats(eng.ctx, eng.workspace(bp.ws_bytes))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+
+    def step(i=None):
+        if i is not None:
+            ev[i][0].record()
+        for g, out, ws, fl, _ in calls:
+            st = dx.dexel_dexelize(eng.ctx, g.nx, g.ny, prims, out, ws, None, fl)
+            if st != dx.DEXEL_OK:
+                raise RuntimeError(f"dexel_dexelize enqueue failed: {st}")
+        if i is not None:
+            ev[i][1].record()
+        bp.enqueue()
+        if i is not None:
+            ev[i][2].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    dx.dexel_profile_enable(eng.ctx, False)
+    prof_ms, _ = dx.dexel_profile_read(eng.ctx, reset=True)
+    bad = [int(c[4].item()) for c in calls if int(c[4].item()) != 0] + [s_ for s_ in bp.statuses() if s_ != 0]
+    if bad:
+        raise RuntimeError(f"device statuses {bad}")
+    if any(tri[a].nseg != nseg[a] for a in axes):
+        raise RuntimeError("dexelisation changed between steps")
+    ms_step = (te - ts) * 1000.0 / args.steps
+    dex_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    off_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    stages = dx.PROFILE_STAGES
+    per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
+    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
+    dom = max(modelled, key=per_step.get)
+    dom_ms = per_step[dom]
+    dom_bytes = kernel_bytes(dom, ncols, n_in, stats)
+    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    line = {
+        "metric": "input dexel segments offset/sec",
+        "value": n_in / (ms_step / 1000.0),
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"tridexel: {WORKLOADS['tridexel']['desc']}", "grid": f"{n}x{n}x{n}",
+                   "primitives": len(rec), "r": r, "nseg_in": nseg},
+        "dexelize_ms_per_step": round(dex_ms, 4),
+        "offset_ms_per_step": round(off_ms, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)], "kernel_ms": round(dom_ms, 4),
+                     "bytes_per_launch": int(dom_bytes)},
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
+        "variant": chosen,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's dilation of the z-ray grid (the generator's c2 grid) on
+        # a square tile of output columns, grown until it takes a few seconds
+        grid = gen.primitives_grid(0)
+        t, best = 8, None
+        while True:
+            x0, y0 = grid.nx // 2 - t // 2, grid.ny // 2 - t // 2
+            cols = (np.arange(y0, y0 + t)[:, None] * grid.nx + np.arange(x0, x0 + t)[None, :]).ravel()
+            tc = time.perf_counter()
+            oracle.offset_columns(grid, r, "dilate", "f64", cols=cols)
+            dt = time.perf_counter() - tc
+            best = (cols.size, dt, t)
+            if dt * 4 > args.cpu_budget or t >= min(grid.nx, grid.ny):
+                break
+            t *= 2
+        nc, dt, t = best
+        per_col = grid.nseg / float(grid.nx * grid.ny)
+        line["cpu_baseline"] = {"value": nc * per_col / dt, "unit": "input segments/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"dilation r={r} of the z-ray grid on a {t}x{t} tile of output "
+                                          f"columns ({nc} columns, {nc * per_col:.0f} input-interval "
+                                          f"equivalents), {dt:.2f} s; the oracle's dexelisation (pure "
+                                          f"Python) is not included"}
+    print(json.dumps(line), flush=True)
+    eng.close()
 
 
 def run_shell(args, dx, torch):
@@ -728,6 +850,8 @@ def main():
         return run_slices(args, dx, torch)
     if args.workload == "dexelize":
         return run_dexelize(args, dx, torch)
+    if args.workload == "tridexel":
+        return run_tridexel(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)

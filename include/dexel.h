@@ -75,6 +75,8 @@ typedef enum { DEXEL_DILATE = 0, DEXEL_ERODE = 1, DEXEL_OPEN = 2, DEXEL_CLOSE = 
 
 #define DEXEL_FLAG_SYNC 1u     /* synchronise the stream and return the device status   */
 #define DEXEL_FLAG_VALIDATE 2u /* check the input is canonical before computing          */
+#define DEXEL_FLAG_RAYS_X 4u   /* dexel_dexelize only: rays along x (grid over y, z)      */
+#define DEXEL_FLAG_RAYS_Y 8u   /* dexel_dexelize only: rays along y (grid over z, x)      */
 
 typedef struct dexel_ctx dexel_ctx;
 
@@ -175,7 +177,15 @@ dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_gri
  * column may hold at most 64 intervals (else DEXEL_ERR_UNSUPPORTED in
  * out->status); an unknown kind gives DEXEL_ERR_INVALID there.  `out` and
  * `ws` (dexel_dexelize_workspace_size bytes, 256-byte aligned) as for
- * dexel_csg; DEXEL_FLAG_VALIDATE is not supported. */
+ * dexel_csg; DEXEL_FLAG_VALIDATE is not supported.
+ *
+ * Rays along another axis (the dexel structures in three orthogonal
+ * directions of Sec. 5, "Limitations", and Sec. 6): with DEXEL_FLAG_RAYS_X
+ * the grid's two axes are y and z (nx cells along y, ny along z) and the
+ * intervals lie along x; with DEXEL_FLAG_RAYS_Y they are z and x and the
+ * intervals lie along y.  The rules above apply with the coordinates taken
+ * in that order, (a1, a2, a0) or (a2, a0, a1), and likewise for b; a ball's
+ * radius is b0 in every case.  Both flags together: DEXEL_ERR_INVALID. */
 typedef enum { DEXEL_PRIM_BALL = 0, DEXEL_PRIM_BOX = 1 } dexel_prim_kind;
 dexel_status dexel_dexelize_workspace_size(dexel_ctx* ctx, int32_t nx, int32_t ny, size_t* bytes);
 dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double* prims, int32_t nprims,

@@ -20,6 +20,12 @@ overlap or touch.  Footprints outside the grid are clipped; z is not.
 
 Primitive records: (kind, a0, a1, a2, b0, b1, b2) with kind 0 = ball (a =
 centre, b0 = radius) and kind 1 = box (a = low corner, b = high corner).
+
+Rays along another axis (dexel structures in three orthogonal directions,
+Sec. 5, "Limitations", and Sec. 6): for rays along axis k the grid's two axes
+are (k + 1) mod 3 and (k + 2) mod 3, in that order, and the intervals lie
+along k; so rays along x give a grid over (y, z), rays along y one over
+(z, x).  The rules above then apply to the coordinates in that order.
 """
 from __future__ import annotations
 
@@ -64,9 +70,26 @@ def merge(intervals):
     return res
 
 
-def dexelize(nx: int, ny: int, prims):
-    """CSR (col_ptr int64[nx*ny+1], z float64[2n]) of the union of the primitives."""
-    prims = [tuple(p) for p in np.asarray(prims, dtype=np.float64).reshape(-1, 7)]
+AXES = {"x": 0, "y": 1, "z": 2}
+
+
+def ray_frame(p, axis: str):
+    """Record p with its coordinates taken as (grid axis 1, grid axis 2,
+    along the ray); a ball's radius is not a coordinate and stays."""
+    k = AXES[axis]
+    order = ((k + 1) % 3, (k + 2) % 3, k)
+    a = [p[1 + i] for i in order]
+    if int(p[0]) == BOX:
+        b = [p[4 + i] for i in order]
+    else:
+        b = list(p[4:7])
+    return (p[0], *a, *b)
+
+
+def dexelize(nx: int, ny: int, prims, axis: str = "z"):
+    """CSR (col_ptr int64[nx*ny+1], z float64[2n]) of the union of the
+    primitives, sampled by rays along `axis`."""
+    prims = [ray_frame(tuple(p), axis) for p in np.asarray(prims, dtype=np.float64).reshape(-1, 7)]
     col_ptr = np.zeros(nx * ny + 1, np.int64)
     z = []
     for y in range(ny):

@@ -20,7 +20,7 @@ from .binding import (  # noqa: F401
     make_out, make_view, NPROF, PROFILE_KERNELS, PROFILE_STAGES, NVARIANT, dexel_autotune,
     dexel_set_variant, CSG_OPS, DEXEL_CSG_DIFFERENCE, DEXEL_CSG_INTERSECT, DEXEL_CSG_UNION,
     dexel_csg, dexel_csg_workspace_size, DEXEL_PRIM_BALL, DEXEL_PRIM_BOX, dexel_dexelize,
-    dexel_dexelize_workspace_size,
+    dexel_dexelize_workspace_size, DEXEL_FLAG_RAYS_X, DEXEL_FLAG_RAYS_Y, RAY_FLAGS,
 )
 
 
@@ -155,9 +155,13 @@ class Engine:
                 raise ValueError("a slice is an nx x 1 grid")
         return batch_offset(self, slices, [r] * len(slices), [op] * len(slices), stream=stream)
 
-    def dexelize(self, nx: int, ny: int, prims, stream=None, max_tries: int = 4) -> DeviceGrid:
+    def dexelize(self, nx: int, ny: int, prims, stream=None, max_tries: int = 4,
+                 axis: str = "z") -> DeviceGrid:
         """Dexel grid of the union of balls and boxes (dexel_dexelize).
-        prims: (n, 7) records (kind, a0, a1, a2, b0, b1, b2), host or device."""
+        prims: (n, 7) records (kind, a0, a1, a2, b0, b1, b2), host or device.
+        axis: the rays' direction; "x" makes an nx x ny grid over (y, z),
+        "y" one over (z, x)."""
+        flags = DEXEL_FLAG_SYNC | RAY_FLAGS[axis]
         p = torch.as_tensor(prims, dtype=torch.float64).reshape(-1, 7).to(self.device).contiguous()
         ncols = int(nx) * int(ny)
         ws = self.workspace(dexel_dexelize_workspace_size(self.ctx, nx, ny))
@@ -168,7 +172,7 @@ class Engine:
             nout = torch.zeros(1, dtype=torch.int64, device=self.device)
             status = torch.zeros(1, dtype=torch.int32, device=self.device)
             out = make_out(nx, ny, col, z, nout, status)
-            st = dexel_dexelize(self.ctx, nx, ny, p, out, ws, stream, DEXEL_FLAG_SYNC)
+            st = dexel_dexelize(self.ctx, nx, ny, p, out, ws, stream, flags)
             if st == DEXEL_OK:
                 return DeviceGrid(nx, ny, col, z)
             if st == DEXEL_ERR_CAPACITY:
@@ -176,6 +180,25 @@ class Engine:
                 continue
             raise DexelError(st, dexel_last_error(self.ctx))
         raise DexelError(DEXEL_ERR_CAPACITY, "retries exhausted")
+
+    def tridexel(self, dims, prims, stream=None) -> dict:
+        """The solid sampled by rays along each of the three axes (the dexel
+        structures in three orthogonal directions of Sec. 5, "Limitations",
+        and Sec. 6).  dims = (n0, n1, n2) cells along x, y, z.  Returns
+        {"x": n1 x n2 grid over (y, z), "y": n2 x n0 grid over (z, x),
+        "z": n0 x n1 grid over (x, y)}."""
+        n0, n1, n2 = (int(d) for d in dims)
+        return {"x": self.dexelize(n1, n2, prims, stream, axis="x"),
+                "y": self.dexelize(n2, n0, prims, stream, axis="y"),
+                "z": self.dexelize(n0, n1, prims, stream, axis="z")}
+
+    def tridexel_offset(self, tri: dict, r: float, op: str = "dilate", stream=None) -> dict:
+        """Offset of each of the three structures by the same ball, in one
+        batched enqueue.  The ball looks the same along every axis, so each
+        direction is the method applied to that direction's grid."""
+        keys = ("x", "y", "z")
+        outs = batch_offset(self, [tri[k] for k in keys], [r] * 3, [op] * 3, stream=stream)
+        return dict(zip(keys, outs))
 
     def shell(self, grid: DeviceGrid, r: float) -> DeviceGrid:
         """Shell of thickness about 2r around the surface: the dilation minus

@@ -32,6 +32,9 @@ DEXEL_DILATE, DEXEL_ERODE, DEXEL_OPEN, DEXEL_CLOSE = 0, 1, 2, 3
 OPS = {"dilate": DEXEL_DILATE, "erode": DEXEL_ERODE, "open": DEXEL_OPEN, "close": DEXEL_CLOSE}
 DEXEL_FLAG_SYNC = 1
 DEXEL_FLAG_VALIDATE = 2
+DEXEL_FLAG_RAYS_X = 4
+DEXEL_FLAG_RAYS_Y = 8
+RAY_FLAGS = {"x": DEXEL_FLAG_RAYS_X, "y": DEXEL_FLAG_RAYS_Y, "z": 0}
 DEXEL_CSG_UNION, DEXEL_CSG_INTERSECT, DEXEL_CSG_DIFFERENCE = 0, 1, 2
 CSG_OPS = {"union": DEXEL_CSG_UNION, "intersect": DEXEL_CSG_INTERSECT,
            "difference": DEXEL_CSG_DIFFERENCE}

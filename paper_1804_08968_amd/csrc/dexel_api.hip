@@ -770,9 +770,12 @@ dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double
     if (nprims < 0 || (nprims > 0 && !prims)) return fail(ctx, DEXEL_ERR_INVALID, "bad primitive list");
     if (!out) return fail(ctx, DEXEL_ERR_INVALID, "null output");
     if (out->nx != nx || out->ny != ny) return fail(ctx, DEXEL_ERR_INVALID, "output nx, ny differ");
-    if (flags & ~(DEXEL_FLAG_SYNC | DEXEL_FLAG_VALIDATE)) return fail(ctx, DEXEL_ERR_INVALID, "unknown flags");
+    if (flags & ~(DEXEL_FLAG_SYNC | DEXEL_FLAG_VALIDATE | DEXEL_FLAG_RAYS_X | DEXEL_FLAG_RAYS_Y))
+        return fail(ctx, DEXEL_ERR_INVALID, "unknown flags");
     if (flags & DEXEL_FLAG_VALIDATE)
         return fail(ctx, DEXEL_ERR_UNSUPPORTED, "dexel_dexelize has no input to validate");
+    if ((flags & DEXEL_FLAG_RAYS_X) && (flags & DEXEL_FLAG_RAYS_Y))
+        return fail(ctx, DEXEL_ERR_INVALID, "DEXEL_FLAG_RAYS_X and DEXEL_FLAG_RAYS_Y together");
     if (!out->col_ptr || !out->nseg_out || !out->status)
         return fail(ctx, DEXEL_ERR_INVALID, "null output col_ptr, nseg_out or status");
     if (out->cap_seg < 0 || (out->cap_seg > 0 && !out->z))
@@ -793,6 +796,7 @@ dexel_status dexel_dexelize(dexel_ctx* ctx, int32_t nx, int32_t ny, const double
     g.nprims = nprims;
     g.nx = nx;
     g.ny = ny;
+    g.axis = (flags & DEXEL_FLAG_RAYS_X) ? 0 : ((flags & DEXEL_FLAG_RAYS_Y) ? 1 : 2);
     g.ncols = ncols;
     g.hdr = (WsHeader*)w;
     g.cnt = (int32_t*)(w + o_cnt);

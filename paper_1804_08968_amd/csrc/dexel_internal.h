@@ -158,7 +158,7 @@ struct DexArgs {
     const double* prims;  // [nprims * 7] records (kind, a0, a1, a2, b0, b1, b2)
     int32_t nprims;
     int32_t nx, ny;
-    int32_t pad;
+    int32_t axis;         // the rays' axis: 0 = x, 1 = y, 2 = z
     int64_t ncols;
     WsHeader* hdr;
     int32_t* cnt;

@@ -2412,15 +2412,38 @@ constexpr int DEX_WG = 256;
 constexpr int DEX_CAPL = 12;
 using DexList = LV<DEX_WG>;
 
+__device__ __forceinline__ double dex_pick(const double* v, int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+
+// Record k in the ray frame: for rays along axis k (0 = x, 1 = y, 2 = z) the
+// grid's lateral axes are (k + 1) mod 3 and (k + 2) mod 3 and the intervals
+// lie along k, so the corners (and a ball's centre) are reordered to
+// (lateral u, lateral v, along); a ball's radius stays in place.
 __device__ __forceinline__ void dex_load(const DexArgs& A, int k, double* q) {
-    if (k < A.nprims) {
-        const double* r = A.prims + 7 * (int64_t)k;
-#pragma unroll
-        for (int i = 0; i < 7; ++i) q[i] = r[i];
-    } else {
+    if (k >= A.nprims) {
 #pragma unroll
         for (int i = 0; i < 7; ++i) q[i] = 0.0;
+        return;
     }
+    const double* r = A.prims + 7 * (int64_t)k;
+    double v[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) v[i] = r[i];
+    if (A.axis == 2) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i] = v[i];
+        return;
+    }
+    const int u = A.axis == 0 ? 1 : 2, w = A.axis == 0 ? 2 : 0;
+    q[0] = v[0];
+    q[1] = dex_pick(v + 1, u);
+    q[2] = dex_pick(v + 1, w);
+    q[3] = dex_pick(v + 1, A.axis);
+    const bool box = v[0] == 1.0;
+    q[4] = box ? dex_pick(v + 4, u) : v[4];
+    q[5] = box ? dex_pick(v + 4, w) : v[5];
+    q[6] = box ? dex_pick(v + 4, A.axis) : v[6];
 }
 
 __host__ __device__ __forceinline__ int dex_tile_h(int ny) { return ny >= 4 ? 4 : 1; }

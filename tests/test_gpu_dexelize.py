@@ -12,6 +12,7 @@ import math
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import dexelize as od
 from synth import gen
@@ -118,6 +119,28 @@ def test_deep_columns_beside_shallow_ones(engine):
     assert np.array_equal(z, rz)
 
 
+@pytest.mark.parametrize("axis", ["x", "y"])
+@pytest.mark.parametrize("seed", range(2))
+def test_rays_along_x_and_y(engine, axis, seed):
+    """Rays along x (grid over y, z) and along y (grid over z, x) on a box of
+    unequal sides, so that a swapped grid axis cannot pass."""
+    rng = np.random.default_rng(40 + seed)
+    ext = np.array([70.0, 45.0, 30.0])
+    prims = []
+    for _ in range(400):
+        c = rng.uniform(-2, ext + 2)
+        if rng.random() < 0.5:
+            prims.append((od.BALL, *c, rng.uniform(0.5, 6.0), 0.0, 0.0))
+        else:
+            prims.append((od.BOX, *c, *(c + rng.uniform(0.0, 9.0, 3))))
+    nu, nv = {"x": (45, 30), "y": (30, 70)}[axis]
+    print(f"[case] dexelize rays along {axis} seed {seed}", flush=True)
+    col, z = engine.dexelize(nu, nv, np.asarray(prims), axis=axis).to_host()
+    rc, rz = od.dexelize(nu, nv, prims, axis=axis)
+    assert np.array_equal(col, rc)
+    assert np.array_equal(z.astype(np.float64), rz)
+
+
 def test_exact_boundaries(engine):
     """A ball whose radius reaches a neighbouring cell centre exactly (excluded:
     the lateral test is strict), a box whose edges pass through cell centres
@@ -175,6 +198,15 @@ def test_batch_shapes_equal_generator(engine, i):
 def test_errors_reported(engine):
     dx = _dx()
     print("[case] dexelize errors", flush=True)
+    with pytest.raises(dx.DexelError) as e:   # both ray axes at once
+        ws = torch.empty(dx.dexel_dexelize_workspace_size(engine.ctx, 4, 4), dtype=torch.uint8, device="cuda")
+        o = (torch.empty(17, dtype=torch.int64, device="cuda"), torch.empty(64, dtype=torch.float32, device="cuda"),
+             torch.zeros(1, dtype=torch.int64, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda"))
+        p = torch.zeros((1, 7), dtype=torch.float64, device="cuda")
+        st = dx.dexel_dexelize(engine.ctx, 4, 4, p, dx.make_out(4, 4, *o), ws, None,
+                               dx.DEXEL_FLAG_SYNC | dx.DEXEL_FLAG_RAYS_X | dx.DEXEL_FLAG_RAYS_Y)
+        raise dx.DexelError(st, "")
+    assert e.value.status == dx.DEXEL_ERR_INVALID
     with pytest.raises(dx.DexelError) as e:
         engine.dexelize(4, 4, [(7.0, 0, 0, 0, 1, 1, 1)])
     assert e.value.status == dx.DEXEL_ERR_INVALID

@@ -63,27 +63,86 @@ def _boundary_dist(prim, x, y, zz):
     return min(abs(x - ax), abs(x - bx), abs(y - ay), abs(y - by), abs(zz - az), abs(zz - bz))
 
 
+def _world(axis, u, v, t):
+    """The world point at grid position (u, v) and ray coordinate t."""
+    return {"z": (u, v, t), "x": (t, u, v), "y": (v, t, u)}[axis]
+
+
+@pytest.mark.parametrize("axis", ["z", "x", "y"])
 @pytest.mark.parametrize("seed", range(3))
-def test_membership_brute_force(seed):
+def test_membership_brute_force(seed, axis):
+    """Membership along each ray is decided by the primitives' inequalities
+    at the world point, written per axis without the oracle's reordering."""
     rng = np.random.default_rng(seed)
-    n = 12
+    nu, nv = 12, 9
     prims = []
     for _ in range(10):
         if rng.random() < 0.5:
-            prims.append((od.BALL, *rng.uniform(0, n, 3), rng.uniform(1, 4), 0.0, 0.0))
+            prims.append((od.BALL, *rng.uniform(0, 12, 3), rng.uniform(1, 4), 0.0, 0.0))
         else:
-            lo = rng.uniform(0, n, 3)
+            lo = rng.uniform(0, 12, 3)
             prims.append((od.BOX, *lo, *(lo + rng.uniform(1, 5, 3))))
-    cp, z = od.dexelize(n, n, prims)
-    for y in range(n):
-        for x in range(n):
-            iv = _col(cp, z, y * n + x)
-            for zz in rng.uniform(-5, n + 5, 60):
-                px, py = x + 0.5, y + 0.5
-                if min(_boundary_dist(p, px, py, zz) for p in prims) < 1e-3:
+    cp, z = od.dexelize(nu, nv, prims, axis=axis)
+    hits = 0
+    for v in range(nv):
+        for u in range(nu):
+            iv = _col(cp, z, v * nu + u)
+            for t in rng.uniform(-5, 17, 60):
+                p = _world(axis, u + 0.5, v + 0.5, t)
+                if min(_boundary_dist(q, *p) for q in prims) < 1e-3:
                     continue
-                truth = any(_inside(p, px, py, zz) for p in prims)
-                assert any(lo <= zz <= hi for lo, hi in iv) == truth, (x, y, zz)
+                truth = any(_inside(q, *p) for q in prims)
+                hits += truth
+                assert any(lo <= t <= hi for lo, hi in iv) == truth, (u, v, t)
+    assert hits > 100
+
+
+def test_box_along_each_axis():
+    """One box [1.2, 4.7] x [0.3, 2.9] x [-1, 3]: rays along x see the y-z
+    footprint and the x extent, rays along y the z-x footprint."""
+    box = [(od.BOX, 1.2, 0.3, -1.0, 4.7, 2.9, 3.0)]
+    cp, z = od.dexelize(4, 5, box, axis="x")      # grid (y, z): y = 0..2, z + 0.5 in [-1, 3] -> z = 0..2
+    for v in range(5):
+        for u in range(4):
+            want = [(1.2, 4.7)] if (u <= 2 and v <= 2) else []
+            assert _col(cp, z, v * 4 + u) == [tuple(float(np.float32(w)) for w in iv) for iv in want], (u, v)
+    cp, z = od.dexelize(5, 6, box, axis="y")      # grid (z, x): z = 0..2, x = 1..4
+    for v in range(6):
+        for u in range(5):
+            want = [(0.3, 2.9)] if (u <= 2 and 1 <= v <= 4) else []
+            assert _col(cp, z, v * 5 + u) == [tuple(float(np.float32(w)) for w in iv) for iv in want], (u, v)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_rotated_set_matches_z(axis):
+    """Rotating every primitive so that the ray axis takes z's place gives,
+    bit for bit, the z-ray grid of the original set."""
+    rng = np.random.default_rng(11)
+    prims = []
+    for _ in range(25):
+        if rng.random() < 0.5:
+            prims.append((od.BALL, *rng.uniform(0, 20, 3), rng.uniform(1, 5), 0.0, 0.0))
+        else:
+            lo = rng.uniform(0, 20, 3)
+            prims.append((od.BOX, *lo, *(lo + rng.uniform(1, 6, 3))))
+    # world (x, y, z) -> coordinates whose (grid 1, grid 2, ray) frame is (x, y, z)
+    rot = {"x": lambda a: (a[2], a[0], a[1]), "y": lambda a: (a[1], a[2], a[0])}[axis]
+    moved = []
+    for p in prims:
+        a = rot(p[1:4])
+        b = rot(p[4:7]) if p[0] == od.BOX else p[4:7]
+        moved.append((p[0], *a, *b))
+    c0, z0 = od.dexelize(20, 20, prims)
+    c1, z1 = od.dexelize(20, 20, moved, axis=axis)
+    assert np.array_equal(c0, c1) and np.array_equal(z0, z1)
+
+
+@pytest.mark.parametrize("axis", ["z", "x", "y"])
+def test_ball_volume_each_axis(axis):
+    R = 20.0
+    cp, z = od.dexelize(64, 64, [(od.BALL, 32.1, 31.7, 30.4, R, 0.0, 0.0)], axis=axis)
+    vol = float(np.sum(z[1::2] - z[0::2]))
+    assert abs(vol / (4.0 / 3.0 * math.pi * R ** 3) - 1.0) < 0.01
 
 
 def test_ball_volume():
