@@ -7,7 +7,7 @@ intervals per column, 2.15e8 intervals), the 2048^2 configuration of the
 method's own scalability experiments.  One step = one closing of the whole
 grid, input resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices|dexelize|tridexel] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|c5|shell|slices|dexelize|tridexel|canonicalize] [--no-cpu-baseline]
 
 value   = input intervals offset per second (intervals of the input grid per
           operation, summed over the step's operations, divided by the step
@@ -90,6 +90,9 @@ WORKLOADS = {
     "tridexel": dict(desc="tri-dexel dilation r=8: the 512^3 soup of 1350 balls and boxes (the c2 primitives) "
                           "dexelised on the GPU along x, y and z, and the three 512x512 grids dilated in one "
                           "batched enqueue", ops=[]),
+    "canonicalize": dict(desc="canonical form of a non-canonical 2048x2048 grid: the dexelised soup of 5400 "
+                              "balls and boxes with every interval split in two overlapping halves and every "
+                              "column's list reversed (47M intervals in, 23.6M out)", ops=[]),
     "shell": dict(desc="shell (dilation minus erosion, then a per-column difference) r=4 of the "
                        "512x512 soup of 1350 spheres/boxes, the grid size and radius of the paper's "
                        "shell figure", ops=[]),
@@ -292,6 +295,98 @@ def run_tridexel(args, dx, torch):
                                           f"columns ({nc} columns, {nc * per_col:.0f} input-interval "
                                           f"equivalents), {dt:.2f} s; the oracle's dexelisation (pure "
                                           f"Python) is not included"}
+    print(json.dumps(line), flush=True)
+    eng.close()
+
+
+def run_canonicalize(args, dx, torch):
+    """canonicalize: dexel_canonicalize of a grid whose columns hold split,
+    reversed intervals; inputs resident in HBM."""
+    from oracle import canonical as oc
+    from synth import gen
+    n, count = 2048, 5400
+    rec = gen.primitive_records(7, n=n, count=count, smin=16.0, smax=256.0, height=float(n))
+    eng = dx.Engine(0)
+    soup = eng.dexelize(n, n, rec)
+    cp, z = soup.to_host()
+    ncols = n * n
+    pairs = z.reshape(-1, 2)
+    mid = (np.float32(0.5) * (pairs[:, 0] + pairs[:, 1])).astype(np.float32)
+    halves = np.stack([np.stack([pairs[:, 0], mid], 1), np.stack([mid, pairs[:, 1]], 1)], 1).reshape(-1, 2)
+    cp2 = 2 * cp
+    cnt2 = np.diff(cp2)
+    col = np.repeat(np.arange(ncols), cnt2)
+    j = np.arange(cp2[-1])
+    src = cp2[col] + cp2[col + 1] - 1 - j          # each column's list reversed
+    messy = np.ascontiguousarray(halves[src]).reshape(-1)
+    del halves, col, j, src
+    n_in = int(cp2[-1])
+    in_ptr = torch.as_tensor(cp2, dtype=torch.int64).cuda()
+    in_z = torch.as_tensor(messy, dtype=torch.float32).cuda()
+    view = dx.make_view(n, n, in_ptr, in_z, n_in)
+    out_ptr = torch.empty(ncols + 1, dtype=torch.int64, device="cuda")
+    out_z = torch.empty(2 * n_in, dtype=torch.float32, device="cuda")
+    nout = torch.zeros(1, dtype=torch.int64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = dx.make_out(n, n, out_ptr, out_z, nout, status)
+    ws = torch.empty(dx.dexel_canonicalize_workspace_size(eng.ctx, view), dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        dx.dexel_canonicalize(eng.ctx, view, out, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        st = dx.dexel_canonicalize(eng.ctx, view, out, ws)
+        if st != dx.DEXEL_OK:
+            raise RuntimeError(f"dexel_canonicalize enqueue failed: {st}")
+    e1.record()
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    if int(status.item()) != 0:
+        raise RuntimeError(f"dexel_canonicalize status {int(status.item())}")
+    n_out = int(nout.item())
+    if n_out != int(cp[-1]) or not torch.equal(out_ptr.cpu(), torch.as_tensor(cp)):
+        raise RuntimeError("canonical form differs from the dexelised soup")
+    ms_step = (te - ts) * 1000.0 / args.steps
+    ev_ms = e0.elapsed_time(e1) / args.steps
+    nbytes = 8 * (ncols + 1) + 8 * n_in + 8 * (ncols + 1) + 8 * n_out
+    gbs = nbytes / (ev_ms / 1000.0) / 1e9
+    line = {
+        "metric": "input dexel intervals canonicalised/sec",
+        "value": n_in / (ms_step / 1000.0),
+        "unit": "intervals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"canonicalize: {WORKLOADS['canonicalize']['desc']}", "grid": f"{n}x{n}",
+                   "nseg_in": n_in, "nseg_out": n_out},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                     "kernel": "k_canon, k_canon_long (count and write passes) and the scan",
+                     "kernel_ms": round(ev_ms, 4), "bytes_per_launch": int(nbytes)},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on whole grid rows from the middle until about the CPU budget
+        tc, rows, done = time.perf_counter(), 0, 0
+        y = n // 2
+        pr = messy.reshape(-1, 2).astype(np.float64)
+        while time.perf_counter() - tc < args.cpu_budget / 2 and rows < n:
+            for x in range(n):
+                c = (y + rows) * n + x
+                oc.column(pr[cp2[c]:cp2[c + 1]])
+                done += int(cp2[c + 1] - cp2[c])
+            rows += 1
+        dt = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": done / dt, "unit": "intervals/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{rows} grid rows from the middle ({rows * n} columns, {done} input "
+                                          f"intervals), {dt:.2f} s, pure Python, one thread"}
     print(json.dumps(line), flush=True)
     eng.close()
 
@@ -852,6 +947,8 @@ def main():
         return run_dexelize(args, dx, torch)
     if args.workload == "tridexel":
         return run_tridexel(args, dx, torch)
+    if args.workload == "canonicalize":
+        return run_canonicalize(args, dx, torch)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     grid = make_grid(args.workload)

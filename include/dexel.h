@@ -160,6 +160,29 @@ dexel_status dexel_csg_workspace_size(dexel_ctx* ctx, const dexel_grid_view* a, 
 dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_grid_view* b, int32_t op,
                        dexel_grid_out* out, void* ws, size_t ws_bytes, void* stream, uint32_t flags);
 
+/* Canonical form of a grid whose columns hold closed intervals in any order,
+ * overlapping freely: per column, the union of its intervals listed sorted,
+ * with intervals that overlap or touch joined (Sec. 3.1, "Dexel
+ * Representation"; the input form every offset call expects).  Endpoints are
+ * copied, never computed, so the result is exact.
+ *
+ * `in`: nx, ny, nseg, col_ptr (device int64[nx*ny+1], col_ptr[0] = 0,
+ * non-decreasing, col_ptr[nx*ny] = nseg) and z (device float32 pairs; within
+ * a column in any order).  Every interval must be finite with start <= end.
+ * A violation of either rule is reported as DEXEL_ERR_INVALID in
+ * out->status, and nothing is written.  `out`: same nx, ny, with cap_seg
+ * intervals of room (the result has at most nseg); on overflow out->status
+ * is DEXEL_ERR_CAPACITY and *out->nseg_out the need.  `ws`: device memory of
+ * dexel_canonicalize_workspace_size bytes (about 4 B per column and 8 B per
+ * input interval beyond dexel_csg's), 256-byte aligned, used during the call
+ * only.  DEXEL_FLAG_SYNC as for dexel_offset; DEXEL_FLAG_VALIDATE is not
+ * supported (the input is always checked).  A column whose running union
+ * stays within 32 intervals takes a fast path; any other is sorted by one
+ * GPU lane (O(m log m) for m intervals). */
+dexel_status dexel_canonicalize_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, size_t* bytes);
+dexel_status dexel_canonicalize(dexel_ctx* ctx, const dexel_grid_view* in, dexel_grid_out* out, void* ws,
+                                size_t ws_bytes, void* stream, uint32_t flags);
+
 /* Dexelisation of analytic primitives into an nx x ny grid (Sec. 1 and Sec.
  * 3.1, "Dexel Representation": the intersections of a solid with parallel
  * rays from a uniform 2D grid).  The rays are the z-parallel lines through

@@ -21,6 +21,7 @@ from .binding import (  # noqa: F401
     dexel_set_variant, CSG_OPS, DEXEL_CSG_DIFFERENCE, DEXEL_CSG_INTERSECT, DEXEL_CSG_UNION,
     dexel_csg, dexel_csg_workspace_size, DEXEL_PRIM_BALL, DEXEL_PRIM_BOX, dexel_dexelize,
     dexel_dexelize_workspace_size, DEXEL_FLAG_RAYS_X, DEXEL_FLAG_RAYS_Y, RAY_FLAGS,
+    dexel_canonicalize, dexel_canonicalize_workspace_size,
 )
 
 
@@ -180,6 +181,28 @@ class Engine:
                 continue
             raise DexelError(st, dexel_last_error(self.ctx))
         raise DexelError(DEXEL_ERR_CAPACITY, "retries exhausted")
+
+    def canonicalize(self, nx: int, ny: int, col_ptr, z, stream=None) -> DeviceGrid:
+        """Canonical grid (per column: sorted, overlapping or touching
+        intervals joined) from columns whose closed intervals come in any
+        order (dexel_canonicalize).  col_ptr: int64[nx*ny+1]; z: float32
+        pairs; host or device."""
+        cp = torch.as_tensor(col_ptr, dtype=torch.int64).reshape(-1).to(self.device).contiguous()
+        zz = torch.as_tensor(z, dtype=torch.float32).reshape(-1).to(self.device).contiguous()
+        nseg = zz.numel() // 2
+        if zz.numel() == 0:
+            zz = torch.zeros(2, dtype=torch.float32, device=self.device)
+        view = make_view(nx, ny, cp, zz, nseg)
+        ws = self.workspace(dexel_canonicalize_workspace_size(self.ctx, view))
+        col = torch.empty(int(nx) * int(ny) + 1, dtype=torch.int64, device=self.device)
+        out_z = torch.empty(2 * max(nseg, 1), dtype=torch.float32, device=self.device)
+        nout = torch.zeros(1, dtype=torch.int64, device=self.device)
+        status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        out = make_out(nx, ny, col, out_z, nout, status)
+        st = dexel_canonicalize(self.ctx, view, out, ws, stream, DEXEL_FLAG_SYNC)
+        if st != DEXEL_OK:
+            raise DexelError(st, dexel_last_error(self.ctx))
+        return DeviceGrid(nx, ny, col, out_z)
 
     def tridexel(self, dims, prims, stream=None) -> dict:
         """The solid sampled by rays along each of the three axes (the dexel

@@ -90,6 +90,11 @@ lib.dexel_dexelize_workspace_size.restype = c_int
 lib.dexel_dexelize.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_int32, _P(dexel_grid_out),
                                c_void_p, c_size_t, c_void_p, ctypes.c_uint32]
 lib.dexel_dexelize.restype = c_int
+lib.dexel_canonicalize_workspace_size.argtypes = [c_void_p, _P(dexel_grid_view), _P(c_size_t)]
+lib.dexel_canonicalize_workspace_size.restype = c_int
+lib.dexel_canonicalize.argtypes = [c_void_p, _P(dexel_grid_view), _P(dexel_grid_out), c_void_p, c_size_t,
+                                   c_void_p, ctypes.c_uint32]
+lib.dexel_canonicalize.restype = c_int
 lib.dexel_profile_enable.argtypes = [c_void_p, c_int]
 lib.dexel_profile_enable.restype = c_int
 lib.dexel_profile_read.argtypes = [c_void_p, _P(ctypes.c_double), _P(c_int64), c_int]
@@ -112,7 +117,7 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
             "dexel_autotune", "dexel_status_string", "dexel_last_error",
             "dexel_csg_workspace_size", "dexel_csg", "dexel_dexelize_workspace_size",
-            "dexel_dexelize"]
+            "dexel_dexelize", "dexel_canonicalize_workspace_size", "dexel_canonicalize"]
 NVARIANT = 4
 NPROF = 11
 PROFILE_STAGES = ["column_gaps", "row_offset", "row_offset_replay", "neighbour",
@@ -231,6 +236,19 @@ def dexel_dexelize(ctx, nx, ny, prims: torch.Tensor, out, ws: torch.Tensor, stre
     return lib.dexel_dexelize(ctx, int(nx), int(ny), _ptr(prims) if n else None, n,
                               ctypes.byref(out), _ptr(ws), int(ws.numel()), _stream_ptr(stream),
                               int(flags))
+
+
+def dexel_canonicalize_workspace_size(ctx, view) -> int:
+    b = c_size_t()
+    st = lib.dexel_canonicalize_workspace_size(ctx, ctypes.byref(view), ctypes.byref(b))
+    if st != DEXEL_OK:
+        raise DexelError(st, dexel_last_error(ctx))
+    return int(b.value)
+
+
+def dexel_canonicalize(ctx, view, out, ws: torch.Tensor, stream=None, flags: int = 0) -> int:
+    return lib.dexel_canonicalize(ctx, ctypes.byref(view), ctypes.byref(out), _ptr(ws), int(ws.numel()),
+                                  _stream_ptr(stream), int(flags))
 
 
 def dexel_batch_workspace_size(ctx, items, cap_hint: int = 0) -> int:

@@ -741,6 +741,77 @@ dexel_status dexel_csg(dexel_ctx* ctx, const dexel_grid_view* a, const dexel_gri
     return DEXEL_OK;
 }
 
+// The CSG layout (header, counts, scan), then the long-column list and the
+// scratch copy of the input intervals used by dexel_canonicalize.
+static size_t canon_layout(int64_t ncols, int64_t nseg, size_t* longc, size_t* sorted) {
+    size_t c, q, b;
+    size_t o = csg_layout(ncols, &c, &q, &b);
+    *longc = o;
+    o = align_up(o + 4 * (size_t)ncols);
+    *sorted = o;
+    return align_up(o + 8 * (size_t)nseg);
+}
+
+dexel_status dexel_canonicalize_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, size_t* bytes) {
+    if (!ctx || !bytes) return DEXEL_ERR_INVALID;
+    dexel_status st = check_view(ctx, in);
+    if (st != DEXEL_OK) return st;
+    size_t l, s;
+    *bytes = canon_layout((int64_t)in->nx * in->ny, in->nseg, &l, &s);
+    return DEXEL_OK;
+}
+
+dexel_status dexel_canonicalize(dexel_ctx* ctx, const dexel_grid_view* in, dexel_grid_out* out, void* ws,
+                                size_t ws_bytes, void* stream, uint32_t flags) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    ctx->err.clear();
+    dexel_status st = check_view(ctx, in);
+    if (st != DEXEL_OK) return st;
+    if (!out) return fail(ctx, DEXEL_ERR_INVALID, "null output");
+    if (out->nx != in->nx || out->ny != in->ny) return fail(ctx, DEXEL_ERR_INVALID, "output nx, ny differ");
+    if (flags & ~(DEXEL_FLAG_SYNC | DEXEL_FLAG_VALIDATE)) return fail(ctx, DEXEL_ERR_INVALID, "unknown flags");
+    if (flags & DEXEL_FLAG_VALIDATE)
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, "dexel_canonicalize always checks its input");
+    if (!out->col_ptr || !out->nseg_out || !out->status)
+        return fail(ctx, DEXEL_ERR_INVALID, "null output col_ptr, nseg_out or status");
+    if (out->cap_seg < 0 || (out->cap_seg > 0 && !out->z))
+        return fail(ctx, DEXEL_ERR_INVALID, "bad output capacity or null output z");
+    if (((uintptr_t)out->z) % 8 != 0) return fail(ctx, DEXEL_ERR_INVALID, "output z must be 8-byte aligned");
+    if (!ws) return fail(ctx, DEXEL_ERR_INVALID, "null workspace");
+    if (((uintptr_t)ws) % 256 != 0) return fail(ctx, DEXEL_ERR_INVALID, "workspace must be 256-byte aligned");
+    const int64_t ncols = (int64_t)in->nx * in->ny;
+    size_t o_cnt, o_scan, o_bsum, o_long, o_sorted;
+    csg_layout(ncols, &o_cnt, &o_scan, &o_bsum);
+    if (canon_layout(ncols, in->nseg, &o_long, &o_sorted) > ws_bytes)
+        return fail(ctx, DEXEL_ERR_WORKSPACE, "workspace smaller than dexel_canonicalize_workspace_size");
+    HIP_TRY(hipSetDevice(ctx->device));
+    char* w = (char*)ws;
+    dexel::CanonArgs g{};
+    g.in_ptr = in->col_ptr;
+    g.in_z = (const float2*)in->z;
+    g.nseg = in->nseg;
+    g.ncols = ncols;
+    g.hdr = (WsHeader*)w;
+    g.cnt = (int32_t*)(w + o_cnt);
+    g.scan = (int64_t*)(w + o_scan);
+    g.bsum = (int64_t*)(w + o_bsum);
+    g.out_ptr = out->col_ptr;
+    g.out_z = (float2*)out->z;
+    g.cap = out->cap_seg;
+    g.out_nseg = out->nseg_out;
+    g.out_status = out->status;
+    g.longc = (int32_t*)(w + o_long);
+    g.sorted = (float2*)(w + o_sorted);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(dexel::launch_canonicalize(g, s));
+    if (!(flags & DEXEL_FLAG_SYNC)) return DEXEL_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    int32_t dst = 0;
+    HIP_TRY(hipMemcpy(&dst, out->status, sizeof(dst), hipMemcpyDeviceToHost));
+    if (dst != 0) return fail(ctx, (dexel_status)dst, "device status " + std::to_string(dst));
+    return DEXEL_OK;
+}
+
 // The CSG layout (header, counts, scan) followed by the list of cell tiles
 // that the dexelisation redoes with the full per-column capacity.
 static size_t dex_layout(int32_t nx, int32_t ny, size_t* spill) {

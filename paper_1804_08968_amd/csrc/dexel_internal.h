@@ -172,6 +172,28 @@ struct DexArgs {
     int32_t* spill;       // [dexelize_tiles] tiles redone with DEX_CAP slots
 };
 constexpr int DEX_CAP = 64;  // most intervals one column may hold
+
+// Canonical form of per-column interval lists (dexel_canonicalize).  The
+// CSG workspace layout, then the list of long columns and a scratch copy of
+// the input intervals.
+struct CanonArgs {
+    const int64_t* in_ptr;
+    const float2* in_z;
+    int64_t nseg;
+    int64_t ncols;
+    WsHeader* hdr;
+    int32_t* cnt;
+    int64_t* scan;
+    int64_t* bsum;
+    int64_t* out_ptr;
+    float2* out_z;
+    int64_t cap;
+    int64_t* out_nseg;
+    int32_t* out_status;
+    int32_t* longc;       // [ncols] columns left to the sorting tier (count in hdr->novf[0])
+    float2* sorted;       // [nseg] the sorting tier's copies, at the columns' own input offsets
+};
+hipError_t launch_canonicalize(const CanonArgs& a, hipStream_t s);
 int64_t dexelize_tiles(int32_t nx, int32_t ny);
 hipError_t launch_dexelize(const DexArgs& a, hipStream_t s);
 

@@ -2326,6 +2326,185 @@ hipError_t launch_csg(const CsgArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// canonical form of per-column interval lists
+// ---------------------------------------------------------------------------
+//
+// A dexel column is a set of closed z-intervals (Sec. 3.1, "Dexel
+// Representation"); its canonical form, the input form of every offset,
+// lists that set sorted, with overlapping or touching intervals joined.
+// The first tier gives one lane per column a canonical LDS list of
+// CANON_CAP slots and inserts the column's intervals into it in input order
+// (the union does not depend on the order).  A column whose list runs out
+// is left to the sorting tier: one lane copies the column's intervals into
+// the scratch array at the column's own input offset, sorts them in place
+// by (start, end) (heapsort), and sweeps them once.  The count pass also
+// checks the input: column pointers inside [0, nseg] and non-decreasing,
+// and every interval finite with start <= end.
+
+constexpr int CANON_CAP = 32;
+
+__device__ __forceinline__ bool canon_ok(float2 v) {
+    return v.x <= v.y && __builtin_isfinite(v.x) && __builtin_isfinite(v.y);
+}
+
+__device__ __forceinline__ bool canon_less(float2 a, float2 b) {
+    return a.x < b.x || (a.x == b.x && a.y < b.y);
+}
+
+// Heapsort of s[0..m) by (start, end), in place.
+__device__ void canon_heapsort(float2* s, int64_t m) {
+    auto sift = [&](int64_t i, int64_t end) {
+        const float2 v = s[i];
+        while (true) {
+            int64_t ch = 2 * i + 1;
+            if (ch >= end) break;
+            float2 cv = s[ch];
+            if (ch + 1 < end) {
+                const float2 c2 = s[ch + 1];
+                if (canon_less(cv, c2)) {
+                    ++ch;
+                    cv = c2;
+                }
+            }
+            if (!canon_less(v, cv)) break;
+            s[i] = cv;
+            i = ch;
+        }
+        s[i] = v;
+    };
+    for (int64_t i = m / 2 - 1; i >= 0; --i) sift(i, m);
+    for (int64_t end = m - 1; end > 0; --end) {
+        const float2 t = s[0];
+        s[0] = s[end];
+        s[end] = t;
+        sift(0, end);
+    }
+}
+
+template <bool WRITE>
+__global__ void __launch_bounds__(WG) k_canon(CanonArgs A) {
+    __shared__ float2 lds[CANON_CAP * WG];
+    const int64_t c = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (c >= A.ncols) return;
+    // after an error of the count pass the scan did not run: write nothing
+    if (WRITE && A.hdr->abort) return;
+    const int64_t b = gld(&A.in_ptr[c]), e = gld(&A.in_ptr[c + 1]);
+    if (!WRITE && (b < 0 || e < b || e > A.nseg || (c == 0 && b != 0) ||
+                   (c == A.ncols - 1 && e != A.nseg))) {
+        set_error(A.hdr, DEXEL_ERR_INVALID);
+        gst(&A.cnt[c], 0);
+        return;
+    }
+    LdsList U{&lds[threadIdx.x], CANON_CAP};
+    int n = 0;
+    bool bad = false, over = false;
+    for (int64_t i = b; i < e; ++i) {
+        const float2 v = gld(&A.in_z[i]);
+        if (!canon_ok(v)) {
+            bad = true;
+            break;
+        }
+        const int m = lv_insert(U, n, v.x, v.y);
+        if (m < 0) {
+            over = true;
+            break;
+        }
+        n = m;
+    }
+    if (!WRITE) {
+        if (bad) {
+            set_error(A.hdr, DEXEL_ERR_INVALID);
+            gst(&A.cnt[c], 0);
+        } else if (over) {
+            const int k = atomicAdd(&A.hdr->novf[0], 1);   // the sorting tier counts it
+            gst(&A.longc[k], (int32_t)c);
+        } else {
+            gst(&A.cnt[c], n);
+        }
+        return;
+    }
+    const int64_t total = gld(&A.scan[A.ncols]);
+    const int64_t off = gld(&A.scan[c]);
+    gst(&A.out_ptr[c], off);
+    if (c == 0) {
+        gst(&A.out_ptr[A.ncols], total);
+        gst(A.out_nseg, total);
+    }
+    if (total > A.cap || over) return;
+    for (int i = 0; i < n; ++i) gst(&A.out_z[off + i], U.get(i));
+}
+
+// The sorting tier: one lane per listed column, a fixed grid walking the
+// list.  The count pass copies, checks and sorts; the write pass sweeps the
+// sorted copy again.
+template <bool WRITE>
+__global__ void __launch_bounds__(WG) k_canon_long(CanonArgs A) {
+    const int nl = A.hdr->novf[0];
+    for (int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x; i < nl; i += (int64_t)gridDim.x * WG) {
+        if (WRITE && A.hdr->abort) return;
+        const int64_t c = gld(&A.longc[i]);
+        const int64_t b = gld(&A.in_ptr[c]), e = gld(&A.in_ptr[c + 1]);
+        float2* s = A.sorted + b;
+        const int64_t m = e - b;
+        if (m > INT32_MAX) {   // a count must fit the per-column int32 counts
+            set_error(A.hdr, DEXEL_ERR_UNSUPPORTED);
+            if (!WRITE) gst(&A.cnt[c], 0);
+            continue;
+        }
+        if (!WRITE) {
+            bool bad = false;
+            for (int64_t k = 0; k < m; ++k) {
+                const float2 v = gld(&A.in_z[b + k]);
+                bad |= !canon_ok(v);
+                s[k] = v;
+            }
+            if (bad) {
+                set_error(A.hdr, DEXEL_ERR_INVALID);
+                gst(&A.cnt[c], 0);
+                continue;
+            }
+            canon_heapsort(s, m);
+        }
+        const int64_t off = WRITE ? gld(&A.scan[c]) : 0;
+        const bool put = WRITE && gld(&A.scan[A.ncols]) <= A.cap;
+        int64_t n = 0;
+        float2 cur = make_float2(0.f, 0.f);
+        for (int64_t k = 0; k < m; ++k) {
+            const float2 v = s[k];
+            if (n > 0 && v.x <= cur.y) {
+                cur.y = fmaxf(cur.y, v.y);
+            } else {
+                if (n > 0 && put) gst(&A.out_z[off + n - 1], cur);
+                cur = v;
+                ++n;
+            }
+        }
+        if (n > 0 && put) gst(&A.out_z[off + n - 1], cur);
+        if (!WRITE) gst(&A.cnt[c], (int32_t)n);
+    }
+}
+
+// The device status: an error of the count pass, else capacity.
+__global__ void k_canon_status(CanonArgs A) {
+    const int st = A.hdr->status;
+    A.out_status[0] = st != 0 ? st : (A.scan[A.ncols] > A.cap ? (int32_t)DEXEL_ERR_CAPACITY : (int32_t)DEXEL_OK);
+}
+
+hipError_t launch_canonicalize(const CanonArgs& a, hipStream_t s) {
+    const unsigned nb = (unsigned)((a.ncols + WG - 1) / WG);
+    const unsigned nlong = nb < 256u ? nb : 256u;
+    hipLaunchKernelGGL(k_init_call, dim3(1), dim3(256), 0, s, a.hdr, (int32_t*)nullptr, 0);
+    hipLaunchKernelGGL(k_canon<false>, dim3(nb), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_canon_long<false>, dim3(nlong), dim3(WG), 0, s, a);
+    hipError_t e = scan_counts(a.cnt, a.ncols, a.bsum, a.scan, a.hdr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_canon<true>, dim3(nb), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_canon_long<true>, dim3(nlong), dim3(WG), 0, s, a);
+    hipLaunchKernelGGL(k_canon_status, dim3(1), dim3(1), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // dexelisation of analytic primitives
 // ---------------------------------------------------------------------------
 //
