@@ -110,6 +110,10 @@ constexpr int K2_DEFER_NI = 16;
 constexpr int SEED_META = 1 + 65;
 constexpr int K3_DEFER_N = 16;
 constexpr int CAP_MID = 48;  // LDS list capacity of the one-lane-per-column replays of K1b and K3
+// LDS list capacity of K1's lane replay: 40 entries hold the partial unions
+// of the columns it gets as a rule (20-40 intervals on lattice-like input)
+// while letting eight of its waves share a CU (48 entries: six).
+constexpr int K1_FB_CAP = 40;
 constexpr int CAP_Z = 32;
 
 // ---------------------------------------------------------------------------
@@ -1517,9 +1521,9 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
 }
 
 // Replay of K1 for columns whose list overflowed: one lane per column over the
-// full grid, a CAP_MID-entry LDS list first, then the growing arena tier.
+// full grid, a K1_FB_CAP-entry LDS list first, then the growing arena tier.
 __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
-    __shared__ float2 lds[CAP_MID * WG];
+    __shared__ float2 lds[K1_FB_CAP * WG];
     if (Q.hdr->abort) return;
     const int cnt = Q.hdr->novf[ST_K1];
     if ((int64_t)blockIdx.x * WG >= cnt) return;
@@ -1530,7 +1534,7 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     const OpParams P = make_op(Q, Q.shapes[s]);
     const int64_t c = g - Q.sbase[s];
     {
-        LdsList L{&lds[threadIdx.x], CAP_MID};
+        LdsList L{&lds[threadIdx.x], K1_FB_CAP};
         const int n = k1_column(P, c, L);
         if (n >= 0) {
             emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
