@@ -916,7 +916,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the offset of one "
-              "grid is not split across GPUs in this build.", file=sys.stderr)
+              "grid is not split across GPUs by this library.", file=sys.stderr)
         sys.exit(2)
 
     import torch
