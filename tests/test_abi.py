@@ -117,6 +117,8 @@ def test_null_arguments_rejected_on_host(lib):
     assert b.lib.dexel_csg(None, ctypes.byref(view), ctypes.byref(view), 0, None, None, 0, None, 0) == inv
     assert b.lib.dexel_dexelize_workspace_size(None, 4, 4, ctypes.byref(nbytes)) == inv
     assert b.lib.dexel_dexelize(None, 4, 4, None, 0, None, None, 0, None, 0) == inv
+    assert b.lib.dexel_canonicalize_workspace_size(None, ctypes.byref(view), ctypes.byref(nbytes)) == inv
+    assert b.lib.dexel_canonicalize(None, ctypes.byref(view), None, None, 0, None, 0) == inv
     b.lib.dexel_ctx_destroy(None)          # no-op
 
 
