@@ -621,7 +621,7 @@ def dex_candidate_pairs(rec, n):
     ball = rec[:, 0] == 0.0
     lo = np.where(ball[:, None], rec[:, 1:3] - rec[:, 4:5], rec[:, 1:3])
     hi = np.where(ball[:, None], rec[:, 1:3] + rec[:, 4:5], rec[:, 4:6])
-    a = np.clip(np.ceil(lo - 0.5), 0, n - 1)
+    a = np.clip(np.ceil(lo - 0.5), 0, n)
     b = np.clip(np.floor(hi - 0.5), -1, n - 1)
     w = np.maximum(b - a + 1, 0)
     return int(np.sum(w[:, 0] * w[:, 1]))
