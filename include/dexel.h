@@ -203,9 +203,9 @@ dexel_status dexel_canonicalize(dexel_ctx* ctx, const dexel_grid_view* in, dexel
  * dexel_csg; DEXEL_FLAG_VALIDATE is not supported.
  *
  * Rays along another axis (the dexel structures in three orthogonal
- * directions of Sec. 5, "Limitations", and Sec. 6): with DEXEL_FLAG_RAYS_X
- * the grid's two axes are y and z (nx cells along y, ny along z) and the
- * intervals lie along x; with DEXEL_FLAG_RAYS_Y they are z and x and the
+ * directions suggested in the "Limitations" paragraph of Sec. 4 and in
+ * Sec. 5): with DEXEL_FLAG_RAYS_X the grid's two axes are y and z (nx cells
+ * along y, ny along z) and the intervals lie along x; with DEXEL_FLAG_RAYS_Y they are z and x and the
  * intervals lie along y.  The rules above apply with the coordinates taken
  * in that order, (a1, a2, a0) or (a2, a0, a1), and likewise for b; a ball's
  * radius is b0 in every case.  Both flags together: DEXEL_ERR_INVALID. */

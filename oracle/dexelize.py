@@ -22,7 +22,7 @@ Primitive records: (kind, a0, a1, a2, b0, b1, b2) with kind 0 = ball (a =
 centre, b0 = radius) and kind 1 = box (a = low corner, b = high corner).
 
 Rays along another axis (dexel structures in three orthogonal directions,
-Sec. 5, "Limitations", and Sec. 6): for rays along axis k the grid's two axes
+the "Limitations" paragraph of Sec. 4, and Sec. 5): for rays along axis k the grid's two axes
 are (k + 1) mod 3 and (k + 2) mod 3, in that order, and the intervals lie
 along k; so rays along x give a grid over (y, z), rays along y one over
 (z, x).  The rules above then apply to the coordinates in that order.

@@ -206,8 +206,8 @@ class Engine:
 
     def tridexel(self, dims, prims, stream=None) -> dict:
         """The solid sampled by rays along each of the three axes (the dexel
-        structures in three orthogonal directions of Sec. 5, "Limitations",
-        and Sec. 6).  dims = (n0, n1, n2) cells along x, y, z.  Returns
+        structures in three orthogonal directions suggested in the "Limitations"
+        paragraph of Sec. 4 and in Sec. 5).  dims = (n0, n1, n2) cells along x, y, z.  Returns
         {"x": n1 x n2 grid over (y, z), "y": n2 x n0 grid over (z, x),
         "z": n0 x n1 grid over (x, y)}."""
         n0, n1, n2 = (int(d) for d in dims)

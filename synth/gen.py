@@ -11,8 +11,8 @@ Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64).
 from __future__ import annotations
 
 import math
-import multiprocessing
 import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -289,7 +289,10 @@ def gyroid_grid(seed: int, n: int = 2048, height: float | None = None,
     M = sqrt(sin^2 kY + cos^2 kX), theta = atan2(cos kX, sin kY).
     ``rows`` restricts generation to y in [rows[0], rows[1]) (same values as
     the full grid there; the returned grid then has ny = rows[1] - rows[0]).
-    Rows are generated in independent chunks (in parallel for large grids).
+    Rows are generated in independent chunks, in parallel threads for large
+    grids (numpy releases the GIL in its array kernels).  No process is
+    forked: callers may already hold GPU state, which a forked child must
+    not inherit.
     """
     rng = np.random.default_rng(seed)
     ph = rng.uniform(0.0, period, size=3)
@@ -300,9 +303,8 @@ def gyroid_grid(seed: int, n: int = 2048, height: float | None = None,
     if workers is None:
         workers = min(16, os.cpu_count() or 1) if len(jobs) >= 8 else 1
     if workers > 1:
-        ctx = multiprocessing.get_context("fork")
-        with ctx.Pool(workers) as pool:
-            parts = pool.map(_gyroid_rows, jobs)
+        with ThreadPoolExecutor(workers) as pool:
+            parts = list(pool.map(_gyroid_rows, jobs))
     else:
         parts = [_gyroid_rows(j) for j in jobs]
     counts = np.concatenate([p[0] for p in parts]).astype(np.int64)

@@ -1,6 +1,6 @@
 """GPU parity of the tri-dexel offset: a solid dexelised along x, y and z
-(three orthogonal dexel structures, Sec. 5 "Limitations" and Sec. 6), each
-structure offset by the same ball, through the C ABI.
+(three orthogonal dexel structures: the "Limitations" paragraph of Sec. 4,
+and Sec. 5), each structure offset by the same ball, through the C ABI.
 
 * Each direction, bit-exact against the oracle: its dexelisation along that
   axis, then its offset in the float32 model; and within tolerance of FP64.
