@@ -136,18 +136,92 @@ def kernel_bytes(stage, ncols, n_in, st):
 _ZERO_STATS = {"row_offset": 0, "neighbour": 0, "seeds": 0, "result": 0}
 
 
+def stage_roofline(dx, per_step, pass_stats, ncols):
+    """Roofline of the dominant stage over a profiled run.
+
+    The dominant stage is the costliest by its main kernel plus its replay
+    kernel (which finishes the same output for the columns whose lists
+    overflowed).  ``frac`` is the main kernel's: its algorithmic bytes per
+    launch over its average launch duration; ``stage_frac`` charges the
+    replay's time too.  One launch per pass."""
+    stages = dx.PROFILE_STAGES
+    modelled = [s for s in stages if kernel_bytes(s, 1, 0, _ZERO_STATS) is not None]
+    tot = {s: per_step[s] + per_step.get(s + "_replay", 0.0) for s in modelled}
+    dom = max(modelled, key=tot.get)
+    launches = max(1, len(pass_stats))
+    dom_ms = per_step[dom] / launches
+    stage_ms = tot[dom] / launches
+    bpl = sum(kernel_bytes(dom, ncols, n_in, st) for n_in, st in pass_stats) / launches
+    achieved = bpl / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
+    st_ach = bpl / (stage_ms / 1000.0) / 1e9 if stage_ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": dx.PROFILE_KERNELS[stages.index(dom)], "kernel_ms": round(dom_ms, 4),
+            "bytes_per_launch": int(bpl), "stage": dom, "stage_ms": round(stage_ms, 4),
+            "stage_frac": round(st_ach / HBM_PEAK_GBS, 5)}
+
+
+def pass_bytes(ncols, n_in, st):
+    """(B_alg, B_min) of one pass.  B_alg: read the input, write and read
+    the x-stage pieces once (8 B of interval plus a 1-byte tag each, with
+    their column offsets), write the output.  B_min: input and output
+    only, what a fused pass that never stores the pieces would move."""
+    ptr = 8 * (ncols + 1)
+    io = ptr + 8 * n_in + ptr + 8 * st["result"]
+    return io + 2 * (ptr + 9 * st["seeds"]), io
+
+
+def step_roofline(pass_stats, ncols, ms_per_step):
+    """Whole-step fractions of the HBM peak from B_alg and B_min."""
+    b_alg = sum(pass_bytes(ncols, n, st)[0] for n, st in pass_stats)
+    b_min = sum(pass_bytes(ncols, n, st)[1] for n, st in pass_stats)
+    t = ms_per_step / 1000.0
+    return {"step_bytes_alg": int(b_alg), "step_bytes_min": int(b_min),
+            "step_frac_alg": round(b_alg / t / 1e9 / HBM_PEAK_GBS, 5),
+            "step_frac_min": round(b_min / t / 1e9 / HBM_PEAK_GBS, 5)}
+
+
+def measure_copy_gbs(torch, mib=1024, reps=5):
+    """Device-to-device bandwidth of a plain elementwise kernel (reads and
+    writes `mib` MiB), median over `reps` runs timed with HIP events."""
+    nb = mib << 20
+    src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.add(src, 1, out=dst)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.add(src, 1, out=dst)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del src, dst
+    return round(2 * nb / (float(np.median(ts)) / 1000.0) / 1e9, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def pass_list(op):
     return {"dilate": ["dilate"], "erode": ["erode"], "close": ["dilate", "erode"],
             "open": ["erode", "dilate"]}[op]
 
 
-def cpu_baseline(grid, ops, budget_s=20.0):
-    """Time the float64 oracle on a square tile of output columns."""
+def _oracle_tile_rate(grid, op, r, budget_s):
+    """Input intervals per second of the float64 oracle on a square tile of
+    output columns from the grid's middle, grown until it takes about a
+    quarter of `budget_s` or more."""
     import oracle
-    op, r = ops[0]
     n = 4
-    best = None
-    cores = oracle.num_threads()
     while True:
         x0 = max(0, grid.nx // 2 - n // 2)
         y0 = max(0, grid.ny // 2 - n // 2)
@@ -160,17 +234,31 @@ def cpu_baseline(grid, ops, budget_s=20.0):
         else:
             oracle.region_chain(grid, r, op, cols, "f64")
         dt = time.perf_counter() - t0
-        best = (cols.size, dt, n)
         if dt * 4 > budget_s or cols.size >= grid.nx * grid.ny:
             break
         n *= 2
-    ncols_s, dt, n = best
     per_col = grid.nseg / float(grid.nx * grid.ny)
-    segs = ncols_s * per_col
-    return {"value": segs / dt, "unit": "input segments/s", "cores": cores, "kind": "oracle",
-            "sample": f"{op} r={r} on a {n}x{n} tile of output columns ({ncols_s} columns, "
-                      f"{segs:.0f} input-interval equivalents at {per_col:.2f} per column), "
-                      f"{dt:.2f} s"}
+    segs = cols.size * per_col
+    return segs / dt, (f"{n}x{n} tile of output columns ({cols.size} columns, {segs:.0f} "
+                       f"input-interval equivalents at {per_col:.2f} per column), {dt:.2f} s")
+
+
+def cpu_baseline(grid, ops, budget_s=20.0):
+    """Time the float64 oracle on a tile of output columns, on every host
+    thread it uses and on one thread."""
+    import oracle
+    op, r = ops[0]
+    cores = oracle.num_threads()
+    v_all, s_all = _oracle_tile_rate(grid, op, r, budget_s)
+    oracle.set_num_threads(1)
+    try:
+        v_one, s_one = _oracle_tile_rate(grid, op, r, budget_s / 2)
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": v_all, "unit": "input segments/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{op} r={r} on a {s_all}",
+            "one_thread": {"value": v_one, "sample": f"{op} r={r} on a {s_one}"}}
 
 
 def csg_bytes(ncols, na, nb, nout):
@@ -204,7 +292,7 @@ def run_tridexel(args, dx, torch):
     bp = dx.BatchPlan(eng, [tri[a] for a in axes], [r] * 3, ["dilate"] * 3)
     chosen, var_ms = bp.autotune(reps=2)
     bp.enqueue(flags=dx.DEXEL_FLAG_SYNC)
-    stats = dx.dexel_workspace_stats(eng.ctx, eng.workspace(bp.ws_bytes))
+    stats = dx.dexel_workspace_stats(eng.ctx, bp.ws)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
 
     def step(i=None):
@@ -243,11 +331,7 @@ def run_tridexel(args, dx, torch):
     off_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
     stages = dx.PROFILE_STAGES
     per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
-    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
-    dom = max(modelled, key=per_step.get)
-    dom_ms = per_step[dom]
-    dom_bytes = kernel_bytes(dom, ncols, n_in, stats)
-    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    roof = stage_roofline(dx, per_step, [(n_in, stats)], ncols)
     line = {
         "metric": "input dexel segments offset/sec",
         "value": n_in / (ms_step / 1000.0),
@@ -265,10 +349,7 @@ def run_tridexel(args, dx, torch):
                    "primitives": len(rec), "r": r, "nseg_in": nseg},
         "dexelize_ms_per_step": round(dex_ms, 4),
         "offset_ms_per_step": round(off_ms, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)], "kernel_ms": round(dom_ms, 4),
-                     "bytes_per_launch": int(dom_bytes)},
+        "roofline": roof,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "variant": chosen,
     }
@@ -407,7 +488,7 @@ def run_shell(args, dx, torch):
     pass_stats = []
     for p in (pd_, pe_):
         p.enqueue(flags=dx.DEXEL_FLAG_SYNC)
-        pass_stats.append((dg.nseg, dx.dexel_workspace_stats(eng.ctx, eng.workspace(p.ws_bytes))))
+        pass_stats.append((dg.nseg, dx.dexel_workspace_stats(eng.ctx, p.ws)))
     nd, ne = pd_.nseg_out, pe_.nseg_out
     va = dx.make_view(grid.nx, grid.ny, pd_.col, pd_.z, nd)
     vb = dx.make_view(grid.nx, grid.ny, pe_.col, pe_.z, ne)
@@ -455,11 +536,7 @@ def run_shell(args, dx, torch):
     csg_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     stages = dx.PROFILE_STAGES
     per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
-    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
-    dom = max(modelled, key=per_step.get)
-    dom_ms = per_step[dom] / 2.0
-    dom_bytes = sum(kernel_bytes(dom, ncols, n_in, st) for n_in, st in pass_stats) / 2.0
-    achieved = dom_bytes / (dom_ms / 1000.0) / 1e9
+    roof = stage_roofline(dx, per_step, pass_stats, ncols)
     cb = csg_bytes(ncols, nd, ne, nshell)
     csg_gbs = cb / (csg_ms / 1000.0) / 1e9
     line = {
@@ -478,10 +555,7 @@ def run_shell(args, dx, torch):
         "config": {"workload": f"shell: {WORKLOADS['shell']['desc']}", "grid": f"{grid.nx}x{grid.ny}",
                    "nseg_in": grid.nseg, "r": r, "nseg_dilation": nd, "nseg_erosion": ne,
                    "nseg_shell": nshell},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)], "kernel_ms": round(dom_ms, 4),
-                     "bytes_per_launch": int(dom_bytes)},
+        "roofline": roof,
         "csg": {"bound": "hbm", "achieved": round(csg_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(csg_gbs / HBM_PEAK_GBS, 5), "kernels": "k_csg_count, scan, k_csg_write",
                 "ms_per_call": round(csg_ms, 4), "bytes_per_call": int(cb)},
@@ -539,7 +613,7 @@ def run_slices(args, dx, torch):
     print(f"[bench] slices ready ({time.perf_counter() - t0:.1f} s), variant {chosen}", file=sys.stderr,
           flush=True)
     bp.enqueue(flags=dx.DEXEL_FLAG_SYNC)
-    st = dx.dexel_workspace_stats(eng.ctx, eng.workspace(bp.ws_bytes))
+    st = dx.dexel_workspace_stats(eng.ctx, bp.ws)
     for _ in range(args.warmup):
         bp.enqueue()
     torch.cuda.synchronize()
@@ -558,11 +632,8 @@ def run_slices(args, dx, torch):
     ms_step = (te - ts) * 1000.0 / args.steps
     stages = dx.PROFILE_STAGES
     per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(stages)}
-    modelled = [s_ for s_ in stages if kernel_bytes(s_, 1, 0, _ZERO_STATS) is not None]
-    dom = max(modelled, key=per_step.get)
     ncols = nx * ny
-    dom_bytes = kernel_bytes(dom, ncols, g.nseg, st)
-    achieved = dom_bytes / (per_step[dom] / 1000.0) / 1e9
+    roof = stage_roofline(dx, per_step, [(g.nseg, st)], ncols)
     line = {
         "metric": "input dexel segments offset/sec",
         "value": g.nseg / (ms_step / 1000.0),
@@ -579,10 +650,7 @@ def run_slices(args, dx, torch):
         "config": {"workload": f"slices: {WORKLOADS['slices']['desc']}", "slices": ny,
                    "columns_per_slice": nx, "nseg_in": g.nseg, "r": r,
                    "nseg_out": sum(o for o in bp.nseg_out)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "kernel": dx.PROFILE_KERNELS[stages.index(dom)],
-                     "kernel_ms": round(per_step[dom], 4), "bytes_per_launch": int(dom_bytes)},
+        "roofline": roof,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per_step.items()},
         "variant": chosen,
     }
@@ -965,7 +1033,7 @@ def main():
         for p in pass_list(op):
             plan = dx.Plan(eng, cur, r, p)
             plan.enqueue(flags=dx.DEXEL_FLAG_SYNC)
-            st = dx.dexel_workspace_stats(eng.ctx, eng.workspace(plan.ws_bytes))
+            st = dx.dexel_workspace_stats(eng.ctx, plan.ws)
             pass_stats.append((cur.nseg, st))
             cur = plan.result()
     plans = [dx.Plan(eng, dg, r, op) for op, r in wl["ops"]]
@@ -976,47 +1044,45 @@ def main():
         for p in plans:
             p.enqueue()
     torch.cuda.synchronize()
-    dx.dexel_profile_read(eng.ctx, reset=True)
-    dx.dexel_profile_enable(eng.ctx, True)
+
+    # timed region: K whole steps with the library's profiling events off;
+    # one HIP event per step boundary on the stream the plans run on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
+    ev[0].record()
+    for i in range(args.steps):
+        for p in plans:
+            p.enqueue()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    for p in plans:
+        if p.status() != 0:
+            raise RuntimeError(f"device status {p.status()} for {p.op}")
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+
+    # kernel breakdown: the same K steps again with the library's stage
+    # events on (recorded on its stream), for the roofline
+    dx.dexel_profile_read(eng.ctx, reset=True)
+    dx.dexel_profile_enable(eng.ctx, True)
     for _ in range(args.steps):
         for p in plans:
             p.enqueue()
     torch.cuda.synchronize()
-    t_end = time.perf_counter()
     dx.dexel_profile_enable(eng.ctx, False)
     prof_ms, passes = dx.dexel_profile_read(eng.ctx, reset=True)
-    for p in plans:
-        if p.status() != 0:
-            raise RuntimeError(f"device status {p.status()} for {p.op}")
 
     ms_per_step = (t_end - t_start) * 1000.0 / args.steps
     n_in_step = sum(p.nseg_in for p in plans)
     value = n_in_step / (ms_per_step / 1000.0)
-
-    # dominant kernel over the timed region: the main kernel of the costliest
-    # stage (a stage's replay kernel finishes the same output for the columns
-    # whose lists overflowed; its time is reported in kernels_ms_per_step)
-    stages = dx.PROFILE_STAGES
-    per_step = {s: prof_ms[i] / args.steps for i, s in enumerate(stages)}
-    modelled = [s for s in stages if kernel_bytes(s, 1, 0, _ZERO_STATS) is not None]
-    dom = max(modelled, key=per_step.get)
-    dom_launches_per_step = len(pass_stats)
-    dom_ms = per_step[dom] / dom_launches_per_step
-    tot_bytes = 0
-    for n_in, st in pass_stats:
-        b = kernel_bytes(dom, ncols, n_in, st)
-        tot_bytes += b if b is not None else 0
-    bytes_per_launch = tot_bytes / max(1, len(pass_stats))
-    achieved = bytes_per_launch / (dom_ms / 1000.0) / 1e9 if dom_ms > 0 else 0.0
-    kname = dx.PROFILE_KERNELS[stages.index(dom)]
+    per_step = {s_: prof_ms[i] / args.steps for i, s_ in enumerate(dx.PROFILE_STAGES)}
+    roofline = stage_roofline(dx, per_step, pass_stats, ncols)
+    kname = roofline["kernel"]
     traffic = measured_traffic(kname) if args.workload == "c3" else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": int(traffic) if traffic is not None else None,
-                "kernel": kname, "kernel_ms": round(dom_ms, 4),
-                "bytes_per_launch": int(bytes_per_launch)}
+    roofline["traffic"] = int(traffic) if traffic is not None else None
+    roofline.update(step_roofline(pass_stats, ncols, ms_per_step))
+    roofline["copy_GBs_measured"] = measure_copy_gbs(torch)
 
     line = {
         "metric": "input dexel segments offset/sec",
@@ -1026,6 +1092,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_median": float(np.median(step_ms)),
+        "ms_per_step_min_max": [float(np.min(step_ms)), float(np.max(step_ms))],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

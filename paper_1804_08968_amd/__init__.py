@@ -235,9 +235,12 @@ class Plan:
     """A pre-sized offset call for repeated asynchronous enqueues.
 
     Construction runs the op once synchronously (learning the workspace and
-    output sizes), then keeps the output buffers and the call arguments.
+    output sizes), then keeps the output buffers, its own workspace and the
+    call arguments for its lifetime, so that an enqueue (or a captured graph
+    replaying one) never writes into memory another call may reallocate.
     ``enqueue`` issues the call on a stream without synchronising;
-    ``status()`` reads the device status of the last call.
+    ``status()`` reads the device status of the last call.  Enqueues of one
+    plan on two streams that may overlap race on its workspace: order them.
     """
 
     def __init__(self, engine: "Engine", grid: DeviceGrid, r: float, op: str):
@@ -256,11 +259,11 @@ class Plan:
         self.out = make_out(grid.nx, grid.ny, self.col, self.z, self.nout, self.status_t)
         self.ws_bytes = dexel_workspace_size(engine.ctx, self.view, self.r, self.code,
                                              engine.last_hint)
-        engine.workspace(self.ws_bytes)
+        self.ws = torch.empty(int(self.ws_bytes), dtype=torch.uint8, device=dev)
 
     def enqueue(self, stream=None, flags: int = 0) -> None:
-        ws = self.engine.workspace(self.ws_bytes)
-        st = dexel_offset(self.engine.ctx, self.view, self.r, self.code, self.out, ws, stream, flags)
+        st = dexel_offset(self.engine.ctx, self.view, self.r, self.code, self.out, self.ws, stream,
+                          flags)
         if st != DEXEL_OK:
             raise DexelError(st, dexel_last_error(self.engine.ctx))
 
@@ -272,8 +275,7 @@ class Plan:
         it.r = self.r
         it.op = self.code
         it.out = self.out
-        ws = self.engine.workspace(self.ws_bytes)
-        return dexel_autotune(self.engine.ctx, [it], ws, stream, reps)
+        return dexel_autotune(self.engine.ctx, [it], self.ws, stream, reps)
 
     def status(self) -> int:
         return int(self.status_t.item())
@@ -334,7 +336,7 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
 class BatchPlan:
     """A pre-sized batch for repeated asynchronous enqueues (and graph
     capture): construction runs the batch once synchronously to size the
-    outputs and the workspace."""
+    outputs and the workspace, which the plan then owns for its lifetime."""
 
     def __init__(self, engine: "Engine", grids, radii, ops):
         self.engine = engine
@@ -352,17 +354,15 @@ class BatchPlan:
                      for g, n in zip(self.grids, self.nseg_out)]
         self.items = _items(self.grids, self.radii, self.ops, self.outs)
         self.ws_bytes = dexel_batch_workspace_size(engine.ctx, self.items, engine.last_hint)
-        engine.workspace(self.ws_bytes)
+        self.ws = torch.empty(int(self.ws_bytes), dtype=torch.uint8, device=dev)
 
     def enqueue(self, stream=None, flags: int = 0) -> None:
-        ws = self.engine.workspace(self.ws_bytes)
-        st = dexel_batch_offset(self.engine.ctx, self.items, ws, stream, flags)
+        st = dexel_batch_offset(self.engine.ctx, self.items, self.ws, stream, flags)
         if st != DEXEL_OK:
             raise DexelError(st, dexel_last_error(self.engine.ctx))
 
     def autotune(self, reps: int = 2, stream=None):
-        ws = self.engine.workspace(self.ws_bytes)
-        return dexel_autotune(self.engine.ctx, self.items, ws, stream, reps)
+        return dexel_autotune(self.engine.ctx, self.items, self.ws, stream, reps)
 
     def statuses(self):
         return [int(o[3].item()) for o in self.outs]

@@ -43,13 +43,55 @@ def test_candidate_pairs_brute_force(seed):
     assert bench.dex_candidate_pairs(np.asarray(rec), n) == want
 
 
-def test_traffic_only_for_the_profiled_source(monkeypatch):
-    """The committed traffic summary is used only while its source hash is the
-    kernels' own; any other source reads as unmeasured."""
-    real = bench.measured_traffic("k_union")
-    assert real is not None and real > 0
+def test_traffic_only_for_the_profiled_source(monkeypatch, tmp_path):
+    """A traffic summary is used only while its source hash is the kernels'
+    own; any other source reads as unmeasured.  Each counter is scaled by
+    what it read for the copy of known size."""
+    f = tmp_path / "traffic.txt"
+    f.write_text("# summary\n"
+                 f"kernels_source_sha256 {bench.kernels_sha256()}\n"
+                 "copy_bytes 1073741824\ncopy_fetch_kib 524288\ncopy_write_kib 1048576\n"
+                 "kernel k_union 1000 300   # comment\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.measured_traffic("k_union") == (1000 * 2.0 + 300 * 1.0) * 1024
+    assert bench.measured_traffic("k_seeds") is None
     monkeypatch.setattr(bench, "kernels_sha256", lambda: "0" * 64)
     assert bench.measured_traffic("k_union") is None
+
+
+class _Dx:
+    PROFILE_STAGES = ["column_gaps", "row_offset", "row_offset_replay", "neighbour",
+                      "neighbour_replay", "seeds", "seeds_replay", "y_union", "y_union_replay",
+                      "result_scan", "compact"]
+    PROFILE_KERNELS = ["k_col_gaps", "k_row_offset", "k_row_offset_fb", "k_neighbour",
+                       "k_neighbour_fb", "k_seeds", "k_seeds_fb", "k_union", "k_union_fb", "k_scan",
+                       "k_copy_out"]
+
+
+def test_dominant_stage_counts_its_replay():
+    """The dominant stage is the costliest by main plus replay time; frac is
+    its main kernel's, stage_frac charges the replay too."""
+    st = {"row_offset": 100, "neighbour": 100, "seeds": 1000, "result": 100}
+    per = {k: 0.0 for k in _Dx.PROFILE_STAGES}
+    per.update(row_offset=2.0, row_offset_replay=6.0, y_union=5.0, y_union_replay=0.5)
+    roof = bench.stage_roofline(_Dx, per, [(500, st), (500, st)], 64)
+    assert roof["stage"] == "row_offset" and roof["kernel"] == "k_row_offset"
+    assert roof["kernel_ms"] == 1.0 and roof["stage_ms"] == 4.0
+    b = bench.kernel_bytes("row_offset", 64, 500, st)
+    assert roof["bytes_per_launch"] == b
+    assert abs(roof["frac"] - b / 1e-3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-5
+    assert abs(roof["stage_frac"] - roof["frac"] / 4.0) < 1e-5
+
+
+def test_step_bytes():
+    """B_alg and B_min of a pass from the sizes it reports."""
+    st = {"row_offset": 0, "neighbour": 0, "seeds": 7, "result": 3}
+    alg, mn = bench.pass_bytes(10, 5, st)
+    ptr = 8 * 11
+    assert mn == ptr + 8 * 5 + ptr + 8 * 3
+    assert alg == mn + 2 * (ptr + 9 * 7)
+    r = bench.step_roofline([(5, st), (3, st)], 10, 1.0)
+    assert r["step_bytes_min"] == mn + bench.pass_bytes(10, 3, st)[1]
 
 
 def test_more_than_one_gpu_is_refused():

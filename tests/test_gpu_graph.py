@@ -80,3 +80,41 @@ def test_graph_replay_batch(engine):
         for a, b in zip(got, eager):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         other.enqueue(flags=dx.DEXEL_FLAG_SYNC)  # eager work between replays
+
+
+def test_graph_replay_after_engine_workspace_grows(engine):
+    """A captured plan keeps its own workspace: growing (and so reallocating)
+    the engine's shared workspace after the capture leaves replays intact."""
+    import torch
+    import paper_1804_08968_amd as dx
+    shapes = gen.batch_shapes(4, count=3, smin=64, smax=128)
+    dgs = [dx.DeviceGrid.from_host(g) for g, _ in shapes]
+    radii = [r for _, r in shapes]
+    bp = dx.BatchPlan(engine, dgs, radii, ["close", "dilate", "erode"])
+    bp.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+    eager = [_host(g) for g in bp.results()]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        bp.enqueue()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    print("[case] capture", flush=True)
+    with torch.cuda.graph(graph, stream=s):
+        bp.enqueue(stream=s)
+    torch.cuda.synchronize()
+    big = dx.DeviceGrid.from_host(gen.primitives_grid(3, n=256, count=400))
+    for rep in range(3):
+        have = engine.workspace(1).numel()
+        engine.workspace(have + (64 << 20))      # frees the old buffer, allocates a larger one
+        engine.offset(big, 6.0 + rep, "close")   # eager work in the reallocated workspace
+        for o in bp.outs:
+            o[0].fill_(-7)
+            o[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+        print(f"[case] replay {rep} after growing the engine workspace", flush=True)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert bp.statuses() == [0] * len(dgs)
+        for a, b in zip((_host(g) for g in bp.results()), eager):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
