@@ -1,13 +1,14 @@
 """Batched offsets: many shapes of different sizes, radii and operations in
 one enqueue.  Each shape's result inside the batch must equal its result
-alone, bit for bit, and the oracle's float32 model."""
+alone, bit for bit, and the oracle's float32 model, and lie within
+tolerance of its float64 result."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
 from synth import gen
-from tests.helpers import random_grid
+from tests.helpers import compare_columns, random_grid
 
 pytestmark = pytest.mark.gpu
 
@@ -39,13 +40,16 @@ def test_batch_equals_alone_and_oracle(engine, oracle_lib):
         assert np.array_equal(cp_b, cp_a) and np.array_equal(z_b, z_a), (g.nx, g.ny, r, op)
         ref = oracle_lib.run(g, r, op, "f32model")
         assert np.array_equal(cp_b, ref.col_ptr) and np.array_equal(z_b, ref.z), (g.nx, g.ny, r, op)
+        ref64 = oracle_lib.run(g, r, op, "f64")
+        res = compare_columns(np.diff(ref64.col_ptr), ref64.z, np.diff(cp_b), z_b, r,
+                              k=2 if op in ("open", "close") else 1)
+        assert res["failed"] == 0, (g.nx, g.ny, r, op, res)
 
 
 def test_batch_c4_subset(engine, oracle_lib):
     """A few shapes of the batched workload (128^2..1024^2 primitive soups,
     radius U[2, 32]) against the oracle on sampled columns."""
     import paper_1804_08968_amd as dx
-    from tests.helpers import compare_columns
     shapes = gen.batch_shapes(0, count=6, smin=128, smax=384)
     dgs = [dx.DeviceGrid.from_host(g) for g, _ in shapes]
     radii = [r for _, r in shapes]

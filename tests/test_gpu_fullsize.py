@@ -1,10 +1,20 @@
-"""Parity at full benchmark size: the closing (r = 16) of the 2048 x 2048
-gyroid lattice (2.15e8 intervals), run as bench.py runs it (a Plan with the
-autotuned kernel variant), checked on sampled output columns against the
-oracle evaluated on just those columns.
+"""Parity at full benchmark size on the 2048 x 2048 gyroid lattice (2.15e8
+intervals, about 51 per column), against the oracle evaluated on whole
+64 x 64 tiles of output columns.
 
-The samples include the grid corners and the x-border columns, which take
-the heavy-column (z-slab) replays, and columns next to them.
+* The closing at r = 16, run as bench.py runs it (a Plan with the autotuned
+  kernel variant).  Its dilation fills the lattice, so the closing keeps
+  about one interval per column.
+* The same grid dilated at r = 4 and r = 8 and eroded at r = 1 and r = 2.
+  There the output keeps many intervals per column (about 47, 35 and 52;
+  the r = 2 erosion removes most walls), so the seed, neighbour and union
+  paths and the heavy-column (z-slab) replays at the grid's x borders all
+  decide the result.
+
+Eight tiles per case: the four grid corners, the middles of both x borders,
+the centre and one seeded random tile.  Each is compared bit for bit with
+the oracle's float32 model and within tolerance with its float64 result
+(the brute force of Sec. 4, "Baseline Comparison").
 """
 from __future__ import annotations
 
@@ -16,42 +26,91 @@ from tests.helpers import compare_columns
 
 pytestmark = pytest.mark.gpu
 
+N = 2048
+T = 64
+
+
+def tile_origins(n=N, seed=5):
+    rng = np.random.default_rng(seed)
+    m = n // 2 - T // 2
+    rx, ry = (int(v) for v in rng.integers(0, n - T, 2))
+    return [("corner00", 0, 0), ("corner10", n - T, 0), ("corner01", 0, n - T),
+            ("corner11", n - T, n - T), ("xborder0", 0, m), ("xborder1", n - T, m),
+            ("centre", m, m), ("random", rx, ry)]
+
+
+TILES = tile_origins()
+
+
+def tile_cols(x0, y0, n=N):
+    return (np.arange(y0, y0 + T)[:, None] * n + np.arange(x0, x0 + T)[None, :]).ravel().astype(np.int64)
+
 
 @pytest.fixture(scope="module")
 def c3_grid():
     return gen.gyroid_grid(0)
 
 
-def sample_columns(n, seed=3, count=24):
-    pts = [(0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1), (0, 1000), (1, 1000), (2, 1000),
-           (3, 1001), (n - 1, 1000), (n - 2, 777), (n - 3, 778), (1000, 0), (1000, 1),
-           (1000, n - 1), (1000, n - 2), (3, 5)]
-    rng = np.random.default_rng(seed)
-    pts += [tuple(int(v) for v in p) for p in rng.integers(0, n, size=(count, 2))]
-    return np.unique(np.array([y * n + x for x, y in pts], np.int64))
-
-
-@pytest.mark.parametrize("op", ["close"])
-def test_c3_closing_sampled(engine, oracle_lib, c3_grid, op):
+def _gpu(engine, g, r, op, autotune):
     import paper_1804_08968_amd as dx
-    g = c3_grid
-    print(f"[case] c3 {op} r=16 {g.nx}x{g.ny} nseg={g.nseg}", flush=True)
+    print(f"[case] gyroid2048 {op} r={r} (GPU)", flush=True)
     dg = dx.DeviceGrid.from_host(g)
-    plan = dx.Plan(engine, dg, 16.0, op)
-    chosen, _ = plan.autotune(reps=1)
-    plan.enqueue(flags=dx.DEXEL_FLAG_SYNC)
-    assert plan.status() == dx.DEXEL_OK
-    col_ptr, z = plan.result().to_host()
-    cols = sample_columns(g.nx)
-    gcnt = np.diff(col_ptr)[cols]
-    gz = np.concatenate([z[2 * col_ptr[c]: 2 * col_ptr[c + 1]] for c in cols]).astype(np.float64)
-    c32, z32 = oracle_lib.region_chain(g, 16.0, op, cols, "f32model")
-    assert np.array_equal(gcnt, c32), f"variant {chosen}: counts differ from the float32 model"
-    assert np.array_equal(gz, z32), f"variant {chosen}: endpoints differ from the float32 model"
-    c64, z64 = oracle_lib.region_chain(g, 16.0, op, cols, "f64")
-    res = compare_columns(c64, z64, gcnt, gz, 16.0, k=2)
-    assert res["failed"] == 0, res
-    # every column of the output is canonical
+    if autotune:
+        plan = dx.Plan(engine, dg, r, op)
+        plan.autotune(reps=1)
+        plan.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+        assert plan.status() == dx.DEXEL_OK
+        col_ptr, z = plan.result().to_host()
+    else:
+        col_ptr, z = engine.offset(dg, r, op).to_host()
     assert col_ptr[0] == 0 and np.all(np.diff(col_ptr) >= 0)
     zz = z[: 2 * col_ptr[-1]].reshape(-1, 2)
     assert np.all(zz[:, 0] <= zz[:, 1])
+    return col_ptr, z
+
+
+@pytest.fixture(scope="module")
+def results():
+    return {}
+
+
+def _result(results, engine, g, r, op):
+    key = (r, op)
+    if key not in results:
+        results.clear()  # one 2048^2 result on the host at a time
+        results[key] = _gpu(engine, g, r, op, autotune=(op == "close"))
+    return results[key]
+
+
+def _check_tile(oracle, g, r, op, col_ptr, z, x0, y0, name):
+    cols = tile_cols(x0, y0)
+    print(f"[case] gyroid2048 {op} r={r} tile {name} ({x0}, {y0}) (oracle)", flush=True)
+    gcnt = np.diff(col_ptr)[cols]
+    gz = np.concatenate([z[2 * col_ptr[c]: 2 * col_ptr[c + 1]] for c in cols]).astype(np.float64)
+    if op in ("dilate", "erode"):
+        c32, z32 = oracle.offset_columns(g, r, op, "f32model", cols=cols)
+        c64, z64 = oracle.offset_columns(g, r, op, "f64", cols=cols)
+    else:
+        c32, z32 = oracle.region_chain(g, r, op, cols, "f32model")
+        c64, z64 = oracle.region_chain(g, r, op, cols, "f64")
+    assert np.array_equal(gcnt, c32), f"{name}: counts differ from the float32 model"
+    assert np.array_equal(gz, z32), f"{name}: endpoints differ from the float32 model"
+    res = compare_columns(c64, z64, gcnt, gz, r, k=2 if op in ("open", "close") else 1)
+    assert res["failed"] == 0, (name, res)
+    return gcnt
+
+
+@pytest.mark.parametrize("name,x0,y0", TILES)
+def test_c3_closing_tiles(engine, oracle_lib, c3_grid, results, name, x0, y0):
+    col_ptr, z = _result(results, engine, c3_grid, 16.0, "close")
+    _check_tile(oracle_lib, c3_grid, 16.0, "close", col_ptr, z, x0, y0, name)
+
+
+@pytest.mark.parametrize("name,x0,y0", TILES)
+@pytest.mark.parametrize("op,r", [("dilate", 4.0), ("dilate", 8.0), ("erode", 1.0), ("erode", 2.0)])
+def test_gyroid2048_fragmented_tiles(engine, oracle_lib, c3_grid, results, op, r, name, x0, y0):
+    col_ptr, z = _result(results, engine, c3_grid, r, op)
+    gcnt = _check_tile(oracle_lib, c3_grid, r, op, col_ptr, z, x0, y0, name)
+    if (op, r) != ("erode", 2.0):
+        # the output really is fragmented (tens of intervals per column)
+        assert gcnt.mean() > 10.0, (name, gcnt.mean())

@@ -56,7 +56,7 @@ def check(engine, oracle, g, r, op, cols=None, label=""):
     return res
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("seed", range(10))
 def test_c1_spheres(engine, oracle_lib, seed):
     g = gen.config_grid("c1", seed)
     check(engine, oracle_lib, g, 3.0, "dilate", label=f"c1 seed{seed}")
@@ -134,6 +134,24 @@ def test_long_lists_grow_the_arena(engine, oracle_lib):
 def test_c2_full(engine, oracle_lib, r, op):
     g = gen.config_grid("c2", 0)
     check(engine, oracle_lib, g, r, op, label="c2")
+
+
+@pytest.mark.parametrize("r", [2.0, 8.0])
+@pytest.mark.parametrize("op", ["dilate", "erode"])
+def test_c2lit_full(engine, oracle_lib, r, op):
+    """The literal 200-primitive version of the 512^2 soup (about 0.8
+    intervals per column), full grid."""
+    g = gen.config_grid("c2lit", 0)
+    check(engine, oracle_lib, g, r, op, label="c2lit")
+
+
+@pytest.mark.parametrize("op", ["dilate", "erode"])
+def test_c2lit_r32_sampled(engine, oracle_lib, op):
+    g = gen.config_grid("c2lit", 1)
+    rng = np.random.default_rng(10)
+    cols = np.unique(np.concatenate([rng.integers(0, g.nx * g.ny, 1500),
+                                     np.arange(0, 64), np.arange(g.nx * g.ny - 64, g.nx * g.ny)]))
+    check(engine, oracle_lib, g, 32.0, op, cols=cols, label="c2lit r32")
 
 
 @pytest.mark.parametrize("op", ["dilate", "erode"])

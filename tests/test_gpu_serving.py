@@ -1,14 +1,15 @@
 """Serving: the same requests give the same results alone (plain server, one
 request at a time) and in the mix (continuous batching, several batches in
 flight, chained requests on device-resident session state), bit for bit,
-and equal to the oracle's float32 model replayed session by session."""
+equal to the oracle's float32 model replayed session by session, and within
+tolerance of the float64 oracle applied to each request's own input."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
 from synth import gen
-from tests.helpers import random_grid
+from tests.helpers import compare_columns, random_grid
 
 pytestmark = pytest.mark.gpu
 
@@ -68,6 +69,11 @@ def test_alone_equals_mix(engine, oracle_lib):
         last[q.session] = ref
         cp, z = _host(d.result)
         assert np.array_equal(cp, ref.col_ptr) and np.array_equal(z, ref.z), q
+        # and within tolerance of the float64 oracle on the same input
+        ref64 = oracle_lib.run(src, q.r, q.op, "f64")
+        res = compare_columns(np.diff(ref64.col_ptr), ref64.z, np.diff(cp), z, q.r,
+                              k=2 if q.op in ("open", "close") else 1)
+        assert res["failed"] == 0, (q, res)
 
 
 def test_admission_rejects_oversized(engine):
