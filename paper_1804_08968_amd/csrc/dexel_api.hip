@@ -31,6 +31,8 @@ struct dexel_ctx {
     // Kernel variant: forced (>= 0) or chosen per batch signature by dexel_autotune.
     int forced_variant = -1;
     std::map<uint64_t, int> tuned;
+    // LDS bytes one workgroup may take (bounds the thin-column erosion's tiles)
+    int max_lds = 65536;
 };
 
 namespace {
@@ -61,7 +63,7 @@ void radius_params(float r, int* R, int* d2max) {
 // Workspace layout of one call (a batch of items; a single op is a batch of one).
 struct Layout {
     size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
-    size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC;
+    size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC, gen, need;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table (shared per radius)
@@ -129,6 +131,8 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.offC = take(8 * g);
     L.cntC = take(4 * g);
     L.scanC = take(8 * (g + 1));
+    L.gen = take(g);
+    L.need = take(g);
     L.A = take(8 * cp);
     L.I = take(8 * cp);
     L.B = take(8 * g * dexel::SEED_SLOT);
@@ -323,6 +327,14 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.offC = (int64_t*)(w + L.offC) + gbase;
             S.cntC = (int32_t*)(w + L.cntC) + gbase;
             S.scanC = (int64_t*)(w + L.scanC) + gbase;
+            S.gen = (uint8_t*)(w + L.gen) + gbase;
+            S.need = (uint8_t*)(w + L.need) + gbase;
+        };
+        // erosion passes of radii whose tiles fit the LDS run the thin-column
+        // filter first
+        auto thin_ok = [&](int erode) {
+            return erode && !(flags & DEXEL_FLAG_NO_THIN) && ii.R <= dexel::THIN_RMAX &&
+                   dexel::thin_lds_bytes(ii.R, ii.d2max) <= ctx->max_lds;
         };
         dexel::Shape a;
         fill(a, g1);
@@ -330,6 +342,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         a.z = (const float2*)it.in.z;
         a.nseg = it.in.nseg;
         a.erode = ops[0];
+        a.thin = thin_ok(a.erode) ? 1 : 0;
         if (ii.chain) {
             int64_t* mptr = (int64_t*)(w + L.mid_ptr) + mid;
             a.out_col_ptr = mptr;
@@ -344,6 +357,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             b.zoff = (const int64_t*)(w + L.zbase) + i;
             b.nseg = -1;
             b.erode = ops[1];
+            b.thin = thin_ok(b.erode) ? 1 : 0;
             b.out_col_ptr = it.out.col_ptr;
             b.out_z = (float2*)it.out.z;
             b.out_cap = it.out.cap_seg;
@@ -368,6 +382,25 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     }
     base1.push_back(g1);
     base2.push_back(g2);
+    // tiles of the thin shapes of each pass, numbered in shape order
+    auto tile_bases = [](std::vector<dexel::Shape>& sh, int64_t* ntiles, int32_t* lds) {
+        int64_t t = 0;
+        int32_t b = 0;
+        for (auto& S : sh) {
+            S.tbase = t;
+            if (!S.thin) continue;
+            t += (int64_t)((S.nx + dexel::THIN_TX - 1) / dexel::THIN_TX) *
+                 ((S.ny + dexel::THIN_TY - 1) / dexel::THIN_TY);
+            const int32_t need = dexel::thin_lds_bytes(S.R, S.d2max);
+            b = need > b ? need : b;
+        }
+        *ntiles = t;
+        *lds = b;
+    };
+    int64_t nt1 = 0, nt2 = 0;
+    int32_t lds1 = 0, lds2 = 0;
+    tile_bases(sh1, &nt1, &lds1);
+    tile_bases(sh2, &nt2, &lds2);
 
     auto make_pass = [&](size_t shapes_off, size_t sbase_off, int nsh, int64_t gcols) {
         dexel::Pass q{};
@@ -391,8 +424,12 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         q.bsum = (int64_t*)(w + L.bsum);
         return q;
     };
-    const dexel::Pass p1 = make_pass(L.shapes1, L.sbase1, (int)sh1.size(), g1);
-    const dexel::Pass p2 = make_pass(L.shapes2, L.sbase2, (int)sh2.size(), g2);
+    dexel::Pass p1 = make_pass(L.shapes1, L.sbase1, (int)sh1.size(), g1);
+    dexel::Pass p2 = make_pass(L.shapes2, L.sbase2, (int)sh2.size(), g2);
+    p1.ntiles = nt1;
+    p1.thin_lds = lds1;
+    p2.ntiles = nt2;
+    p2.thin_lds = lds2;
     int64_t* zbase = (int64_t*)(w + L.zbase);
 
     HIP_TRY(dexel::launch_init_call(p1.hdr, p1.shape_status, n, s));
@@ -469,6 +506,9 @@ dexel_status dexel_ctx_create(int device, dexel_ctx** ctx) {
     if (hipSetDevice(device) != hipSuccess) return DEXEL_ERR_HIP;
     dexel_ctx* c = new dexel_ctx();
     c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = lds < 65536 ? lds : 65536;
     *ctx = c;
     return DEXEL_OK;
 }

@@ -70,6 +70,15 @@ struct Shape {
     float2* out_z;
     const int64_t* out_zoff;  // if set, results are written at out_z + *out_zoff
     int64_t out_cap;
+    // thin-column erosion (k_thin_erode): `thin` set for an erosion pass the
+    // tiled max / min filter evaluates first; its tiles are tbase .. of the
+    // pass.  gen[c] = 1 marks an output column left to the general kernels,
+    // need[c] the general stages column c must run for them (NEED_* bits).
+    int32_t thin;
+    int32_t pad1;
+    int64_t tbase;
+    uint8_t* gen;
+    uint8_t* need;
     int32_t out_is_intermediate;
     int32_t last_pass;        // write the caller's nseg_out / status after this pass
     int64_t* out_nseg;
@@ -83,6 +92,9 @@ struct Pass {
     int32_t nshapes;
     int32_t pad;
     int64_t gcols;            // padded global column count of the pass
+    int64_t ntiles;           // tiles of the thin-column erosion over the pass's thin shapes
+    int32_t thin_lds;         // dynamic LDS bytes of k_thin_erode (largest R of the thin shapes)
+    int32_t pad2;
     WsHeader* hdr;
     int32_t* shape_status;    // [items] per-item status (output capacity)
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
@@ -119,10 +131,23 @@ hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t 
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s);
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
-// Profiled intervals of one pass, one per launch group: column gaps, row
-// offset, its replay, neighbour intersection, its replay, seeds, their
-// replay, y dilation + union, its replay, result scan, compaction.
-constexpr int NPROF = 11;
+// Profiled intervals of one pass, one per launch group: column gaps,
+// thin-column erosion, row offset, its replay, neighbour intersection, its
+// replay, seeds, their replay, y dilation + union, its replay, result scan,
+// compaction.
+constexpr int NPROF = 12;
+// Thin-column erosion: tile of THIN_TX x THIN_TY output columns, radii up to
+// THIN_RMAX; LDS bytes a tile stages at integer radius R.
+constexpr int THIN_TX = 64;
+constexpr int THIN_TY = 16;
+constexpr int THIN_RMAX = 32;
+inline int thin_lds_bytes(int R, int d2max) {
+    return (THIN_TX + 2 * R) * (THIN_TY + 2 * R) * 8 + 4 * (d2max + 1) + 4 * (R + 1);
+}
+// need[] bits: stages of the general kernels a column of a thin shape runs.
+constexpr int NEED_UNION = 1;   // y union (the column is general itself)
+constexpr int NEED_SEEDS = 2;   // neighbour intersection and seeds (a general column within R rows)
+constexpr int NEED_ROW = 4;     // row offset (a general column within 2R rows)
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
 // variant: kernel variant (per-lane LDS list capacities), 0..NVARIANT-1.
 constexpr int NVARIANT = 4;

@@ -1427,6 +1427,12 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
     return pl;
 }
 
+// Must column c of shape S run the general stage `bit`?  Only the columns of
+// thin shapes skip stages.
+__device__ __forceinline__ bool needs(const Shape& S, int64_t c, int bit) {
+    return !S.thin || (gld(&S.need[c]) & bit);
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
@@ -1508,8 +1514,9 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
+    bool valid = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_ROW);
+    if (!__any(valid)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
-    bool valid = pl.valid;
     LdsList U{&lds[threadIdx.x], CAP};
     int n = valid ? k1_column(P, pl.c, U) : 0;
     if (n < 0) {
@@ -1553,11 +1560,13 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     __shared__ float2 lds[2 * CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
+    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_SEEDS);
+    if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     // a column whose own V0 is fragmented (its neighbours' are too, as a
     // rule) goes straight to the replay
-    const bool defer = pl.valid && gld(&P.cntA[pl.c]) > K3_DEFER_N;
-    bool valid = pl.valid && !defer;
+    const bool defer = live && gld(&P.cntA[pl.c]) > K3_DEFER_N;
+    bool valid = live && !defer;
     LdsList L0{&lds[threadIdx.x], CAP};
     LdsList L1{&lds[CAP * WG + threadIdx.x], CAP};
     int res = 0;
@@ -1685,9 +1694,11 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
+    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_SEEDS);
+    if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     int np = 0;
-    if (pl.valid) {
+    if (live) {
         const int64_t g = pl.g0 + threadIdx.x;
         if (gld(&P.cntI[pl.c]) > K2_DEFER_NI) {
             P.cntB[pl.c] = 0;
@@ -1843,11 +1854,14 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     __shared__ float tab[256];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
-    const OpParams P = make_op(Q, Q.shapes[pl.s]);
     if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
+    // columns of thin shapes that k_thin_erode finished are skipped
+    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_UNION);
+    if (!__any(live)) return;
+    const OpParams P = make_op(Q, Q.shapes[pl.s]);
     // a column whose V0 is fragmented goes straight to the replay
-    const bool defer = pl.valid && gld(&P.cntA[pl.c]) > K3_DEFER_N;
-    bool valid = pl.valid && !defer;
+    const bool defer = live && gld(&P.cntA[pl.c]) > K3_DEFER_N;
+    bool valid = live && !defer;
     LdsList U{&lds[threadIdx.x], CAP};
     int n = k3_column<true>(P, pl.c, valid, U, tab);
     if (defer) push_overflow(Q, ST_K3H, pl.g0 + threadIdx.x);
@@ -2055,6 +2069,151 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(SCAN_T), 0, s, cnt, n,
                        bsum, nb, off, hdr);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// erosion of thin columns
+// ---------------------------------------------------------------------------
+//
+// An erosion complements every in-grid stencil column on read.  When each of
+// them holds at most one interval [a, b], its complement is the two rays
+// (-inf, a] and [b, +inf) (the whole line if the column is empty), and a
+// ray's chord only moves the ray's end.  The union of all chords is then
+// (-inf, MA] U [MB, +inf) with MA = max fl(a + H[d2]) and MB =
+// min fl(b - H[d2]) over the ball's stencil, and the eroded column is
+// [MA, MB] if MA < MB, else empty: a max / min filter over the stencil, with
+// the same chords and roundings as the general kernels.
+//
+// k_thin_erode evaluates it on tiles of THIN_TX x THIN_TY output columns of
+// the pass's thin shapes: the tile's (THIN_TX + 2R) x (THIN_TY + 2R)
+// neighbourhood is staged in LDS once as one (a, b) pair per column (empty:
+// (+inf, -inf), so that MA = +inf; outside the grid: (-inf, +inf), which
+// changes nothing; a column of two or more intervals: NaN), then each wave
+// evaluates THIN_TY / 4 output rows, one lane per column.  An output column
+// whose stencil holds a longer column is marked general (gen = 1) and left
+// to the general kernels; k_thin_spread marks the columns those must
+// evaluate for it (need[]).
+constexpr int THIN_T = 256;
+
+__global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
+    extern __shared__ float2 thin_lds[];
+    if (Q.hdr->abort) return;
+    const int64_t t = map_block(Q.ntiles);
+    int lo = 0, hi = Q.nshapes;  // the last shape whose tiles start at or before t
+    while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (Q.shapes[m].tbase <= t) lo = m; else hi = m;
+    }
+    const Shape& S = Q.shapes[lo];
+    const OpParams P = make_op(Q, S);
+    const int R = P.R;
+    const int ntx = (P.nx + THIN_TX - 1) / THIN_TX;
+    const int64_t tl = t - S.tbase;
+    const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * THIN_TY;
+    const int SW = THIN_TX + 2 * R, SH = THIN_TY + 2 * R;
+    float2* st = thin_lds;
+    float* Hs = (float*)(st + SW * SH);
+    int* wd = (int*)(Hs + P.d2max + 1);
+    for (int i = threadIdx.x; i <= P.d2max; i += THIN_T) Hs[i] = gld(&P.H[i]);
+    // wd[k]: largest |dx| of the stencil row at |dy| = k
+    for (int k = threadIdx.x; k <= R; k += THIN_T) {
+        int w = 0;
+        while ((w + 1) * (w + 1) + k * k <= P.d2max) ++w;
+        wd[k] = w;
+    }
+    int thick = 0;
+    for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
+        const int sy = i / SW, sx = i - sy * SW;
+        const int xx = x0 - R + sx, yy = y0 - R + sy;
+        float2 v = make_float2(-DX_INF, DX_INF);
+        if (xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
+            const int64_t c = (int64_t)yy * P.nx + xx;
+            const int64_t b = gld(&P.col_ptr[c]);
+            const int m = (int)(gld(&P.col_ptr[c + 1]) - b);
+            if (m == 0) {
+                v = make_float2(DX_INF, -DX_INF);
+            } else if (m == 1) {
+                v = gld(&P.z[b]);
+            } else {
+                v = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+                thick = 1;
+            }
+        }
+        st[i] = v;
+    }
+    const int any_thick = __syncthreads_or(thick);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    for (int k = 0; k < THIN_TY / 4; ++k) {
+        const int ly = wv + 4 * k;
+        const int y = y0 + ly;
+        if (y >= P.ny) break;  // wave-uniform
+        const bool live = x < P.nx;
+        const float2* ctr = st + (ly + R) * SW + lane + R;
+        float MA = -DX_INF, MB = DX_INF;
+        bool thk = false;
+        for (int dy = -R; dy <= R; ++dy) {
+            const int w = wd[dy < 0 ? -dy : dy];
+            const float2* row = ctr + dy * SW;
+            const float* hr = Hs + dy * dy;
+            if (any_thick) {
+                for (int dx = -w; dx <= w; ++dx) {
+                    const float2 v = row[dx];
+                    const float hh = hr[dx * dx];
+                    thk |= v.x != v.x;
+                    MA = fmaxf(MA, v.x + hh);
+                    MB = fminf(MB, v.y - hh);
+                }
+            } else {
+                for (int dx = -w; dx <= w; ++dx) {
+                    const float2 v = row[dx];
+                    const float hh = hr[dx * dx];
+                    MA = fmaxf(MA, v.x + hh);
+                    MB = fminf(MB, v.y - hh);
+                }
+            }
+        }
+        const bool done = live && !thk;
+        const int outn = (done && MA < MB) ? 1 : 0;
+        int tot;
+        const int pre = wave_excl_scan(outn, &tot);
+        unsigned long long base = 0;
+        if (lane == 0 && tot > 0) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        const unsigned long long end = base + (unsigned long long)tot;
+        const bool ok = end <= (unsigned long long)P.cap;
+        if (!ok && lane == 0) {
+            note_need(P.hdr, end);
+            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        }
+        if (!live) continue;
+        const int64_t c = (int64_t)y * P.nx + x;
+        gst(&S.gen[c], (uint8_t)(thk ? 1 : 0));
+        if (!done) continue;
+        gst(&P.offC[c], (int64_t)(base + pre));
+        gst(&P.cntC[c], ok ? outn : 0);
+        if (ok && outn) gst(&P.C[base + pre], make_float2(MA, MB));
+    }
+}
+
+// need[c] of every column of a thin shape: NEED_UNION if the column is
+// general itself, NEED_SEEDS if a general column lies within R rows of it
+// (its seeds and intersection feed that column's y union), NEED_ROW if one
+// lies within 2R rows (its row offset feeds those intersections).
+__global__ void __launch_bounds__(WG) k_thin_spread(Pass Q) {
+    if (Q.hdr->abort) return;
+    const Place pl = place_block(Q);
+    const Shape& S = Q.shapes[pl.s];
+    if (!S.thin || !pl.valid) return;
+    const int y = (int)(pl.c / S.nx), x = (int)(pl.c - (int64_t)y * S.nx);
+    int bits = gld(&S.gen[pl.c]) ? NEED_UNION | NEED_SEEDS | NEED_ROW : 0;
+    for (int d = 1; d <= 2 * S.R && !(bits & NEED_SEEDS) && !(bits && d > S.R); ++d) {
+        const bool lo_in = y - d >= 0, hi_in = y + d < S.ny;
+        const bool g = (lo_in && gld(&S.gen[pl.c - (int64_t)d * S.nx])) ||
+                       (hi_in && gld(&S.gen[pl.c + (int64_t)d * S.nx]));
+        if (g) bits |= d <= S.R ? NEED_SEEDS | NEED_ROW : NEED_ROW;
+    }
+    gst(&S.need[pl.c], (uint8_t)bits);
 }
 
 // ---------------------------------------------------------------------------
@@ -2819,30 +2978,35 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(0);
     hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
-    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
+    if (p.ntiles > 0) {
+        hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.thin_lds, s, p);
+        hipLaunchKernelGGL(k_thin_spread, g, b, 0, s, p);
+    }
     DX_MARK(2);
-    hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
     DX_MARK(3);
-    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
     DX_MARK(4);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    DX_MARK(5);
     hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
-    DX_MARK(5);
-    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(6);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
+    DX_MARK(7);
     hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
     hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
-    DX_MARK(7);
-    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(8);
+    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
+    DX_MARK(9);
     hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
-    DX_MARK(9);
+    DX_MARK(10);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
-    DX_MARK(10);
-    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
     DX_MARK(11);
+    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
+    DX_MARK(12);
 #undef DX_MARK
     return hipGetLastError();
 }

@@ -106,6 +106,18 @@ def test_c3_closing_tiles(engine, oracle_lib, c3_grid, results, name, x0, y0):
     _check_tile(oracle_lib, c3_grid, 16.0, "close", col_ptr, z, x0, y0, name)
 
 
+def test_c3_closing_thin_equals_general(engine, c3_grid, results):
+    """The whole 2048^2 closing: the erosion pass's thin-column filter (the
+    bench's path) gives the same grid, bit for bit, as the general kernels."""
+    import paper_1804_08968_amd as dx
+    col_ptr, z = _result(results, engine, c3_grid, 16.0, "close")
+    print("[case] gyroid2048 close r=16 general kernels (GPU)", flush=True)
+    dg = dx.DeviceGrid.from_host(c3_grid)
+    gcp, gz = engine.offset(dg, 16.0, "close", flags=dx.DEXEL_FLAG_NO_THIN).to_host()
+    assert np.array_equal(col_ptr, gcp)
+    assert np.array_equal(z[: 2 * col_ptr[-1]], gz[: 2 * gcp[-1]])
+
+
 @pytest.mark.parametrize("name,x0,y0", TILES)
 @pytest.mark.parametrize("op,r", [("dilate", 4.0), ("dilate", 8.0), ("erode", 1.0), ("erode", 2.0)])
 def test_gyroid2048_fragmented_tiles(engine, oracle_lib, c3_grid, results, op, r, name, x0, y0):
