@@ -39,7 +39,9 @@
  *
  * Ownership: the library never allocates device memory.  Inputs, outputs and
  * a workspace (size from dexel_workspace_size) are supplied by the caller.
- * A context owns host-side state only (radius lookup tables, error text).
+ * A context owns host-side state only (autotune choices, error text); the
+ * radius table of a call is computed on the host and passed to the device
+ * through kernel arguments, so no host buffer outlives a call either.
  * One host thread per context at a time.
  *
  * Asynchrony and errors: host-detectable argument errors are returned before

@@ -17,10 +17,6 @@ using dexel::WsHeader;
 struct dexel_ctx {
     int device = 0;
     std::string err;
-    // Radius lookup tables, one pinned host buffer per distinct radius.  A
-    // table is immutable once built, so an asynchronous upload from it can
-    // never observe a later call's table.
-    std::map<uint32_t, float*> luts;
     // Optional per-stage timing: HIP events recorded on the call's stream at
     // the stage boundaries of every pass, read back by dexel_profile_read.
     bool profile = false;
@@ -187,17 +183,13 @@ dexel_status check_out(dexel_ctx* ctx, const dexel_grid_view* in, const dexel_gr
     return DEXEL_OK;
 }
 
-// Pinned host table H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..floor(r^2).
-float* lut_for(dexel_ctx* ctx, float r, int d2max) {
-    const uint32_t key = float_bits(r);
-    auto it = ctx->luts.find(key);
-    if (it != ctx->luts.end()) return it->second;
-    float* h = nullptr;
-    if (hipHostMalloc((void**)&h, sizeof(float) * (size_t)(d2max + 1), hipHostMallocDefault) != hipSuccess)
-        return nullptr;
+// Half-width table H[d2] = float(sqrt(double(r)^2 - d2)), d2 = 0..floor(r^2),
+// computed on the host per call and uploaded through kernel arguments (no
+// host buffer outlives the call, nothing is allocated).
+std::vector<float> half_widths(float r, int d2max) {
+    std::vector<float> h((size_t)d2max + 1);
     const double r2 = (double)r * (double)r;
     for (int d2 = 0; d2 <= d2max; ++d2) h[d2] = (float)std::sqrt(r2 - (double)d2);
-    ctx->luts[key] = h;
     return h;
 }
 
@@ -300,8 +292,6 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     for (int32_t i = 0; i < n; ++i) {
         const dexel_batch_item& it = items[i];
         const ItemInfo& ii = info[i];
-        float* lut = lut_for(ctx, it.r, ii.d2max);
-        if (!lut) return fail(ctx, DEXEL_ERR_HIP, "cannot allocate pinned lookup table");
         const int ops[2] = {it.op == DEXEL_ERODE || it.op == DEXEL_OPEN ? 1 : 0,
                             it.op == DEXEL_CLOSE ? 1 : 0};
         auto fill = [&](dexel::Shape& S, int64_t gbase) {
@@ -436,9 +426,8 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     std::set<size_t> filled;  // shared radius tables already copied
     for (int32_t i = 0; i < n; ++i) {
         if (!filled.insert(L.lut_off[i]).second) continue;
-        float* lut = lut_for(ctx, items[i].r, info[i].d2max);
-        HIP_TRY(hipMemcpyAsync(w + L.lut_off[i], lut, sizeof(float) * (size_t)(info[i].d2max + 1),
-                               hipMemcpyHostToDevice, s));
+        const std::vector<float> h = half_widths(items[i].r, info[i].d2max);
+        HIP_TRY(dexel::launch_put_f32((float*)(w + L.lut_off[i]), h.data(), (int)h.size(), s));
     }
     HIP_TRY(dexel::launch_put_shapes((dexel::Shape*)(w + L.shapes1), sh1.data(), (int)sh1.size(), s));
     HIP_TRY(dexel::launch_put_i64((int64_t*)(w + L.sbase1), base1.data(), (int)base1.size(), s));
@@ -518,7 +507,6 @@ void dexel_ctx_destroy(dexel_ctx* ctx) {
     for (auto& g : ctx->pending)
         for (hipEvent_t e : g) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
-    for (auto& kv : ctx->luts) (void)hipHostFree(kv.second);
     delete ctx;
 }
 

@@ -128,6 +128,13 @@ struct I64Chunk {
 // Launchers (dexel_kernels.hip).  All enqueue on `s`, none synchronises.
 hipError_t launch_put_shapes(Shape* dst, const Shape* host, int n, hipStream_t s);
 hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t s);
+constexpr int F32_CHUNK = 256;
+struct F32Chunk {
+    float v[F32_CHUNK];
+    int32_t n;
+    int32_t first;
+};
+hipError_t launch_put_f32(float* dst, const float* host, int n, hipStream_t s);
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s);
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);

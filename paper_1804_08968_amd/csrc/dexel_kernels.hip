@@ -2275,6 +2275,10 @@ __global__ void k_put_shapes(Shape* dst, ShapeChunk ch) {
     if (i < ch.n) dst[ch.first + i] = ch.s[i];
 }
 
+__global__ void k_put_f32(float* dst, F32Chunk ch) {
+    for (int i = threadIdx.x; i < ch.n; i += blockDim.x) dst[ch.first + i] = ch.v[i];
+}
+
 __global__ void k_put_i64(int64_t* dst, I64Chunk ch) {
     for (int i = threadIdx.x; i < ch.n; i += blockDim.x) dst[ch.first + i] = ch.v[i];
 }
@@ -2349,6 +2353,17 @@ hipError_t launch_put_i64(int64_t* dst, const int64_t* host, int n, hipStream_t 
         ch.first = first;
         for (int i = 0; i < ch.n; ++i) ch.v[i] = host[first + i];
         hipLaunchKernelGGL(k_put_i64, dim3(1), dim3(256), 0, s, dst, ch);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_put_f32(float* dst, const float* host, int n, hipStream_t s) {
+    for (int first = 0; first < n; first += F32_CHUNK) {
+        F32Chunk ch;
+        ch.n = n - first < F32_CHUNK ? n - first : F32_CHUNK;
+        ch.first = first;
+        for (int i = 0; i < ch.n; ++i) ch.v[i] = host[first + i];
+        hipLaunchKernelGGL(k_put_f32, dim3(1), dim3(256), 0, s, dst, ch);
     }
     return hipGetLastError();
 }
