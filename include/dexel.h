@@ -129,6 +129,26 @@ dexel_status dexel_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, flo
  * call needed from the workspace header (a small device-to-host copy). */
 dexel_status dexel_workspace_need(dexel_ctx* ctx, const void* ws, int64_t* cap_hint);
 
+/* Allocation-free dexel_offset, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and result as dexel_offset, without a
+ * workspace argument: the workspace is a static device array of
+ * DEXEL_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends (its address is looked up once per device by
+ * dexel_ctx_create).  The call allocates nothing (no hipMalloc, no pinned
+ * host memory, no profiling events) and records no memset, so it can be
+ * captured in a graph.  Every call on one GPU uses that GPU's one array:
+ * calls that overlap on a GPU (several streams, contexts or threads at
+ * once) race and must be serialised by the caller.  A call whose workspace
+ * (dexel_workspace_size with cap_hint 0) exceeds the array returns
+ * DEXEL_ERR_UNSUPPORTED before anything is enqueued; grids up to about
+ * 512 x 512 at a few intervals per column fit.  DEXEL_ERR_WORKSPACE in
+ * *out->status means the input needed more internal capacity than the
+ * array holds (no retry is possible: use dexel_offset). */
+#define DEXEL_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+dexel_status dexel_offset_noalloc(dexel_ctx* ctx, const dexel_grid_view* in, float r, int32_t op,
+                                  dexel_grid_out* out, void* stream, uint32_t flags);
+
 /* Dilation by the closed ball of radius r (Sec. 3.1 "Dilation"; computed as
  * in Sec. 3.3).  `in` and `out` must not alias; ws/ws_bytes from
  * dexel_workspace_size with op = DEXEL_DILATE. */

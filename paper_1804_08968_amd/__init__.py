@@ -21,7 +21,8 @@ from .binding import (  # noqa: F401
     dexel_set_variant, CSG_OPS, DEXEL_CSG_DIFFERENCE, DEXEL_CSG_INTERSECT, DEXEL_CSG_UNION,
     dexel_csg, dexel_csg_workspace_size, DEXEL_PRIM_BALL, DEXEL_PRIM_BOX, dexel_dexelize,
     dexel_dexelize_workspace_size, DEXEL_FLAG_RAYS_X, DEXEL_FLAG_RAYS_Y, RAY_FLAGS,
-    dexel_canonicalize, dexel_canonicalize_workspace_size,
+    dexel_canonicalize, dexel_canonicalize_workspace_size, dexel_offset_noalloc,
+    DEXEL_NOALLOC_SCRATCH_BYTES,
 )
 
 

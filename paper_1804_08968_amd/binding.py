@@ -35,6 +35,7 @@ DEXEL_FLAG_VALIDATE = 2
 DEXEL_FLAG_RAYS_X = 4
 DEXEL_FLAG_RAYS_Y = 8
 DEXEL_FLAG_NO_THIN = 16
+DEXEL_NOALLOC_SCRATCH_BYTES = 256 << 20
 RAY_FLAGS = {"x": DEXEL_FLAG_RAYS_X, "y": DEXEL_FLAG_RAYS_Y, "z": 0}
 DEXEL_CSG_UNION, DEXEL_CSG_INTERSECT, DEXEL_CSG_DIFFERENCE = 0, 1, 2
 CSG_OPS = {"union": DEXEL_CSG_UNION, "intersect": DEXEL_CSG_INTERSECT,
@@ -66,6 +67,9 @@ lib.dexel_ctx_destroy.restype = None
 lib.dexel_workspace_size.argtypes = [c_void_p, _P(dexel_grid_view), c_float, c_int32, c_int64,
                                      _P(c_size_t)]
 lib.dexel_workspace_size.restype = c_int
+lib.dexel_offset_noalloc.argtypes = [c_void_p, _P(dexel_grid_view), c_float, c_int32, _P(dexel_grid_out),
+                                     c_void_p, c_uint32]
+lib.dexel_offset_noalloc.restype = c_int
 lib.dexel_workspace_need.argtypes = [c_void_p, c_void_p, _P(c_int64)]
 lib.dexel_workspace_need.restype = c_int
 for _name in ("dexel_dilate", "dexel_erode"):
@@ -113,7 +117,7 @@ lib.dexel_last_error.argtypes = [c_void_p]
 lib.dexel_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
-            "dexel_workspace_need", "dexel_dilate", "dexel_erode", "dexel_offset",
+            "dexel_workspace_need", "dexel_dilate", "dexel_erode", "dexel_offset", "dexel_offset_noalloc",
             "dexel_batch_workspace_size", "dexel_batch_offset", "dexel_profile_enable",
             "dexel_profile_read", "dexel_workspace_stats", "dexel_set_variant",
             "dexel_autotune", "dexel_status_string", "dexel_last_error",
@@ -192,6 +196,12 @@ def dexel_workspace_need(ctx, ws: torch.Tensor) -> int:
     if st != DEXEL_OK:
         raise DexelError(st, dexel_last_error(ctx))
     return int(v.value)
+
+
+def dexel_offset_noalloc(ctx, view, r, op, out, stream=None, flags: int = 0) -> int:
+    """dexel_offset on the library's static device scratch (allocates nothing)."""
+    return lib.dexel_offset_noalloc(ctx, ctypes.byref(view), float(r), int(op), ctypes.byref(out),
+                                    _stream_ptr(stream), int(flags))
 
 
 def dexel_offset(ctx, view, r, op, out, ws: torch.Tensor, stream=None, flags: int = 0) -> int:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -29,6 +30,8 @@ struct dexel_ctx {
     std::map<uint64_t, int> tuned;
     // LDS bytes one workgroup may take (bounds the thin-column erosion's tiles)
     int max_lds = 65536;
+    // device address of this device's static scratch (dexel_offset_noalloc)
+    void* scratch = nullptr;
 };
 
 namespace {
@@ -487,14 +490,38 @@ dexel_status sync_status(dexel_ctx* ctx, hipStream_t s, int32_t n, const dexel_b
 
 extern "C" {
 
+// Workspace of dexel_offset_noalloc: one copy on every GPU the library runs
+// on, held until the process ends.  On the host `noalloc_scratch` is only a
+// stand-in for the symbol: host code uses the device address that
+// hipGetSymbolAddress returns for the current device (one lookup per device,
+// kept in noalloc_ptr), never the array's own name.
+static __device__ __align__(256) unsigned char noalloc_scratch[DEXEL_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex noalloc_mu;
+static std::map<int, void*> noalloc_ptr;
+
+// Address of `device`'s scratch; `device` must be current.
+static void* noalloc_scratch_of(int device) {
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    auto it = noalloc_ptr.find(device);
+    if (it != noalloc_ptr.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return nullptr;
+    noalloc_ptr[device] = p;
+    return p;
+}
+
 dexel_status dexel_ctx_create(int device, dexel_ctx** ctx) {
     if (!ctx) return DEXEL_ERR_INVALID;
     *ctx = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DEXEL_ERR_HIP;
     if (hipSetDevice(device) != hipSuccess) return DEXEL_ERR_HIP;
+    void* scratch = noalloc_scratch_of(device);
+    if (!scratch) return DEXEL_ERR_HIP;
     dexel_ctx* c = new dexel_ctx();
     c->device = device;
+    c->scratch = scratch;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = lds < 65536 ? lds : 65536;
@@ -541,6 +568,40 @@ dexel_status dexel_offset(dexel_ctx* ctx, const dexel_grid_view* in, float r, in
     it.op = op;
     it.out = *out;
     return dexel_batch_offset(ctx, 1, &it, ws, ws_bytes, stream, flags);
+}
+
+dexel_status dexel_offset_noalloc(dexel_ctx* ctx, const dexel_grid_view* in, float r, int32_t op,
+                                  dexel_grid_out* out, void* stream, uint32_t flags) {
+    if (!ctx) return DEXEL_ERR_INVALID;
+    ctx->err.clear();
+    if (!in || !out) return fail(ctx, DEXEL_ERR_INVALID, "null input or output");
+    if (!ctx->scratch) return fail(ctx, DEXEL_ERR_HIP, "no static scratch on this device");
+    dexel_batch_item it{};
+    it.in = *in;
+    it.r = r;
+    it.op = op;
+    it.out = *out;
+    std::vector<ItemInfo> info;
+    dexel_status st = check_items(ctx, 1, &it, &info, true);
+    if (st != DEXEL_OK) return st;
+    const size_t need = make_layout(info, default_cap(in)).total;
+    if (need > DEXEL_NOALLOC_SCRATCH_BYTES) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf),
+                      "the call needs %zu bytes of workspace; the static scratch holds %zu (use dexel_offset)",
+                      need, (size_t)DEXEL_NOALLOC_SCRATCH_BYTES);
+        return fail(ctx, DEXEL_ERR_UNSUPPORTED, buf);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // no profiling events: creating them would allocate
+    const bool prof = ctx->profile;
+    ctx->profile = false;
+    st = enqueue_batch(ctx, 1, &it, info, ctx->scratch, DEXEL_NOALLOC_SCRATCH_BYTES, s, flags,
+                       pick_variant(ctx, 1, &it));
+    ctx->profile = prof;
+    if (st != DEXEL_OK) return st;
+    if (flags & DEXEL_FLAG_SYNC) return sync_status(ctx, s, 1, &it);
+    return DEXEL_OK;
 }
 
 dexel_status dexel_dilate(dexel_ctx* ctx, const dexel_grid_view* in, float r, dexel_grid_out* out,
