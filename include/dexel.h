@@ -79,9 +79,10 @@ typedef enum { DEXEL_DILATE = 0, DEXEL_ERODE = 1, DEXEL_OPEN = 2, DEXEL_CLOSE = 
 #define DEXEL_FLAG_VALIDATE 2u /* check the input is canonical before computing          */
 #define DEXEL_FLAG_RAYS_X 4u   /* dexel_dexelize only: rays along x (grid over y, z)      */
 #define DEXEL_FLAG_RAYS_Y 8u   /* dexel_dexelize only: rays along y (grid over z, x)      */
-/* Offsets: evaluate every erosion pass with the general kernels, without the
- * thin-column filter (for comparison; the result is the same, bit for bit). */
-#define DEXEL_FLAG_NO_THIN 16u
+/* Offsets: evaluate every column with the general kernels, without the
+ * tiled fast paths (the thin-column erosion filter and the single-interval
+ * dilation test); for comparison, the result is the same, bit for bit. */
+#define DEXEL_FLAG_GENERAL 16u
 
 typedef struct dexel_ctx dexel_ctx;
 
@@ -270,13 +271,14 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
 
 /* Profiling.  When enabled, every pass of every later call records HIP
  * events on its stream around each of its DEXEL_NPROF launch groups: column
- * gaps, thin-column erosion, row offset, its global-memory replay, neighbour intersection, its
+ * gaps, thin-column erosion, row offset, its replays, single-interval
+ * dilation, neighbour intersection, its
  * replay, extrusion seeds, their replay, y dilation with per-column union,
  * its replay, result scan, compaction copy.
  * dexel_profile_read waits for the recorded events and returns the
  * accumulated milliseconds per group and the number of passes (a dilation or
  * erosion is one pass, open/close two); reset != 0 clears the accumulators. */
-#define DEXEL_NPROF 12
+#define DEXEL_NPROF 13
 dexel_status dexel_profile_enable(dexel_ctx* ctx, int on);
 dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset);
 

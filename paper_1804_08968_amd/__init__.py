@@ -12,7 +12,7 @@ import torch
 from .binding import (  # noqa: F401
     DEXEL_CLOSE, DEXEL_DILATE, DEXEL_ERODE, DEXEL_ERR_CAPACITY, DEXEL_ERR_HIP,
     DEXEL_ERR_INVALID, DEXEL_ERR_NOT_CANONICAL, DEXEL_ERR_UNSUPPORTED, DEXEL_ERR_WORKSPACE,
-    DEXEL_FLAG_SYNC, DEXEL_FLAG_VALIDATE, DEXEL_FLAG_NO_THIN, DEXEL_OK, DEXEL_OPEN, EXPORTED, LIB_PATH, OPS,
+    DEXEL_FLAG_SYNC, DEXEL_FLAG_VALIDATE, DEXEL_FLAG_GENERAL, DEXEL_OK, DEXEL_OPEN, EXPORTED, LIB_PATH, OPS,
     DexelError, dexel_batch_item, dexel_batch_offset, dexel_batch_workspace_size,
     dexel_ctx_create, dexel_ctx_destroy, dexel_dilate, dexel_erode, dexel_grid_out,
     dexel_grid_view, dexel_last_error, dexel_offset, dexel_profile_enable, dexel_profile_read,
@@ -91,7 +91,7 @@ class Engine:
         workspace or output capacity; `hint` is the first capacity hint (0:
         the library's default for this input), and each retry starts from
         this call's own need, never from another call's.  `flags` adds
-        DEXEL_FLAG_* bits (e.g. DEXEL_FLAG_NO_THIN) to the call."""
+        DEXEL_FLAG_* bits (e.g. DEXEL_FLAG_GENERAL) to the call."""
         code = OPS[op]
         nseg = grid.nseg
         view = grid.view(nseg)

@@ -34,7 +34,7 @@ DEXEL_FLAG_SYNC = 1
 DEXEL_FLAG_VALIDATE = 2
 DEXEL_FLAG_RAYS_X = 4
 DEXEL_FLAG_RAYS_Y = 8
-DEXEL_FLAG_NO_THIN = 16
+DEXEL_FLAG_GENERAL = 16
 DEXEL_NOALLOC_SCRATCH_BYTES = 256 << 20
 RAY_FLAGS = {"x": DEXEL_FLAG_RAYS_X, "y": DEXEL_FLAG_RAYS_Y, "z": 0}
 DEXEL_CSG_UNION, DEXEL_CSG_INTERSECT, DEXEL_CSG_DIFFERENCE = 0, 1, 2
@@ -124,12 +124,12 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_csg_workspace_size", "dexel_csg", "dexel_dexelize_workspace_size",
             "dexel_dexelize", "dexel_canonicalize_workspace_size", "dexel_canonicalize"]
 NVARIANT = 4
-NPROF = 12
-PROFILE_STAGES = ["column_gaps", "thin_erosion", "row_offset", "row_offset_replay", "neighbour",
+NPROF = 13
+PROFILE_STAGES = ["column_gaps", "thin_erosion", "row_offset", "row_offset_replay", "solid_dilation", "neighbour",
                   "neighbour_replay", "seeds", "seeds_replay", "y_union", "y_union_replay",
                   "result_scan", "compact"]
 # main HIP kernel of each profiled group (as rocprofv3 names it)
-PROFILE_KERNELS = ["k_col_gaps", "k_thin_erode", "k_row_offset", "k_row_offset_fb", "k_neighbour",
+PROFILE_KERNELS = ["k_col_gaps", "k_thin_erode", "k_row_offset", "k_row_offset_fb", "k_solid_dilate", "k_neighbour",
                    "k_neighbour_fb", "k_seeds", "k_seeds_fb", "k_union", "k_union_fb", "k_scan",
                    "k_copy_out"]
 

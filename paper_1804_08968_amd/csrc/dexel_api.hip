@@ -62,7 +62,7 @@ void radius_params(float r, int* R, int* d2max) {
 // Workspace layout of one call (a batch of items; a single op is a batch of one).
 struct Layout {
     size_t hdr, shape_status, zbase, shapes1, shapes2, sbase1, sbase2, luts;
-    size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC, gen, need;
+    size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC, gen, need, lu;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table (shared per radius)
@@ -132,6 +132,7 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.scanC = take(8 * (g + 1));
     L.gen = take(g);
     L.need = take(g);
+    L.lu = take(16 * g);
     L.A = take(8 * cp);
     L.I = take(8 * cp);
     L.B = take(8 * g * dexel::SEED_SLOT);
@@ -322,12 +323,15 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.scanC = (int64_t*)(w + L.scanC) + gbase;
             S.gen = (uint8_t*)(w + L.gen) + gbase;
             S.need = (uint8_t*)(w + L.need) + gbase;
+            S.lu = (float4*)(w + L.lu) + gbase;
         };
-        // erosion passes of radii whose tiles fit the LDS run the thin-column
-        // filter first
-        auto thin_ok = [&](int erode) {
-            return erode && !(flags & DEXEL_FLAG_NO_THIN) && ii.R <= dexel::THIN_RMAX &&
-                   dexel::thin_lds_bytes(ii.R, ii.d2max) <= ctx->max_lds;
+        // passes of radii whose tiles fit the LDS take a tiled fast path:
+        // erosions the thin-column filter, dilations the single-interval test
+        auto fast_of = [&](int erode) {
+            if ((flags & DEXEL_FLAG_GENERAL) || ii.R > dexel::THIN_RMAX ||
+                dexel::thin_lds_bytes(ii.R, ii.d2max) > ctx->max_lds)
+                return (int32_t)dexel::FAST_NONE;
+            return (int32_t)(erode ? dexel::FAST_THIN : dexel::FAST_SOLID);
         };
         dexel::Shape a;
         fill(a, g1);
@@ -335,7 +339,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         a.z = (const float2*)it.in.z;
         a.nseg = it.in.nseg;
         a.erode = ops[0];
-        a.thin = thin_ok(a.erode) ? 1 : 0;
+        a.fast = fast_of(a.erode);
         if (ii.chain) {
             int64_t* mptr = (int64_t*)(w + L.mid_ptr) + mid;
             a.out_col_ptr = mptr;
@@ -350,7 +354,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             b.zoff = (const int64_t*)(w + L.zbase) + i;
             b.nseg = -1;
             b.erode = ops[1];
-            b.thin = thin_ok(b.erode) ? 1 : 0;
+            b.fast = fast_of(b.erode);
             b.out_col_ptr = it.out.col_ptr;
             b.out_z = (float2*)it.out.z;
             b.out_cap = it.out.cap_seg;
@@ -375,13 +379,13 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     }
     base1.push_back(g1);
     base2.push_back(g2);
-    // tiles of the thin shapes of each pass, numbered in shape order
+    // tiles of the shapes with a tiled fast path, numbered in shape order
     auto tile_bases = [](std::vector<dexel::Shape>& sh, int64_t* ntiles, int32_t* lds) {
         int64_t t = 0;
         int32_t b = 0;
         for (auto& S : sh) {
             S.tbase = t;
-            if (!S.thin) continue;
+            if (S.fast == dexel::FAST_NONE) continue;
             t += (int64_t)((S.nx + dexel::THIN_TX - 1) / dexel::THIN_TX) *
                  ((S.ny + dexel::THIN_TY - 1) / dexel::THIN_TY);
             const int32_t need = dexel::thin_lds_bytes(S.R, S.d2max);
@@ -419,10 +423,19 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     };
     dexel::Pass p1 = make_pass(L.shapes1, L.sbase1, (int)sh1.size(), g1);
     dexel::Pass p2 = make_pass(L.shapes2, L.sbase2, (int)sh2.size(), g2);
+    auto has = [](const std::vector<dexel::Shape>& sh, int32_t mode) {
+        for (const auto& S : sh)
+            if (S.fast == mode) return (int16_t)1;
+        return (int16_t)0;
+    };
     p1.ntiles = nt1;
-    p1.thin_lds = lds1;
+    p1.fast_lds = lds1;
+    p1.nthin = has(sh1, dexel::FAST_THIN);
+    p1.nsolid = has(sh1, dexel::FAST_SOLID);
     p2.ntiles = nt2;
-    p2.thin_lds = lds2;
+    p2.fast_lds = lds2;
+    p2.nthin = has(sh2, dexel::FAST_THIN);
+    p2.nsolid = has(sh2, dexel::FAST_SOLID);
     int64_t* zbase = (int64_t*)(w + L.zbase);
 
     HIP_TRY(dexel::launch_init_call(p1.hdr, p1.shape_status, n, s));

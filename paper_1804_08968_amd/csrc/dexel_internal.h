@@ -18,7 +18,7 @@ struct WsHeader {
     unsigned long long bumpC;
     unsigned long long arena;       // bump allocator of the overflow arena
     int64_t nseg_out;
-    int32_t novf[8];                // columns whose per-lane list overflowed LDS, per stage
+    int32_t novf[10];               // columns on each overflow / work list (Stage)
     unsigned long long nseeds;      // kept extrusion seeds of the current pass
     int64_t reserved[2];
 };
@@ -26,10 +26,12 @@ static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 
 // Overflow lists: columns whose per-lane list overflowed in K1, K1b, K2 (seed
 // slot) and K3, replayed one lane per column; and columns deferred as heavy
-// in K2, K1b and K3, replayed one wave per column (z slabs).
+// in K2, K1b and K3, or overflowing K1's lane replay, replayed one wave per
+// column (z slabs); and the columns of a single-interval dilation test left
+// to the gap cut.
 enum Stage {
     ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3,
-    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, NSTAGE = 7
+    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, NSTAGE = 9
 };
 
 // Seed slots per column: the seeds of a column are written at
@@ -70,15 +72,19 @@ struct Shape {
     float2* out_z;
     const int64_t* out_zoff;  // if set, results are written at out_z + *out_zoff
     int64_t out_cap;
-    // thin-column erosion (k_thin_erode): `thin` set for an erosion pass the
-    // tiled max / min filter evaluates first; its tiles are tbase .. of the
-    // pass.  gen[c] = 1 marks an output column left to the general kernels,
-    // need[c] the general stages column c must run for them (NEED_* bits).
-    int32_t thin;
+    // tiled fast paths: `fast` = FAST_THIN for an erosion pass the thin-column
+    // max / min filter evaluates before the row offset, FAST_SOLID for a
+    // dilation pass whose single-interval columns k_solid_dilate settles after
+    // it; the shape's tiles are tbase .. of the pass.  gen[c] = 1 marks an
+    // output column left to the general kernels, need[c] the general stages
+    // column c must run for them (NEED_* bits).
+    int32_t fast;
     int32_t pad1;
     int64_t tbase;
     uint8_t* gen;
     uint8_t* need;
+    float4* lu;               // FAST_SOLID, columns left to the gap cut: smallest chord start and
+                              // largest chord end, and where its gaps start and end (see k_solid_dilate)
     int32_t out_is_intermediate;
     int32_t last_pass;        // write the caller's nseg_out / status after this pass
     int64_t* out_nseg;
@@ -92,9 +98,9 @@ struct Pass {
     int32_t nshapes;
     int32_t pad;
     int64_t gcols;            // padded global column count of the pass
-    int64_t ntiles;           // tiles of the thin-column erosion over the pass's thin shapes
-    int32_t thin_lds;         // dynamic LDS bytes of k_thin_erode (largest R of the thin shapes)
-    int32_t pad2;
+    int64_t ntiles;           // tiles of the tiled fast paths over the pass's shapes that have one
+    int32_t fast_lds;         // dynamic LDS bytes of the tiled fast paths (largest R of their shapes)
+    int16_t nthin, nsolid;    // shapes of the pass with each fast path
     WsHeader* hdr;
     int32_t* shape_status;    // [items] per-item status (output capacity)
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
@@ -139,12 +145,14 @@ hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hi
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
 // Profiled intervals of one pass, one per launch group: column gaps,
-// thin-column erosion, row offset, its replay, neighbour intersection, its
-// replay, seeds, their replay, y dilation + union, its replay, result scan,
-// compaction.
-constexpr int NPROF = 12;
-// Thin-column erosion: tile of THIN_TX x THIN_TY output columns, radii up to
-// THIN_RMAX; LDS bytes a tile stages at integer radius R.
+// thin-column erosion, row offset, its replays, single-interval dilation,
+// neighbour intersection, its replays, seeds, their replays, y dilation +
+// union, its replays, result scan, compaction.
+constexpr int NPROF = 13;
+enum FastPath { FAST_NONE = 0, FAST_THIN = 1, FAST_SOLID = 2 };
+// Tiled fast paths: tile of THIN_TX x THIN_TY output columns, radii up to
+// THIN_RMAX; LDS bytes a tile stages at integer radius R (one float2 per
+// staged column, the half-width table and the stencil's row widths).
 constexpr int THIN_TX = 64;
 constexpr int THIN_TY = 16;
 constexpr int THIN_RMAX = 32;

@@ -271,14 +271,12 @@ __device__ __forceinline__ int col_len(const OpParams& P, int64_t cc, int64_t* b
 // the capacity.
 //
 // Every step consumes exactly one chord (the U entries that start first are
-// taken in an inner loop), so the column's items are loaded a group of
-// MERGE_AHEAD steps ahead: the loads of the next group are issued before the
-// current group is processed, and the only wait is at the end of a group.
-// Loads past the end of the column are clamped to its last item and never
-// used.
-constexpr int MERGE_AHEAD = 8;
-
-template <bool E, class L>
+// taken in an inner loop), so the column's items are kept in a ring of
+// AHEAD registers: the item consumed by a step is replaced at once by the
+// load of the item AHEAD steps later, so every load has AHEAD steps to
+// arrive.  Loads past the end of the column are clamped to its last item and
+// never used.
+template <bool E, int AHEAD, class L>
 __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int m, int cnt, float h) {
     const int top = U.cap - n, last = U.cap - 1;
     for (int i = n - 1; i >= 0; --i) U.set(top + i, U.get(i));
@@ -286,8 +284,9 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
     // chord (-inf, inf), never merged)
     const float2* zc = P.z + b;
     auto raw = [&](int j) { return gld(&zc[min(j, m - 1)]); };
-    float2 c0 = raw(0), c1 = raw(1), c2 = raw(2), c3 = raw(3);
-    float2 c4 = raw(4), c5 = raw(5), c6 = raw(6), c7 = raw(7);
+    float2 ring[AHEAD];
+#pragma unroll
+    for (int q = 0; q < AHEAD; ++q) ring[q] = raw(q);
     float2 u0 = U.get(min(top, last));  // next unread entry of U
     float prevy = -DX_INF;              // E: end of the previous item
     float2 cur = make_float2(0.f, 0.f);  // the open output interval
@@ -318,25 +317,13 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
         }
         push(c);
     };
-    for (int j = 0; j < cnt; j += MERGE_AHEAD) {
-        const float2 n0 = raw(j + 8), n1 = raw(j + 9), n2 = raw(j + 10), n3 = raw(j + 11);
-        const float2 n4 = raw(j + 12), n5 = raw(j + 13), n6 = raw(j + 14), n7 = raw(j + 15);
-        step(c0, j);
-        step(c1, j + 1);
-        step(c2, j + 2);
-        step(c3, j + 3);
-        step(c4, j + 4);
-        step(c5, j + 5);
-        step(c6, j + 6);
-        step(c7, j + 7);
-        c0 = n0;
-        c1 = n1;
-        c2 = n2;
-        c3 = n3;
-        c4 = n4;
-        c5 = n5;
-        c6 = n6;
-        c7 = n7;
+    for (int j = 0; j < cnt; j += AHEAD) {
+#pragma unroll
+        for (int q = 0; q < AHEAD; ++q) {
+            const float2 it = ring[q];
+            ring[q] = raw(j + q + AHEAD);
+            step(it, j + q);
+        }
     }
     while (i < n) {
         push(u0);
@@ -384,7 +371,7 @@ __device__ __forceinline__ int pass2_offset(int v, int R) {
     return (k & 1) ? t : -t;
 }
 
-template <bool E, class L>
+template <bool E, int AHEAD, class L>
 __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
     int x, y;
     col_xy(P, c, &x, &y);
@@ -478,7 +465,7 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
             }
         }
         if (n != 1) {
-            n = merge_column<E>(P, U, n, bc, m, cnt, h);
+            n = merge_column<E, AHEAD>(P, U, n, bc, m, cnt, h);
             if (n < 0) return -1;
             continue;
         }
@@ -520,9 +507,11 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
     return n;
 }
 
-template <class L>
+constexpr int MERGE_AHEAD = 8;
+
+template <int AHEAD = MERGE_AHEAD, class L>
 __device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
-    return P.erode ? k1_column_e<true>(P, c, U) : k1_column_e<false>(P, c, U);
+    return P.erode ? k1_column_e<true, AHEAD>(P, c, U) : k1_column_e<false, AHEAD>(P, c, U);
 }
 
 __device__ int64_t k1_bound(const OpParams& P, int64_t c) {
@@ -1128,6 +1117,42 @@ __device__ int k1b_slab(const OpParams& P, int64_t c, float zs, float ze, const 
     return n;
 }
 
+// K1 restricted to the slab [zs, ze]: the chords of the row window clipped to
+// the slab, nearest columns first; only the chords from the first one ending
+// at or above zs to the last one starting at or below ze are visited, and the
+// lane stops once its slab is covered whole.
+template <bool E, class L>
+__device__ int k1_slab_e(const OpParams& P, int64_t c, float zs, float ze, const L& U) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const int64_t row = (int64_t)y * P.nx;
+    int n = 0;
+    for (int v = 0; v <= 2 * P.R; ++v) {
+        const int xx = visit_col(x, v);
+        if (xx < 0 || xx >= P.nx) continue;
+        const int t = (v + 1) >> 1;
+        const float h = gld(&P.H[t * t]);
+        int64_t b;
+        const int m = col_len(P, row + xx, &b);
+        const int cnt = E ? m + 1 : m;
+        int l = 0, hh = cnt;  // first chord ending at or above zs
+        while (l < hh) {
+            const int mid = (l + hh) >> 1;
+            if (col_item<E>(P.z, b, m, mid).y + h < zs) l = mid + 1; else hh = mid;
+        }
+        int hint = 0;
+        for (int k = l; k < cnt; ++k) {
+            const float2 it = col_item<E>(P.z, b, m, k);
+            const float lo = it.x - h, hi = it.y + h;
+            if (lo > ze) break;
+            n = lv_insert_fwd(U, n, fmaxf(lo, zs), fminf(hi, ze), &hint);
+            if (n < 0) return -1;
+        }
+        if (n == 1 && U.get(0).x <= zs && U.get(0).y >= ze) break;
+    }
+    return n;
+}
+
 // K2 restricted to the slab [zs, ze]: the input items of the row window are
 // clipped to the slab before painting, so a piece cut at a slab boundary is
 // kept as two pieces whose chords overlap.
@@ -1427,10 +1452,12 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
     return pl;
 }
 
-// Must column c of shape S run the general stage `bit`?  Only the columns of
-// thin shapes skip stages.
+// Must column c of shape S run the general stage `bit`?  Only shapes with a
+// tiled fast path skip stages; a FAST_SOLID shape decides after the row
+// offset, which therefore runs on all its columns.
 __device__ __forceinline__ bool needs(const Shape& S, int64_t c, int bit) {
-    return !S.thin || (gld(&S.need[c]) & bit);
+    if (S.fast == FAST_NONE || (S.fast == FAST_SOLID && bit == NEED_ROW)) return true;
+    return (gld(&S.need[c]) & bit) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1527,8 +1554,9 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     emit_wave(P, pl.c, valid, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
 }
 
-// Replay of K1 for columns whose list overflowed: one lane per column over the
-// full grid, a K1_FB_CAP-entry LDS list first, then the growing arena tier.
+// Replay of K1 for columns whose list overflowed: one lane per column with a
+// K1_FB_CAP-entry LDS list; a column that overflows it too goes on to the
+// slab replay (k_row_offset_heavy).
 __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     __shared__ float2 lds[K1_FB_CAP * WG];
     if (Q.hdr->abort) return;
@@ -1540,19 +1568,73 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     const int s = find_shape(Q, g);
     const OpParams P = make_op(Q, Q.shapes[s]);
     const int64_t c = g - Q.sbase[s];
-    {
-        LdsList L{&lds[threadIdx.x], K1_FB_CAP};
-        const int n = k1_column(P, c, L);
-        if (n >= 0) {
-            emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
-            return;
+    LdsList L{&lds[threadIdx.x], K1_FB_CAP};
+    const int n = k1_column(P, c, L);
+    if (n >= 0) emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
+    else push_overflow(Q, ST_K1H, g);  // long partial union: the slab replay
+}
+
+// Replay of K1 for the columns whose partial union outgrew the lane replay
+// (as a rule at the grid's x borders, where the one-sided row window leaves
+// the union fragmented): one wave per column, one z-slab per lane; lane 0
+// stitches the slab lists into an arena list and emits it.  If a slab list
+// overflows, lane 0 evaluates the column alone in the growing arena tier.
+__global__ void __launch_bounds__(WG) k_row_offset_heavy(Pass Q) {
+    __shared__ float2 lds[CAP_Z * WG];
+    __shared__ int nsh[WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_K1H];
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int64_t g = Q.ovf[(int64_t)ST_K1H * Q.gcols + e];
+        const int s = find_shape(Q, g);
+        const OpParams P = make_op(Q, Q.shapes[s]);
+        const int64_t c = g - Q.sbase[s];
+        int x, y;
+        col_xy(P, c, &x, &y);
+        const int64_t row = (int64_t)y * P.nx;
+        // finite z range of the row window's intervals (column summaries)
+        float zmin = DX_INF, zmax = -DX_INF;
+        for (int j = lane; j <= 2 * P.R; j += WG) {
+            const int xx = x - P.R + j;
+            if (xx < 0 || xx >= P.nx || gld(&P.gap[row + xx]) < 0.f) continue;
+            const float4 e4 = gld(&P.ends[row + xx]);
+            widen(&zmin, &zmax, e4.x);
+            widen(&zmin, &zmax, e4.w);
         }
+        zmin = wave_min(zmin);
+        zmax = wave_max(zmax);
+        const float2 sl = lane_slab(zmin, zmax);
+        LdsList U{&lds[lane], CAP_Z};
+        const int n = P.erode ? k1_slab_e<true>(P, c, sl.x, sl.y, U) : k1_slab_e<false>(P, c, sl.x, sl.y, U);
+        __syncthreads();  // the previous column's stitch has read nsh and lds
+        nsh[lane] = n;
+        __syncthreads();
+        const bool fail = __any(n < 0);
+        if (lane != 0) continue;
+        if (fail) {
+            arena_eval(P, 1, k1_bound(P, c), [&](const MemList& M, const MemList&) {
+                const int nn = k1_column(P, c, M);
+                if (nn >= 0) emit_lane(P, c, M, nn, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
+                return nn;
+            });
+            continue;
+        }
+        int64_t tot = 0;
+        for (int l = 0; l < WG; ++l) tot += nsh[l];
+        const int64_t pos = arena_alloc(P, tot > 0 ? tot : 1);
+        if (pos < 0) continue;
+        float2* out = P.arena + pos;
+        int k = 0;
+        for (int l = 0; l < WG; ++l)
+            for (int i = 0; i < nsh[l]; ++i) {
+                const float2 v = lds[i * WG + l];
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                else out[k++] = v;
+            }
+        MemList M{out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
+        emit_lane(P, c, M, k, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
     }
-    arena_eval(P, 1, k1_bound(P, c), [&](const MemList& U, const MemList&) {
-        const int n = k1_column(P, c, U);
-        if (n >= 0) emit_lane(P, c, U, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
-        return n;
-    });
 }
 
 template <int CAP>
@@ -1855,7 +1937,7 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
     if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
-    // columns of thin shapes that k_thin_erode finished are skipped
+    // columns a tiled fast path finished are skipped
     const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_UNION);
     if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
@@ -2105,6 +2187,7 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
         if (Q.shapes[m].tbase <= t) lo = m; else hi = m;
     }
     const Shape& S = Q.shapes[lo];
+    if (S.fast != FAST_THIN) return;
     const OpParams P = make_op(Q, S);
     const int R = P.R;
     const int ntx = (P.nx + THIN_TX - 1) / THIN_TX;
@@ -2196,15 +2279,345 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
     }
 }
 
-// need[c] of every column of a thin shape: NEED_UNION if the column is
-// general itself, NEED_SEEDS if a general column lies within R rows of it
-// (its seeds and intersection feed that column's y union), NEED_ROW if one
-// lies within 2R rows (its row offset feeds those intersections).
-__global__ void __launch_bounds__(WG) k_thin_spread(Pass Q) {
+// Tile shapes of the tiled fast paths: the stencil's half-width table and
+// row widths wd[k] (largest |dx| at |dy| = k), staged by the whole block.
+__device__ __forceinline__ void stage_stencil(const OpParams& P, float* Hs, int* wd) {
+    for (int i = threadIdx.x; i <= P.d2max; i += THIN_T) Hs[i] = gld(&P.H[i]);
+    for (int k = threadIdx.x; k <= P.R; k += THIN_T) {
+        int w = 0;
+        while ((w + 1) * (w + 1) + k * k <= P.d2max) ++w;
+        wd[k] = w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dilation by the chord extremes and a gap cut
+// ---------------------------------------------------------------------------
+//
+// Every chord of an output column's stencil lies in [L, U], with
+// L = min fl(af - H[d2]) and U = max fl(bl + H[d2]) over the stencil columns
+// (af, bl: a column's first start and last end), and both ends belong to the
+// union.  V0(c) = [L0 .. U0], the union of the chords of the column's own
+// row, is part of it too.  A chord [L, e] with e >= L0 exists iff the
+// smallest start of the chords reaching L0 (first items suffice: a column's
+// first chord has both its smallest start and smallest end) equals L; then
+// [L, L0] is covered, and likewise [U0, U] if the largest end of the chords
+// starting at or below U0 equals U.  The union is then [L, U] minus the
+// points of the open gaps of V0, and of (L, L0) or (U0, U) where not
+// covered, that no chord of another row covers.  k_solid_dilate evaluates
+// these filters on the tiles of k_thin_erode, staging each column's first
+// item, then its last item, in LDS: a column with no such gap is settled as
+// [L, U]; one with at most GC_CAP goes to the gap cut (k_gap_cut), which
+// applies the chords of the other rows to its gaps; every other column is
+// left to the general kernels.
+constexpr int GC_CAP = 4;      // open gaps the gap cut tracks per column
+constexpr int GC_BUDGET = 160; // stencil columns meeting a gap it visits before giving up
+
+__global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
+    extern __shared__ float2 thin_lds[];
+    if (Q.hdr->abort) return;
+    const int64_t t = map_block(Q.ntiles);
+    int lo = 0, hi = Q.nshapes;
+    while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (Q.shapes[m].tbase <= t) lo = m; else hi = m;
+    }
+    const Shape& S = Q.shapes[lo];
+    if (S.fast != FAST_SOLID) return;
+    const OpParams P = make_op(Q, S);
+    const int R = P.R;
+    const int ntx = (P.nx + THIN_TX - 1) / THIN_TX;
+    const int64_t tl = t - S.tbase;
+    const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * THIN_TY;
+    const int SW = THIN_TX + 2 * R, SH = THIN_TY + 2 * R;
+    float2* st = thin_lds;
+    float* Hs = (float*)(st + SW * SH);
+    int* wd = (int*)(Hs + P.d2max + 1);
+    stage_stencil(P, Hs, wd);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = x0 + lane;
+    constexpr int KR = THIN_TY / 4;  // output rows per wave
+    // V0 of this lane's output columns: count, first start, last end
+    int n0[KR];
+    float L0[KR], U0[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int y = y0 + wv + 4 * k;
+        n0[k] = -1;
+        L0[k] = DX_INF;
+        U0[k] = -DX_INF;
+        if (x < P.nx && y < P.ny) {
+            const int64_t c = (int64_t)y * P.nx + x;
+            n0[k] = gld(&P.cntA[c]);
+            if (n0[k] > 0) {
+                const float2* V = P.A + gld(&P.offA[c]);
+                L0[k] = gld(&V[0]).x;
+                U0[k] = gld(&V[n0[k] - 1]).y;
+            }
+        }
+    }
+    float L[KR], Lg[KR], U[KR], Ug[KR];
+    for (int half = 0; half < 2; ++half) {
+        // half 0: first items (af, bf), neutral (+inf, -inf); half 1: last
+        // items (al, bl), neutral (+inf, -inf) too
+        if (half) __syncthreads();  // half 0 has read the staging buffer
+        for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
+            const int sy = i / SW, sx = i - sy * SW;
+            const int xx = x0 - R + sx, yy = y0 - R + sy;
+            float2 v = make_float2(DX_INF, -DX_INF);
+            if (xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
+                const int64_t c = (int64_t)yy * P.nx + xx;
+                if (gld(&P.gap[c]) >= 0.f) {
+                    const float4 e4 = gld(&P.ends[c]);
+                    v = half ? make_float2(e4.z, e4.w) : make_float2(e4.x, e4.y);
+                }
+            }
+            st[i] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+            const int ly = wv + 4 * k;
+            if (y0 + ly >= P.ny) break;  // wave-uniform
+            const float2* ctr = st + (ly + R) * SW + lane + R;
+            // half 0: m = min start, g = min start of the chords ending at or above L0
+            // half 1: m = max end, g = max end of the chords starting at or below U0
+            float m = half ? -DX_INF : DX_INF, g = m;
+            const float tgt = half ? U0[k] : L0[k];
+            for (int dy = -R; dy <= R; ++dy) {
+                const int w = wd[dy < 0 ? -dy : dy];
+                const float2* row = ctr + dy * SW;
+                const float* hr = Hs + dy * dy;
+                for (int dx = -w; dx <= w; ++dx) {
+                    const float2 v = row[dx];
+                    const float hh = hr[dx * dx];
+                    const float a = v.x - hh, b = v.y + hh;
+                    if (half == 0) {
+                        m = fminf(m, a);
+                        g = fminf(g, b >= tgt ? a : DX_INF);
+                    } else {
+                        m = fmaxf(m, b);
+                        g = fmaxf(g, a <= tgt ? b : -DX_INF);
+                    }
+                }
+            }
+            if (half == 0) {
+                L[k] = m;
+                Lg[k] = g;
+            } else {
+                U[k] = m;
+                Ug[k] = g;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int y = y0 + wv + 4 * k;
+        if (y >= P.ny) break;  // wave-uniform
+        const bool live = x < P.nx;
+        const int64_t c = (int64_t)y * P.nx + x;
+        // open gaps left: V0's own, and the end pieces not covered by one chord
+        int ng = 0;
+        if (live && L[k] <= U[k]) {
+            if (n0[k] == 0) ng = L[k] < U[k] ? 1 : 0;
+            else ng = (n0[k] - 1) + (Lg[k] != L[k] ? 1 : 0) + (Ug[k] != U[k] ? 1 : 0);
+        }
+        const bool done = live && (L[k] > U[k] || ng == 0);
+        const bool cut = live && !done && ng <= GC_CAP;
+        const int outn = (done && L[k] <= U[k]) ? 1 : 0;
+        int tot;
+        const int pre = wave_excl_scan(outn, &tot);
+        unsigned long long base = 0;
+        if (lane == 0 && tot > 0) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        const unsigned long long end = base + (unsigned long long)tot;
+        const bool ok = end <= (unsigned long long)P.cap;
+        if (!ok && lane == 0) {
+            note_need(P.hdr, end);
+            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        }
+        if (!live) continue;
+        gst(&S.gen[c], (uint8_t)(done || cut ? 0 : 1));
+        if (cut) {
+            // (L, U) and the range the gaps are taken from: an end already
+            // covered by one chord starts it at V0's end instead
+            gst(&S.lu[c], make_float4(L[k], U[k], Lg[k] == L[k] && n0[k] > 0 ? L0[k] : L[k],
+                                      Ug[k] == U[k] && n0[k] > 0 ? U0[k] : U[k]));
+            push_overflow(Q, ST_GAP, S.gbase + c);
+        }
+        if (!done) continue;
+        gst(&P.offC[c], (int64_t)(base + pre));
+        gst(&P.cntC[c], ok ? outn : 0);
+        if (ok && outn) gst(&P.C[base + pre], make_float2(L[k], U[k]));
+    }
+}
+
+// Gap cut of one column: its open gaps (at most GC_CAP, sorted, in G) are cut
+// by the chords of the stencil columns outside its own row (that row is in
+// V0 already), visited ring by ring from the nearest.  A chord [A, B] removes
+// [A, B] from a gap (l, u) it meets (A < u, B > l), leaving (l, A) if A > l
+// and (B, u) if B < u.  Returns the number of gaps left (all of them now gaps
+// of the union), or -1 if they outgrow GC_CAP or the visits the budget.
+template <class L>
+__device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, int ng) {
+    int budget = GC_BUDGET;
+    const L* cur = &G;
+    const L* oth = &T;
+    auto visit = [&](int dx, int dy) -> bool {  // false: give up
+        const int xx = x + dx, yy = y + dy;
+        if (xx < 0 || xx >= P.nx || yy < 0 || yy >= P.ny) return true;
+        const int d2 = dx * dx + dy * dy;
+        if (d2 > P.d2max) return true;
+        const int64_t cc = (int64_t)yy * P.nx + xx;
+        if (gld(&P.gap[cc]) < 0.f) return true;
+        const float h = gld(&P.H[d2]);
+        const float4 e4 = gld(&P.ends[cc]);
+        const float A0 = e4.x - h, B1 = e4.w + h;
+        bool meet = false;
+        for (int j = 0; j < ng; ++j) {
+            const float2 g = cur->get(j);
+            meet = meet || (A0 < g.y && B1 > g.x);
+        }
+        if (!meet) return true;
+        if (--budget < 0) return false;
+        const int64_t b = gld(&P.col_ptr[cc]);
+        const int m = (int)(gld(&P.col_ptr[cc + 1]) - b);
+        const float2* zc = P.z + b;
+        int k = 0, nn = 0;
+        for (int j = 0; j < ng; ++j) {
+            const float2 g = cur->get(j);
+            if (!(A0 < g.y && B1 > g.x)) {
+                if (nn >= GC_CAP) return false;
+                oth->set(nn++, g);
+                continue;
+            }
+            // first chord ending above the gap's start (chord ends increase)
+            int l = k, hh = m;
+            while (l < hh) {
+                const int mid = (l + hh) >> 1;
+                if (gld(&zc[mid]).y + h > g.x) hh = mid; else l = mid + 1;
+            }
+            k = l;
+            float cl = g.x;
+            for (; k < m; ++k) {
+                const float2 it = gld(&zc[k]);
+                const float A = it.x - h;
+                if (!(A < g.y)) break;
+                if (A > cl) {
+                    if (nn >= GC_CAP) return false;
+                    oth->set(nn++, make_float2(cl, A));
+                }
+                cl = fmaxf(cl, it.y + h);
+                if (!(cl < g.y)) break;
+            }
+            if (cl < g.y) {
+                if (nn >= GC_CAP) return false;
+                oth->set(nn++, make_float2(cl, g.y));
+            }
+            // the next gap starts above this one: resume at the last chord seen
+            if (k > 0) --k;
+        }
+        ng = nn;
+        const L* tmp = cur;
+        cur = oth;
+        oth = tmp;
+        return true;
+    };
+    for (int r = 1; r <= P.R && ng > 0; ++r) {
+        for (int s = -1; s <= 1 && ng > 0; s += 2) {          // rows y -+ r
+            for (int dx = -r; dx <= r && ng > 0; ++dx)
+                if (!visit(dx, s * r)) return -1;
+        }
+        for (int s = -1; s <= 1 && ng > 0; s += 2) {          // columns x -+ r, rows in between
+            for (int dy = -(r - 1); dy <= r - 1 && ng > 0; ++dy)
+                if (dy != 0 && !visit(s * r, dy)) return -1;
+        }
+    }
+    if (cur != &G)
+        for (int j = 0; j < ng; ++j) G.set(j, cur->get(j));
+    return ng;
+}
+
+// The columns k_solid_dilate left to the gap cut, one lane each: build the
+// gaps of V0 inside [L, U], cut them, and write [L, U] minus what is left; a
+// column the cut gives up on is marked general.
+__global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
+    __shared__ float2 lds[2 * GC_CAP * WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_GAP];
+    if ((int64_t)blockIdx.x * WG >= cnt) return;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const bool live = i < cnt;
+    const int64_t g = live ? Q.ovf[(int64_t)ST_GAP * Q.gcols + i] : Q.ovf[(int64_t)ST_GAP * Q.gcols];
+    const int s = find_shape(Q, g);
+    const Shape& S = Q.shapes[s];
+    const OpParams P = make_op(Q, S);
+    const int64_t c = g - Q.sbase[s];
+    int x, y;
+    col_xy(P, c, &x, &y);
+    const LdsList G{&lds[threadIdx.x], GC_CAP};
+    const LdsList T{&lds[GC_CAP * WG + threadIdx.x], GC_CAP};
+    const float4 lu = gld(&S.lu[c]);
+    int ng = 0;
+    if (live) {
+        // the gaps of V0 inside [lu.z, lu.w], in order
+        const int n0 = gld(&P.cntA[c]);
+        const float2* V = P.A + gld(&P.offA[c]);
+        // (at most GC_CAP of them, as k_solid_dilate counted)
+        float prev = lu.z;
+        for (int j = 0; j < n0 && ng >= 0; ++j) {
+            const float2 v = gld(&V[j]);
+            if (v.x > prev) {
+                if (ng < GC_CAP) G.set(ng++, make_float2(prev, v.x)); else ng = -1;
+            }
+            prev = fmaxf(prev, v.y);
+        }
+        if (ng >= 0 && lu.w > prev) {
+            if (ng < GC_CAP) G.set(ng++, make_float2(prev, lu.w)); else ng = -1;
+        }
+        if (ng >= 0) ng = gap_cut(P, x, y, G, T, ng);
+    }
+    const bool ok1 = live && ng >= 0;
+    const int outn = ok1 ? ng + 1 : 0;
+    int tot;
+    const int pre = wave_excl_scan(outn, &tot);
+    unsigned long long base = 0;
+    if (threadIdx.x == 0 && tot > 0) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    const unsigned long long end = base + (unsigned long long)tot;
+    const bool ok = end <= (unsigned long long)P.cap;
+    if (!ok && threadIdx.x == 0) {
+        note_need(P.hdr, end);
+        set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+    }
+    if (!live) return;
+    if (!ok1) {
+        gst(&S.gen[c], (uint8_t)1);
+        return;
+    }
+    gst(&P.offC[c], (int64_t)(base + pre));
+    gst(&P.cntC[c], ok ? outn : 0);
+    if (!ok) return;
+    float2* d = P.C + base + pre;
+    float a = lu.x;  // the union is [L, U] minus the gaps left
+    for (int j = 0; j < ng; ++j) {
+        const float2 gp = G.get(j);
+        gst(&d[j], make_float2(a, gp.x));
+        a = gp.y;
+    }
+    gst(&d[ng], make_float2(a, lu.y));
+}
+
+// need[c] of every column of the shapes with fast path `mode`: NEED_UNION if
+// the column is general itself, NEED_SEEDS if a general column lies within R
+// rows of it (its seeds and intersection feed that column's y union),
+// NEED_ROW if one lies within 2R rows (its row offset feeds those
+// intersections).
+__global__ void __launch_bounds__(WG) k_fast_spread(Pass Q, int mode) {
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
     const Shape& S = Q.shapes[pl.s];
-    if (!S.thin || !pl.valid) return;
+    if (S.fast != mode || !pl.valid) return;
     const int y = (int)(pl.c / S.nx), x = (int)(pl.c - (int64_t)y * S.nx);
     int bits = gld(&S.gen[pl.c]) ? NEED_UNION | NEED_SEEDS | NEED_ROW : 0;
     for (int d = 1; d <= 2 * S.R && !(bits & NEED_SEEDS) && !(bits && d > S.R); ++d) {
@@ -2258,12 +2671,12 @@ __global__ void k_init_call(WsHeader* h, int32_t* shape_status, int nitems) {
         h->nseeds = 0;
         h->bumpA = h->bumpI = h->bumpC = h->arena = 0;
     }
-    if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
+    if (threadIdx.x < NSTAGE) h->novf[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < nitems; i += blockDim.x) shape_status[i] = 0;
 }
 
 __global__ void k_init_pass(WsHeader* h) {
-    if (threadIdx.x < 8) h->novf[threadIdx.x] = 0;
+    if (threadIdx.x < NSTAGE) h->novf[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         h->bumpA = h->bumpI = h->bumpC = h->arena = 0;
         h->nseeds = 0;
@@ -2993,35 +3406,42 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(0);
     hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
-    if (p.ntiles > 0) {
-        hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.thin_lds, s, p);
-        hipLaunchKernelGGL(k_thin_spread, g, b, 0, s, p);
+    if (p.ntiles > 0 && p.nthin > 0) {
+        hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.fast_lds, s, p);
+        hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_THIN);
     }
     DX_MARK(2);
     hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
     DX_MARK(3);
     hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
+    hipLaunchKernelGGL(k_row_offset_heavy, gf, b, 0, s, p);
     DX_MARK(4);
-    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    if (p.ntiles > 0 && p.nsolid > 0) {
+        hipLaunchKernelGGL(k_solid_dilate, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.fast_lds, s, p);
+        hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
+        hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_SOLID);
+    }
     DX_MARK(5);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    DX_MARK(6);
     hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
-    DX_MARK(6);
-    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(7);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
+    DX_MARK(8);
     hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
     hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
-    DX_MARK(8);
-    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(9);
+    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
+    DX_MARK(10);
     hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
-    DX_MARK(10);
+    DX_MARK(11);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
-    DX_MARK(11);
-    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
     DX_MARK(12);
+    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
+    DX_MARK(13);
 #undef DX_MARK
     return hipGetLastError();
 }

@@ -68,7 +68,7 @@ def test_constants_match_binding():
                  "DEXEL_ERODE", "DEXEL_OPEN", "DEXEL_CLOSE", "DEXEL_FLAG_SYNC",
                  "DEXEL_FLAG_VALIDATE", "DEXEL_CSG_UNION", "DEXEL_CSG_INTERSECT",
                  "DEXEL_CSG_DIFFERENCE", "DEXEL_PRIM_BALL", "DEXEL_PRIM_BOX",
-                 "DEXEL_FLAG_RAYS_X", "DEXEL_FLAG_RAYS_Y", "DEXEL_FLAG_NO_THIN"):
+                 "DEXEL_FLAG_RAYS_X", "DEXEL_FLAG_RAYS_Y", "DEXEL_FLAG_GENERAL"):
         assert name in c, name
         assert getattr(binding, name) == c[name], name
     assert c["DEXEL_NVARIANT"] == binding.NVARIANT

@@ -113,7 +113,7 @@ def test_c3_closing_thin_equals_general(engine, c3_grid, results):
     col_ptr, z = _result(results, engine, c3_grid, 16.0, "close")
     print("[case] gyroid2048 close r=16 general kernels (GPU)", flush=True)
     dg = dx.DeviceGrid.from_host(c3_grid)
-    gcp, gz = engine.offset(dg, 16.0, "close", flags=dx.DEXEL_FLAG_NO_THIN).to_host()
+    gcp, gz = engine.offset(dg, 16.0, "close", flags=dx.DEXEL_FLAG_GENERAL).to_host()
     assert np.array_equal(col_ptr, gcp)
     assert np.array_equal(z[: 2 * col_ptr[-1]], gz[: 2 * gcp[-1]])
 

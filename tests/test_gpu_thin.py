@@ -10,7 +10,7 @@ is [MA, MB] or empty (Sec. 3.1, "Erosion", with the chords of Sec. 4,
 kernel and leaves every other column to the general kernels, which then run
 only where such a column needs them.  Each case is checked three ways:
 bit-exact against the oracle's float32 model, within tolerance of the
-float64 oracle, and bit-exact against the same call with DEXEL_FLAG_NO_THIN
+float64 oracle, and bit-exact against the same call with DEXEL_FLAG_GENERAL
 (general kernels for every column).
 
 Grids cut the 64 x 16 tiles raggedly, mix in columns of two or more
@@ -79,7 +79,7 @@ def check(engine, oracle, g, r, op, label):
     import paper_1804_08968_amd as dx
     print(f"[case] thin {label} nx={g.nx} ny={g.ny} nseg={g.nseg} r={r} op={op}", flush=True)
     col_ptr, z = run(engine, g, r, op)
-    gcp, gz = run(engine, g, r, op, flags=dx.DEXEL_FLAG_NO_THIN)
+    gcp, gz = run(engine, g, r, op, flags=dx.DEXEL_FLAG_GENERAL)
     assert np.array_equal(col_ptr, gcp), "counts differ from the general kernels"
     assert np.array_equal(z[: 2 * col_ptr[-1]], gz[: 2 * gcp[-1]]), "endpoints differ from the general kernels"
     ref32 = oracle.run(g, r, op, "f32model")
