@@ -126,7 +126,7 @@ def kernel_bytes(stage, ncols, n_in, st):
     return {
         "column_gaps": inp + 4 * ncols,
         "thin_erosion": inp + ncols + 12 * ncols + 8 * res,
-        "solid_dilation": 20 * ncols + lst_v0 + ncols + 12 * ncols + 8 * res,
+        "chord_extremes": 20 * ncols + ncols + 12 * ncols + 8 * res,
         "row_offset": inp + 4 * ncols + lst_v0,
         "neighbour": lst_v0 + lst_i,
         "seeds": inp + lst_i + 20 * ncols + 9 * seeds,

@@ -271,14 +271,15 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
 
 /* Profiling.  When enabled, every pass of every later call records HIP
  * events on its stream around each of its DEXEL_NPROF launch groups: column
- * gaps, thin-column erosion, row offset, its replays, single-interval
- * dilation, neighbour intersection, its
+ * gaps, thin-column erosion, chord-extreme dilation test, row offset, its
+ * replays, test against the row offset and gap cut, neighbour
+ * intersection, its
  * replay, extrusion seeds, their replay, y dilation with per-column union,
  * its replay, result scan, compaction copy.
  * dexel_profile_read waits for the recorded events and returns the
  * accumulated milliseconds per group and the number of passes (a dilation or
  * erosion is one pass, open/close two); reset != 0 clears the accumulators. */
-#define DEXEL_NPROF 13
+#define DEXEL_NPROF 14
 dexel_status dexel_profile_enable(dexel_ctx* ctx, int on);
 dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset);
 

@@ -1,6 +1,7 @@
 // Host side of the libdexel C ABI (see include/dexel.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -28,7 +29,7 @@ struct dexel_ctx {
     // Kernel variant: forced (>= 0) or chosen per batch signature by dexel_autotune.
     int forced_variant = -1;
     std::map<uint64_t, int> tuned;
-    // LDS bytes one workgroup may take (bounds the thin-column erosion's tiles)
+    // LDS bytes one workgroup may take (bounds the tiled fast paths' radii)
     int max_lds = 65536;
     // device address of this device's static scratch (dexel_offset_noalloc)
     void* scratch = nullptr;
@@ -328,8 +329,9 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         // passes of radii whose tiles fit the LDS take a tiled fast path:
         // erosions the thin-column filter, dilations the single-interval test
         auto fast_of = [&](int erode) {
-            if ((flags & DEXEL_FLAG_GENERAL) || ii.R > dexel::THIN_RMAX ||
-                dexel::thin_lds_bytes(ii.R, ii.d2max) > ctx->max_lds)
+            const int lds = erode ? dexel::thin_lds_bytes(ii.R, ii.d2max)
+                                  : dexel::solid_lds_bytes(ii.R, ii.d2max);
+            if ((flags & DEXEL_FLAG_GENERAL) || ii.R > dexel::THIN_RMAX || lds > ctx->max_lds)
                 return (int32_t)dexel::FAST_NONE;
             return (int32_t)(erode ? dexel::FAST_THIN : dexel::FAST_SOLID);
         };
@@ -380,24 +382,27 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     base1.push_back(g1);
     base2.push_back(g2);
     // tiles of the shapes with a tiled fast path, numbered in shape order
-    auto tile_bases = [](std::vector<dexel::Shape>& sh, int64_t* ntiles, int32_t* lds) {
+    auto tile_bases = [](std::vector<dexel::Shape>& sh, dexel::Pass* q) {
         int64_t t = 0;
-        int32_t b = 0;
+        int32_t bt = 0, bs = 0;
         for (auto& S : sh) {
             S.tbase = t;
             if (S.fast == dexel::FAST_NONE) continue;
-            t += (int64_t)((S.nx + dexel::THIN_TX - 1) / dexel::THIN_TX) *
-                 ((S.ny + dexel::THIN_TY - 1) / dexel::THIN_TY);
-            const int32_t need = dexel::thin_lds_bytes(S.R, S.d2max);
-            b = need > b ? need : b;
+            const bool thin = S.fast == dexel::FAST_THIN;
+            const int ty = thin ? dexel::THIN_TY : dexel::SOLID_TY;
+            t += (int64_t)((S.nx + dexel::THIN_TX - 1) / dexel::THIN_TX) * ((S.ny + ty - 1) / ty);
+            if (thin) {
+                bt = std::max(bt, (int32_t)dexel::thin_lds_bytes(S.R, S.d2max));
+                q->nthin = 1;
+            } else {
+                bs = std::max(bs, (int32_t)dexel::solid_lds_bytes(S.R, S.d2max));
+                q->nsolid = 1;
+            }
         }
-        *ntiles = t;
-        *lds = b;
+        q->ntiles = t;
+        q->thin_lds = bt;
+        q->solid_lds = bs;
     };
-    int64_t nt1 = 0, nt2 = 0;
-    int32_t lds1 = 0, lds2 = 0;
-    tile_bases(sh1, &nt1, &lds1);
-    tile_bases(sh2, &nt2, &lds2);
 
     auto make_pass = [&](size_t shapes_off, size_t sbase_off, int nsh, int64_t gcols) {
         dexel::Pass q{};
@@ -423,19 +428,8 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
     };
     dexel::Pass p1 = make_pass(L.shapes1, L.sbase1, (int)sh1.size(), g1);
     dexel::Pass p2 = make_pass(L.shapes2, L.sbase2, (int)sh2.size(), g2);
-    auto has = [](const std::vector<dexel::Shape>& sh, int32_t mode) {
-        for (const auto& S : sh)
-            if (S.fast == mode) return (int16_t)1;
-        return (int16_t)0;
-    };
-    p1.ntiles = nt1;
-    p1.fast_lds = lds1;
-    p1.nthin = has(sh1, dexel::FAST_THIN);
-    p1.nsolid = has(sh1, dexel::FAST_SOLID);
-    p2.ntiles = nt2;
-    p2.fast_lds = lds2;
-    p2.nthin = has(sh2, dexel::FAST_THIN);
-    p2.nsolid = has(sh2, dexel::FAST_SOLID);
+    tile_bases(sh1, &p1);
+    tile_bases(sh2, &p2);
     int64_t* zbase = (int64_t*)(w + L.zbase);
 
     HIP_TRY(dexel::launch_init_call(p1.hdr, p1.shape_status, n, s));
@@ -537,7 +531,8 @@ dexel_status dexel_ctx_create(int device, dexel_ctx** ctx) {
     c->scratch = scratch;
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
-        c->max_lds = lds < 65536 ? lds : 65536;
+        c->max_lds = lds;
+    c->max_lds = dexel::prepare_kernels(c->max_lds);
     *ctx = c;
     return DEXEL_OK;
 }

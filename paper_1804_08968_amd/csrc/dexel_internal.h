@@ -27,11 +27,11 @@ static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 // Overflow lists: columns whose per-lane list overflowed in K1, K1b, K2 (seed
 // slot) and K3, replayed one lane per column; and columns deferred as heavy
 // in K2, K1b and K3, or overflowing K1's lane replay, replayed one wave per
-// column (z slabs); and the columns of a single-interval dilation test left
-// to the gap cut.
+// column (z slabs); and the columns the tiled dilation test leaves to the
+// test against V0 (ST_SOLB) and to the gap cut (ST_GAP).
 enum Stage {
     ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3,
-    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, NSTAGE = 9
+    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, ST_SOLB = 9, NSTAGE = 10
 };
 
 // Seed slots per column: the seeds of a column are written at
@@ -73,18 +73,16 @@ struct Shape {
     const int64_t* out_zoff;  // if set, results are written at out_z + *out_zoff
     int64_t out_cap;
     // tiled fast paths: `fast` = FAST_THIN for an erosion pass the thin-column
-    // max / min filter evaluates before the row offset, FAST_SOLID for a
-    // dilation pass whose single-interval columns k_solid_dilate settles after
-    // it; the shape's tiles are tbase .. of the pass.  gen[c] = 1 marks an
-    // output column left to the general kernels, need[c] the general stages
-    // column c must run for them (NEED_* bits).
+    // max / min filter evaluates first, FAST_SOLID for a dilation pass whose
+    // columns the chord-extreme test, the test against V0 and the gap cut
+    // settle; the shape's tiles are tbase .. of the pass.  gen[c] holds GEN_*
+    // bits, need[c] the general stages column c must run (NEED_* bits).
     int32_t fast;
     int32_t pad1;
     int64_t tbase;
     uint8_t* gen;
     uint8_t* need;
-    float4* lu;               // FAST_SOLID, columns left to the gap cut: smallest chord start and
-                              // largest chord end, and where its gaps start and end (see k_solid_dilate)
+    float4* lu;               // FAST_SOLID, unsettled columns: chord extremes (see k_solid_dilate)
     int32_t out_is_intermediate;
     int32_t last_pass;        // write the caller's nseg_out / status after this pass
     int64_t* out_nseg;
@@ -99,8 +97,10 @@ struct Pass {
     int32_t pad;
     int64_t gcols;            // padded global column count of the pass
     int64_t ntiles;           // tiles of the tiled fast paths over the pass's shapes that have one
-    int32_t fast_lds;         // dynamic LDS bytes of the tiled fast paths (largest R of their shapes)
-    int16_t nthin, nsolid;    // shapes of the pass with each fast path
+    int32_t thin_lds;         // dynamic LDS bytes of k_thin_erode (largest R of its shapes)
+    int32_t solid_lds;        // dynamic LDS bytes of k_solid_dilate (largest R of its shapes)
+    int16_t nthin, nsolid;    // the pass has shapes with each fast path (0 / 1)
+    int32_t k1_round;         // k_row_offset's launch: 1 before the dilation tests' V0 stage, 2 after
     WsHeader* hdr;
     int32_t* shape_status;    // [items] per-item status (output capacity)
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
@@ -145,28 +145,41 @@ hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hi
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
 // Profiled intervals of one pass, one per launch group: column gaps,
-// thin-column erosion, row offset, its replays, single-interval dilation,
+// thin-column erosion, chord-extreme dilation test, row offset, its replays,
+// test against V0 and gap cut (with the row offsets they still need),
 // neighbour intersection, its replays, seeds, their replays, y dilation +
 // union, its replays, result scan, compaction.
-constexpr int NPROF = 13;
+constexpr int NPROF = 14;
 enum FastPath { FAST_NONE = 0, FAST_THIN = 1, FAST_SOLID = 2 };
-// Tiled fast paths: tile of THIN_TX x THIN_TY output columns, radii up to
-// THIN_RMAX; LDS bytes a tile stages at integer radius R (one float2 per
-// staged column, the half-width table and the stencil's row widths).
+// Tiled fast paths: tiles of THIN_TX x THIN_TY (thin erosion) or
+// THIN_TX x SOLID_TY (dilation test) output columns, radii up to THIN_RMAX.
+// LDS bytes a tile stages at integer radius R: per staged column one float2
+// (thin) or two float2 and a float (dilation), then the half-width table and
+// the stencil's row widths.
 constexpr int THIN_TX = 64;
 constexpr int THIN_TY = 16;
+constexpr int SOLID_TY = 8;
 constexpr int THIN_RMAX = 32;
 inline int thin_lds_bytes(int R, int d2max) {
     return (THIN_TX + 2 * R) * (THIN_TY + 2 * R) * 8 + 4 * (d2max + 1) + 4 * (R + 1);
 }
-// need[] bits: stages of the general kernels a column of a thin shape runs.
+inline int solid_lds_bytes(int R, int d2max) {
+    return (THIN_TX + 2 * R) * (SOLID_TY + 2 * R) * 20 + 4 * (d2max + 1) + 4 * (R + 1);
+}
+// need[] bits: stages of the general kernels a column runs.
 constexpr int NEED_UNION = 1;   // y union (the column is general itself)
 constexpr int NEED_SEEDS = 2;   // neighbour intersection and seeds (a general column within R rows)
 constexpr int NEED_ROW = 4;     // row offset (a general column within 2R rows)
+// gen[] bits.
+constexpr int GEN_V0 = 1;       // FAST_SOLID: the column's V0 is evaluated before the general stages
+constexpr int GEN_GENERAL = 2;  // the column is left to the general kernels
 // ev: nullptr, or NPROF + 1 events recorded on `s` at the stage boundaries.
 // variant: kernel variant (per-lane LDS list capacities), 0..NVARIANT-1.
 constexpr int NVARIANT = 4;
 hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant);
+// Dynamic-LDS limit of the tiled kernels (once per context): sets the largest
+// accepted value up to max_lds and returns it (65536 at least).
+int prepare_kernels(int max_lds);
 hipError_t launch_finish(const Pass& p, int64_t* zbase, hipStream_t s);
 
 // Per-column Boolean operation of two grids (dexel_csg).  Workspace: header,

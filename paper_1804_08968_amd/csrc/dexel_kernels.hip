@@ -478,30 +478,54 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
             f = make_float2(ec4.x, ec4.y);
             l = make_float2(ec4.z, ec4.w);
         }
+        // The runs are found and inserted with the items loaded four at a
+        // time (independent loads, clamped to the column), so a visit waits
+        // for memory about once per run instead of once per item.
         const float2 u = U.get(0);
         int k0 = 0, k1 = cnt;
         if (f.x - h < u.x) {
             k0 = 1;
-            while (k0 < cnt && col_item<E>(P.z, bc, m, k0).x - h < u.x) ++k0;
+            for (bool more = true; more && k0 < cnt;) {
+                float2 q[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) q[i] = col_item<E>(P.z, bc, m, min(k0 + i, cnt - 1));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (more && k0 < cnt && q[i].x - h < u.x) ++k0;
+                    else more = false;
+                }
+            }
         }
         if (k1 > k0 && l.y + h > u.y) {
             k1 = cnt - 1;
-            while (k1 > k0 && col_item<E>(P.z, bc, m, k1 - 1).y + h > u.y) --k1;
+            for (bool more = true; more && k1 > k0;) {
+                float2 q[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) q[i] = col_item<E>(P.z, bc, m, max(k1 - 1 - i, 0));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (more && k1 > k0 && q[i].y + h > u.y) --k1;
+                    else more = false;
+                }
+            }
         }
-        // candidates: items [0, k0) then [k1, cnt); the next item is loaded
-        // before the current one is inserted
+        // candidates: items [0, k0) then [k1, cnt), inserted in that order
         const int nc = k0 + (cnt - k1);
         int hint = 0;
-        float2 nxt = k0 > 0 ? f : l;
-        if (k0 == 0 && k1 < cnt - 1) nxt = col_item<E>(P.z, bc, m, k1);
-        for (int j = 0; j < nc; ++j) {
-            const float2 iv = nxt;
-            if (j + 1 < nc) {
-                const int k = j + 1 < k0 ? j + 1 : k1 + (j + 1 - k0);
-                nxt = col_item<E>(P.z, bc, m, k);
+        for (int j = 0; j < nc; j += 4) {
+            float2 q[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int jj = min(j + i, nc - 1);
+                q[i] = col_item<E>(P.z, bc, m, jj < k0 ? jj : k1 + (jj - k0));
             }
-            n = lv_insert_fwd(U, n, iv.x - h, iv.y + h, &hint);
-            if (n < 0) return -1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (j + i < nc) {
+                    n = lv_insert_fwd(U, n, q[i].x - h, q[i].y + h, &hint);
+                    if (n < 0) return -1;
+                }
+            }
         }
     }
     return n;
@@ -1453,11 +1477,19 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
 }
 
 // Must column c of shape S run the general stage `bit`?  Only shapes with a
-// tiled fast path skip stages; a FAST_SOLID shape decides after the row
-// offset, which therefore runs on all its columns.
-__device__ __forceinline__ bool needs(const Shape& S, int64_t c, int bit) {
-    if (S.fast == FAST_NONE || (S.fast == FAST_SOLID && bit == NEED_ROW)) return true;
-    return (gld(&S.need[c]) & bit) != 0;
+// tiled fast path skip stages.  The row offset's main kernel runs twice: in
+// its first round on every column of the shapes without a fast path and on
+// the needed ones of FAST_THIN shapes (the columns the FAST_SOLID test did
+// not settle reach the row offset through its lane replay's list); in the
+// second on the FAST_SOLID columns whose V0 the general stages still need.
+__device__ __forceinline__ bool needs(const Pass& Q, const Shape& S, int64_t c, int bit) {
+    if (bit == NEED_ROW) {
+        if (Q.k1_round == 2)
+            return S.fast == FAST_SOLID && (gld(&S.need[c]) & NEED_ROW) && !(gld(&S.gen[c]) & GEN_V0);
+        if (S.fast == FAST_NONE) return true;
+        return S.fast == FAST_THIN && (gld(&S.need[c]) & NEED_ROW);
+    }
+    return S.fast == FAST_NONE || (gld(&S.need[c]) & bit);
 }
 
 // ---------------------------------------------------------------------------
@@ -1541,7 +1573,7 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
-    bool valid = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_ROW);
+    bool valid = pl.valid && needs(Q, Q.shapes[pl.s], pl.c, NEED_ROW);
     if (!__any(valid)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     LdsList U{&lds[threadIdx.x], CAP};
@@ -1642,7 +1674,7 @@ __global__ void __launch_bounds__(WG) k_neighbour(Pass Q) {
     __shared__ float2 lds[2 * CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
-    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_SEEDS);
+    const bool live = pl.valid && needs(Q, Q.shapes[pl.s], pl.c, NEED_SEEDS);
     if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     // a column whose own V0 is fragmented (its neighbours' are too, as a
@@ -1776,7 +1808,7 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     __shared__ float2 lds[CAP * WG];
     if (Q.hdr->abort) return;
     const Place pl = place_block(Q);
-    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_SEEDS);
+    const bool live = pl.valid && needs(Q, Q.shapes[pl.s], pl.c, NEED_SEEDS);
     if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     int np = 0;
@@ -1938,7 +1970,7 @@ __global__ void __launch_bounds__(WG) k_union(Pass Q) {
     const Place pl = place_block(Q);
     if (!pl.valid) Q.cntC_g[pl.g0 + threadIdx.x] = 0;  // padding column
     // columns a tiled fast path finished are skipped
-    const bool live = pl.valid && needs(Q.shapes[pl.s], pl.c, NEED_UNION);
+    const bool live = pl.valid && needs(Q, Q.shapes[pl.s], pl.c, NEED_UNION);
     if (!__any(live)) return;
     const OpParams P = make_op(Q, Q.shapes[pl.s]);
     // a column whose V0 is fragmented goes straight to the replay
@@ -2271,7 +2303,7 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
         }
         if (!live) continue;
         const int64_t c = (int64_t)y * P.nx + x;
-        gst(&S.gen[c], (uint8_t)(thk ? 1 : 0));
+        gst(&S.gen[c], (uint8_t)(thk ? GEN_GENERAL : 0));
         if (!done) continue;
         gst(&P.offC[c], (int64_t)(base + pre));
         gst(&P.cntC[c], ok ? outn : 0);
@@ -2297,24 +2329,34 @@ __device__ __forceinline__ void stage_stencil(const OpParams& P, float* Hs, int*
 // Every chord of an output column's stencil lies in [L, U], with
 // L = min fl(af - H[d2]) and U = max fl(bl + H[d2]) over the stencil columns
 // (af, bl: a column's first start and last end), and both ends belong to the
-// union.  V0(c) = [L0 .. U0], the union of the chords of the column's own
-// row, is part of it too.  A chord [L, e] with e >= L0 exists iff the
-// smallest start of the chords reaching L0 (first items suffice: a column's
-// first chord has both its smallest start and smallest end) equals L; then
-// [L, L0] is covered, and likewise [U0, U] if the largest end of the chords
-// starting at or below U0 equals U.  The union is then [L, U] minus the
-// points of the open gaps of V0, and of (L, L0) or (U0, U) where not
-// covered, that no chord of another row covers.  k_solid_dilate evaluates
-// these filters on the tiles of k_thin_erode, staging each column's first
-// item, then its last item, in LDS: a column with no such gap is settled as
-// [L, U]; one with at most GC_CAP goes to the gap cut (k_gap_cut), which
-// applies the chords of the other rows to its gaps; every other column is
-// left to the general kernels.
+// union.  Three chords chain into [L, U] in most columns of a solid shape:
+// [L, E1], where E1 is the largest end of the chords starting at L (each a
+// column's first chord: it has the column's smallest start and smallest
+// end); [S1, U], likewise at the top with last chords; and the hull [A, B]
+// of a column whose gaps are all within 2H[d2] (its chords chain into
+// [af - h, bl + h]).  If E1 >= S1, or some such hull has A <= E1 and
+// B >= S1, the column's dilation is exactly [L, U] and nothing else of it is
+// evaluated.  L, U, E1 and S1 are taken over the whole stencil (E1 and S1
+// in a second sweep once L and U are known), the hulls only over its inner
+// part (d2 <= d2max / 4), where the columns whose gaps are short enough for
+// their distance are as a rule: a hull missed there only sends the column on
+// to the exact evaluation.
+// k_solid_dilate evaluates these filters on LDS-staged tiles of
+// THIN_TX x SOLID_TY output columns ((af, bl), (bf, al) and half the
+// largest-gap bound of each neighbourhood column); every other column goes
+// to the row offset's lane replay (its V0 is needed) and then to k_solid_b.
+//
+// k_solid_b tests a column against V0(c) = [L0 .. U0], the union of the
+// chords of its own row: the union is [L, U] minus the points of the open
+// gaps of [L, E1] U V0 U [S1, U] inside [L, U] that no chord of another row
+// covers.  A column without such a gap is settled; one with at most GC_CAP
+// goes to the gap cut (k_gap_cut), which applies the chords of the other
+// rows to them; every other column is left to the general kernels.
 constexpr int GC_CAP = 4;      // open gaps the gap cut tracks per column
 constexpr int GC_BUDGET = 160; // stencil columns meeting a gap it visits before giving up
 
 __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
-    extern __shared__ float2 thin_lds[];
+    extern __shared__ float2 solid_lds[];
     if (Q.hdr->abort) return;
     const int64_t t = map_block(Q.ntiles);
     int lo = 0, hi = Q.nshapes;
@@ -2328,103 +2370,91 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
     const int R = P.R;
     const int ntx = (P.nx + THIN_TX - 1) / THIN_TX;
     const int64_t tl = t - S.tbase;
-    const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * THIN_TY;
-    const int SW = THIN_TX + 2 * R, SH = THIN_TY + 2 * R;
-    float2* st = thin_lds;
-    float* Hs = (float*)(st + SW * SH);
+    const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * SOLID_TY;
+    const int SW = THIN_TX + 2 * R, SH = SOLID_TY + 2 * R;
+    float2* sab = solid_lds;                 // (af, bl)
+    float2* sba = sab + SW * SH;             // (bf, al)
+    float* sg = (float*)(sba + SW * SH);     // half the largest-gap bound
+    float* Hs = sg + SW * SH;
     int* wd = (int*)(Hs + P.d2max + 1);
     stage_stencil(P, Hs, wd);
+    // empty and off-grid columns stage (+inf, -inf), (+inf, -inf) and -1:
+    // they change no filter and are never a hull
+    for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
+        const int sy = i / SW, sx = i - sy * SW;
+        const int xx = x0 - R + sx, yy = y0 - R + sy;
+        float2 ab = make_float2(DX_INF, -DX_INF), ba = make_float2(DX_INF, -DX_INF);
+        float gp = -1.f;
+        if (xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
+            const int64_t c = (int64_t)yy * P.nx + xx;
+            gp = gld(&P.gap[c]);
+            if (gp >= 0.f) {
+                const float4 e4 = gld(&P.ends[c]);
+                ab = make_float2(e4.x, e4.w);
+                ba = make_float2(e4.y, e4.z);
+                gp *= 0.5f;
+            }
+        }
+        sab[i] = ab;
+        sba[i] = ba;
+        sg[i] = gp;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x = x0 + lane;
-    constexpr int KR = THIN_TY / 4;  // output rows per wave
-    // V0 of this lane's output columns: count, first start, last end
-    int n0[KR];
-    float L0[KR], U0[KR];
-#pragma unroll
-    for (int k = 0; k < KR; ++k) {
-        const int y = y0 + wv + 4 * k;
-        n0[k] = -1;
-        L0[k] = DX_INF;
-        U0[k] = -DX_INF;
-        if (x < P.nx && y < P.ny) {
-            const int64_t c = (int64_t)y * P.nx + x;
-            n0[k] = gld(&P.cntA[c]);
-            if (n0[k] > 0) {
-                const float2* V = P.A + gld(&P.offA[c]);
-                L0[k] = gld(&V[0]).x;
-                U0[k] = gld(&V[n0[k] - 1]).y;
+    const int d2in = P.d2max / 4;
+    for (int k = 0; k < SOLID_TY / 4; ++k) {
+        const int ly = wv + 4 * k;
+        const int y = y0 + ly;
+        if (y >= P.ny) break;  // wave-uniform
+        const int ci = (ly + R) * SW + lane + R;
+        // L and U over the whole stencil
+        float L = DX_INF, U = -DX_INF;
+        for (int dy = -R; dy <= R; ++dy) {
+            const int w = wd[dy < 0 ? -dy : dy];
+            const int ri = ci + dy * SW;
+            const float* hr = Hs + dy * dy;
+            for (int dx = -w; dx <= w; ++dx) {
+                const float2 v = sab[ri + dx];
+                const float hh = hr[dx * dx];
+                L = fminf(L, v.x - hh);
+                U = fmaxf(U, v.y + hh);
             }
         }
-    }
-    float L[KR], Lg[KR], U[KR], Ug[KR];
-    for (int half = 0; half < 2; ++half) {
-        // half 0: first items (af, bf), neutral (+inf, -inf); half 1: last
-        // items (al, bl), neutral (+inf, -inf) too
-        if (half) __syncthreads();  // half 0 has read the staging buffer
-        for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
-            const int sy = i / SW, sx = i - sy * SW;
-            const int xx = x0 - R + sx, yy = y0 - R + sy;
-            float2 v = make_float2(DX_INF, -DX_INF);
-            if (xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
-                const int64_t c = (int64_t)yy * P.nx + xx;
-                if (gld(&P.gap[c]) >= 0.f) {
-                    const float4 e4 = gld(&P.ends[c]);
-                    v = half ? make_float2(e4.z, e4.w) : make_float2(e4.x, e4.y);
-                }
+        // E1 and S1 over the whole stencil, then a connecting hull in its
+        // inner part
+        float E1 = -DX_INF, S1 = DX_INF;
+        for (int dy = -R; dy <= R; ++dy) {
+            const int w = wd[dy < 0 ? -dy : dy];
+            const int ri = ci + dy * SW;
+            const float* hr = Hs + dy * dy;
+            for (int dx = -w; dx <= w; ++dx) {
+                const float2 v = sab[ri + dx], u = sba[ri + dx];
+                const float hh = hr[dx * dx];
+                E1 = fmaxf(E1, v.x - hh == L ? u.x + hh : -DX_INF);
+                S1 = fminf(S1, v.y + hh == U ? u.y - hh : DX_INF);
             }
-            st[i] = v;
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < KR; ++k) {
-            const int ly = wv + 4 * k;
-            if (y0 + ly >= P.ny) break;  // wave-uniform
-            const float2* ctr = st + (ly + R) * SW + lane + R;
-            // half 0: m = min start, g = min start of the chords ending at or above L0
-            // half 1: m = max end, g = max end of the chords starting at or below U0
-            float m = half ? -DX_INF : DX_INF, g = m;
-            const float tgt = half ? U0[k] : L0[k];
+        bool hull = false;
+        if (E1 < S1) {
             for (int dy = -R; dy <= R; ++dy) {
-                const int w = wd[dy < 0 ? -dy : dy];
-                const float2* row = ctr + dy * SW;
+                if (dy * dy > d2in) continue;
+                int w = wd[dy < 0 ? -dy : dy];
+                while (w * w + dy * dy > d2in) --w;
+                const int ri = ci + dy * SW;
                 const float* hr = Hs + dy * dy;
                 for (int dx = -w; dx <= w; ++dx) {
-                    const float2 v = row[dx];
+                    const float2 v = sab[ri + dx];
                     const float hh = hr[dx * dx];
-                    const float a = v.x - hh, b = v.y + hh;
-                    if (half == 0) {
-                        m = fminf(m, a);
-                        g = fminf(g, b >= tgt ? a : DX_INF);
-                    } else {
-                        m = fmaxf(m, b);
-                        g = fmaxf(g, a <= tgt ? b : -DX_INF);
-                    }
+                    hull = hull || (sg[ri + dx] <= hh && v.x - hh <= E1 && v.y + hh >= S1);
                 }
             }
-            if (half == 0) {
-                L[k] = m;
-                Lg[k] = g;
-            } else {
-                U[k] = m;
-                Ug[k] = g;
-            }
         }
-    }
-#pragma unroll
-    for (int k = 0; k < KR; ++k) {
-        const int y = y0 + wv + 4 * k;
-        if (y >= P.ny) break;  // wave-uniform
         const bool live = x < P.nx;
         const int64_t c = (int64_t)y * P.nx + x;
-        // open gaps left: V0's own, and the end pieces not covered by one chord
-        int ng = 0;
-        if (live && L[k] <= U[k]) {
-            if (n0[k] == 0) ng = L[k] < U[k] ? 1 : 0;
-            else ng = (n0[k] - 1) + (Lg[k] != L[k] ? 1 : 0) + (Ug[k] != U[k] ? 1 : 0);
-        }
-        const bool done = live && (L[k] > U[k] || ng == 0);
-        const bool cut = live && !done && ng <= GC_CAP;
-        const int outn = (done && L[k] <= U[k]) ? 1 : 0;
+        const bool empty = L > U;
+        const bool done = live && (empty || E1 >= S1 || hull);
+        const int outn = (done && !empty) ? 1 : 0;
         int tot;
         const int pre = wave_excl_scan(outn, &tot);
         unsigned long long base = 0;
@@ -2437,18 +2467,81 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
             set_error(P.hdr, DEXEL_ERR_WORKSPACE);
         }
         if (!live) continue;
-        gst(&S.gen[c], (uint8_t)(done || cut ? 0 : 1));
-        if (cut) {
-            // (L, U) and the range the gaps are taken from: an end already
-            // covered by one chord starts it at V0's end instead
-            gst(&S.lu[c], make_float4(L[k], U[k], Lg[k] == L[k] && n0[k] > 0 ? L0[k] : L[k],
-                                      Ug[k] == U[k] && n0[k] > 0 ? U0[k] : U[k]));
-            push_overflow(Q, ST_GAP, S.gbase + c);
+        gst(&S.gen[c], (uint8_t)(done ? 0 : GEN_V0));
+        if (!done) {
+            // (E1 = -inf, S1 = +inf if no inner chord reaches L, U: the test
+            // against V0 then takes the whole of (L, L0) and (U0, U) as gaps)
+            gst(&S.lu[c], make_float4(L, E1 > L ? E1 : L, S1 < U ? S1 : U, U));
+            push_overflow(Q, ST_K1, S.gbase + c);
+            push_overflow(Q, ST_SOLB, S.gbase + c);
+            continue;
         }
-        if (!done) continue;
         gst(&P.offC[c], (int64_t)(base + pre));
         gst(&P.cntC[c], ok ? outn : 0);
-        if (ok && outn) gst(&P.C[base + pre], make_float2(L[k], U[k]));
+        if (ok && outn) gst(&P.C[base + pre], make_float2(L, U));
+    }
+}
+
+// The columns k_solid_dilate left, now with V0, one lane each (see above).
+__global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_SOLB];
+    if ((int64_t)blockIdx.x * WG >= cnt) return;
+    const int i = blockIdx.x * WG + threadIdx.x;
+    const bool live = i < cnt;
+    const int64_t g = Q.ovf[(int64_t)ST_SOLB * Q.gcols + (live ? i : 0)];
+    const int s = find_shape(Q, g);
+    const Shape& S = Q.shapes[s];
+    const OpParams P = make_op(Q, S);
+    const int64_t c = g - Q.sbase[s];
+    const float4 lu = gld(&S.lu[c]);  // (L, E1, S1, U)
+    // gaps of [L, E1] U V0 U [S1, U] inside [L, U]; more than GC_CAP: give up
+    int ng = 0;
+    if (live) {
+        const int n0 = gld(&P.cntA[c]);
+        const float2* V = P.A + gld(&P.offA[c]);
+        float prev = lu.y;
+        for (int j = 0; j < n0 && ng <= GC_CAP; ++j) {
+            const float2 v = gld(&V[j]);
+            if (v.x > prev) ++ng;
+            prev = fmaxf(prev, v.y);
+        }
+        if (lu.z > prev) ++ng;
+    }
+    const bool done = live && ng == 0;
+    const bool cut = live && ng > 0 && ng <= GC_CAP;
+    const int outn = done ? 1 : 0;
+    int tot;
+    const int pre = wave_excl_scan(outn, &tot);
+    unsigned long long base = 0;
+    if (threadIdx.x == 0 && tot > 0) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+    base = __shfl(base, 0, 64);
+    const unsigned long long end = base + (unsigned long long)tot;
+    const bool ok = end <= (unsigned long long)P.cap;
+    if (!ok && threadIdx.x == 0) {
+        note_need(P.hdr, end);
+        set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+    }
+    if (!live) return;
+    if (cut) {
+        // the gap cut reads (L, U) and the range its gaps are taken from
+        gst(&S.lu[c], make_float4(lu.x, lu.w, lu.y, lu.z));
+        push_overflow(Q, ST_GAP, g);
+        return;
+    }
+    if (!done) {
+        gst(&S.gen[c], (uint8_t)(GEN_V0 | GEN_GENERAL));
+        return;
+    }
+    gst(&P.offC[c], (int64_t)(base + pre));
+    gst(&P.cntC[c], ok ? 1 : 0);
+    if (ok) gst(&P.C[base + pre], make_float2(lu.x, lu.w));
+}
+
+__global__ void k_reset_k1(Pass Q) {
+    if (threadIdx.x == 0) {
+        Q.hdr->novf[ST_K1] = 0;
+        Q.hdr->novf[ST_K1H] = 0;
     }
 }
 
@@ -2538,9 +2631,9 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
     return ng;
 }
 
-// The columns k_solid_dilate left to the gap cut, one lane each: build the
-// gaps of V0 inside [L, U], cut them, and write [L, U] minus what is left; a
-// column the cut gives up on is marked general.
+// The columns k_solid_b left to the gap cut, one lane each: build the gaps
+// of V0 inside [lu.z, lu.w], cut them, and write [L, U] = [lu.x, lu.y] minus
+// what is left; a column the cut gives up on is marked general.
 __global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
     __shared__ float2 lds[2 * GC_CAP * WG];
     if (Q.hdr->abort) return;
@@ -2563,7 +2656,7 @@ __global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
         // the gaps of V0 inside [lu.z, lu.w], in order
         const int n0 = gld(&P.cntA[c]);
         const float2* V = P.A + gld(&P.offA[c]);
-        // (at most GC_CAP of them, as k_solid_dilate counted)
+        // (at most GC_CAP of them, as k_solid_b counted)
         float prev = lu.z;
         for (int j = 0; j < n0 && ng >= 0; ++j) {
             const float2 v = gld(&V[j]);
@@ -2592,7 +2685,7 @@ __global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
     }
     if (!live) return;
     if (!ok1) {
-        gst(&S.gen[c], (uint8_t)1);
+        gst(&S.gen[c], (uint8_t)(GEN_V0 | GEN_GENERAL));
         return;
     }
     gst(&P.offC[c], (int64_t)(base + pre));
@@ -2619,11 +2712,11 @@ __global__ void __launch_bounds__(WG) k_fast_spread(Pass Q, int mode) {
     const Shape& S = Q.shapes[pl.s];
     if (S.fast != mode || !pl.valid) return;
     const int y = (int)(pl.c / S.nx), x = (int)(pl.c - (int64_t)y * S.nx);
-    int bits = gld(&S.gen[pl.c]) ? NEED_UNION | NEED_SEEDS | NEED_ROW : 0;
+    int bits = (gld(&S.gen[pl.c]) & GEN_GENERAL) ? NEED_UNION | NEED_SEEDS | NEED_ROW : 0;
     for (int d = 1; d <= 2 * S.R && !(bits & NEED_SEEDS) && !(bits && d > S.R); ++d) {
         const bool lo_in = y - d >= 0, hi_in = y + d < S.ny;
-        const bool g = (lo_in && gld(&S.gen[pl.c - (int64_t)d * S.nx])) ||
-                       (hi_in && gld(&S.gen[pl.c + (int64_t)d * S.nx]));
+        const bool g = (lo_in && (gld(&S.gen[pl.c - (int64_t)d * S.nx]) & GEN_GENERAL)) ||
+                       (hi_in && (gld(&S.gen[pl.c + (int64_t)d * S.nx]) & GEN_GENERAL));
         if (g) bits |= d <= S.R ? NEED_SEEDS | NEED_ROW : NEED_ROW;
     }
     gst(&S.need[pl.c], (uint8_t)bits);
@@ -3407,43 +3500,69 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
     if (p.ntiles > 0 && p.nthin > 0) {
-        hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.fast_lds, s, p);
+        hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.thin_lds, s, p);
         hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_THIN);
     }
     DX_MARK(2);
-    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p);
+    if (p.ntiles > 0 && p.nsolid > 0)
+        hipLaunchKernelGGL(k_solid_dilate, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.solid_lds, s, p);
     DX_MARK(3);
+    Pass p1 = p;
+    p1.k1_round = 1;
+    hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p1);
+    DX_MARK(4);
     hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_row_offset_heavy, gf, b, 0, s, p);
-    DX_MARK(4);
+    DX_MARK(5);
     if (p.ntiles > 0 && p.nsolid > 0) {
-        hipLaunchKernelGGL(k_solid_dilate, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.fast_lds, s, p);
+        hipLaunchKernelGGL(k_solid_b, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
         hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_SOLID);
+        // the row offsets the general columns' stages still need
+        hipLaunchKernelGGL(k_reset_k1, dim3(1), dim3(64), 0, s, p);
+        Pass p2 = p;
+        p2.k1_round = 2;
+        hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p2);
+        hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
+        hipLaunchKernelGGL(k_row_offset_heavy, gf, b, 0, s, p);
     }
-    DX_MARK(5);
-    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
     DX_MARK(6);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    DX_MARK(7);
     hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
-    DX_MARK(7);
-    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(8);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
+    DX_MARK(9);
     hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
     hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
-    DX_MARK(9);
-    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(10);
+    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
+    DX_MARK(11);
     hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
-    DX_MARK(11);
+    DX_MARK(12);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
-    DX_MARK(12);
-    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
     DX_MARK(13);
+    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
+    DX_MARK(14);
 #undef DX_MARK
     return hipGetLastError();
+}
+
+int prepare_kernels(int max_lds) {
+    // the largest dynamic LDS both tiled kernels accept, from the device's
+    // limit down; a refused setting is cleared from the runtime's error state
+    for (int b = max_lds; b > 65536; b -= 16384) {
+        if (hipFuncSetAttribute((const void*)k_thin_erode, hipFuncAttributeMaxDynamicSharedMemorySize, b) ==
+                hipSuccess &&
+            hipFuncSetAttribute((const void*)k_solid_dilate, hipFuncAttributeMaxDynamicSharedMemorySize, b) ==
+                hipSuccess)
+            return b;
+        (void)hipGetLastError();
+    }
+    return 65536;
 }
 
 hipError_t launch_pass(const Pass& p, hipStream_t s, hipEvent_t* ev, int variant) {
