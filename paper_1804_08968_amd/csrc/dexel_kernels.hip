@@ -2209,6 +2209,47 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
 // evaluate for it (need[]).
 constexpr int THIN_T = 256;
 
+// min / max by comparison: the staged values hold no NaN that matters (the
+// thin filter's NaN markers only reach columns whose result is discarded), so
+// IEEE minNum / maxNum, which also quiet the operands, are not needed.
+__device__ __forceinline__ float mn(float a, float b) { return a < b ? a : b; }
+__device__ __forceinline__ float mx(float a, float b) { return a > b ? a : b; }
+
+// One stencil row of the tiled filters: f(v, hh) for dx = -w .. w with
+// v = row[dx] and hh = hr[dx * dx], the LDS loads of four points issued
+// together.
+template <class T, class F>
+__device__ __forceinline__ void sweep_row(const T* row, const float* hr, int w, F f) {
+    int dx = -w;
+    for (; dx + 3 <= w; dx += 4) {
+        const T v0 = row[dx], v1 = row[dx + 1], v2 = row[dx + 2], v3 = row[dx + 3];
+        const float h0 = hr[dx * dx], h1 = hr[(dx + 1) * (dx + 1)];
+        const float h2 = hr[(dx + 2) * (dx + 2)], h3 = hr[(dx + 3) * (dx + 3)];
+        f(v0, h0);
+        f(v1, h1);
+        f(v2, h2);
+        f(v3, h3);
+    }
+    for (; dx <= w; ++dx) f(row[dx], hr[dx * dx]);
+}
+
+// The same over two staged arrays: f(v, u, hh), v = ra[dx], u = rb[dx].
+template <class T, class F>
+__device__ __forceinline__ void sweep_row2(const T* ra, const T* rb, const float* hr, int w, F f) {
+    int dx = -w;
+    for (; dx + 3 <= w; dx += 4) {
+        const T v0 = ra[dx], v1 = ra[dx + 1], v2 = ra[dx + 2], v3 = ra[dx + 3];
+        const T u0 = rb[dx], u1 = rb[dx + 1], u2 = rb[dx + 2], u3 = rb[dx + 3];
+        const float h0 = hr[dx * dx], h1 = hr[(dx + 1) * (dx + 1)];
+        const float h2 = hr[(dx + 2) * (dx + 2)], h3 = hr[(dx + 3) * (dx + 3)];
+        f(v0, u0, h0);
+        f(v1, u1, h1);
+        f(v2, u2, h2);
+        f(v3, u3, h3);
+    }
+    for (; dx <= w; ++dx) f(ra[dx], rb[dx], hr[dx * dx]);
+}
+
 __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
     extern __shared__ float2 thin_lds[];
     if (Q.hdr->abort) return;
@@ -2272,20 +2313,16 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
             const float2* row = ctr + dy * SW;
             const float* hr = Hs + dy * dy;
             if (any_thick) {
-                for (int dx = -w; dx <= w; ++dx) {
-                    const float2 v = row[dx];
-                    const float hh = hr[dx * dx];
+                sweep_row(row, hr, w, [&](float2 v, float hh) {
                     thk |= v.x != v.x;
-                    MA = fmaxf(MA, v.x + hh);
-                    MB = fminf(MB, v.y - hh);
-                }
+                    MA = mx(MA, v.x + hh);
+                    MB = mn(MB, v.y - hh);
+                });
             } else {
-                for (int dx = -w; dx <= w; ++dx) {
-                    const float2 v = row[dx];
-                    const float hh = hr[dx * dx];
-                    MA = fmaxf(MA, v.x + hh);
-                    MB = fminf(MB, v.y - hh);
-                }
+                sweep_row(row, hr, w, [&](float2 v, float hh) {
+                    MA = mx(MA, v.x + hh);
+                    MB = mn(MB, v.y - hh);
+                });
             }
         }
         const bool done = live && !thk;
@@ -2412,14 +2449,11 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         float L = DX_INF, U = -DX_INF;
         for (int dy = -R; dy <= R; ++dy) {
             const int w = wd[dy < 0 ? -dy : dy];
-            const int ri = ci + dy * SW;
             const float* hr = Hs + dy * dy;
-            for (int dx = -w; dx <= w; ++dx) {
-                const float2 v = sab[ri + dx];
-                const float hh = hr[dx * dx];
-                L = fminf(L, v.x - hh);
-                U = fmaxf(U, v.y + hh);
-            }
+            sweep_row(sab + ci + dy * SW, hr, w, [&](float2 v, float hh) {
+                L = mn(L, v.x - hh);
+                U = mx(U, v.y + hh);
+            });
         }
         // E1 and S1 over the whole stencil, then a connecting hull in its
         // inner part
@@ -2428,12 +2462,10 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
             const int w = wd[dy < 0 ? -dy : dy];
             const int ri = ci + dy * SW;
             const float* hr = Hs + dy * dy;
-            for (int dx = -w; dx <= w; ++dx) {
-                const float2 v = sab[ri + dx], u = sba[ri + dx];
-                const float hh = hr[dx * dx];
-                E1 = fmaxf(E1, v.x - hh == L ? u.x + hh : -DX_INF);
-                S1 = fminf(S1, v.y + hh == U ? u.y - hh : DX_INF);
-            }
+            sweep_row2(sab + ri, sba + ri, hr, w, [&](float2 v, float2 u, float hh) {
+                E1 = mx(E1, v.x - hh == L ? u.x + hh : -DX_INF);
+                S1 = mn(S1, v.y + hh == U ? u.y - hh : DX_INF);
+            });
         }
         bool hull = false;
         if (E1 < S1) {
