@@ -125,6 +125,7 @@ def kernel_bytes(stage, ncols, n_in, st):
     lst_i = 12 * ncols + 8 * iv
     return {
         "column_gaps": inp + 4 * ncols,
+        "direct": inp + 20 * ncols + 12 * ncols + 8 * res,
         "thin_erosion": inp + ncols + 12 * ncols + 8 * res,
         "chord_extremes": 20 * ncols + ncols + 12 * ncols + 8 * res,
         "row_offset": inp + 4 * ncols + lst_v0,
@@ -931,8 +932,25 @@ def run_serving(args, dx, torch):
     # warm the library (LUTs, kernel code) and measure the plain service rate
     serve.Server(eng, pool, mode="plain").run(make(4, None, 99))
     sat_reqs = make(args.serve_requests, None, 2)  # the same mix as the loaded runs
-    sat = serve.summarize(serve.Server(eng, pool, mode="plain").run(sat_reqs))
+    sat_done = serve.Server(eng, pool, mode="plain").run(sat_reqs)
+    sat = serve.summarize(sat_done)
     print(f"[bench] saturation run {sat}", file=sys.stderr, flush=True)
+    # service time of each request of the plain run (one request on the GPU at
+    # a time, back to back): which requests take the time
+    kinds = ["soup" if i % 2 == 0 else "gyroid" for i in range(len(pool))]
+    prev, svc = 0.0, []
+    by_id = {q.id: q for q in sat_reqs}
+    for d in sorted(sat_done, key=lambda d: d.done):
+        q = by_id[d.id]
+        begin = max(prev, d.start)
+        g = pool[q.shape]
+        svc.append({"id": q.id, "op": q.op, "r": round(q.r, 2), "chain": q.chain,
+                    "shape": f"{kinds[q.shape]} {g.nx}^2", "nseg_in": d.nseg_in,
+                    "service_ms": round((d.done - begin) * 1000.0, 2)})
+        prev = d.done
+    slowest = sorted(svc, key=lambda v: -v["service_ms"])[:8]
+    for v in slowest:
+        print(f"[bench] slow plain request {v}", file=sys.stderr, flush=True)
     if not sat["completed"] or not sat["makespan_s"]:
         raise RuntimeError(f"saturation run completed nothing: {sat}")
     mu = sat["completed"] / sat["makespan_s"]
@@ -963,7 +981,8 @@ def run_serving(args, dx, torch):
         "config": {"workload": f"c5: {WORKLOADS['c5']['desc']}",
                    "requests_per_load": args.serve_requests, "max_batch": 16, "slots": 2,
                    "budget_bytes": 64 << 30},
-        "serving": {"saturation_req_s_plain": mu, "loads": table},
+        "serving": {"saturation_req_s_plain": mu, "loads": table, "slowest_plain": slowest,
+                    "service_ms_total_plain": round(sum(v["service_ms"] for v in svc), 1)},
         "latency_ms_p50": top["latency_ms_p50"],
         "latency_ms_p99": top["latency_ms_p99"],
     }

@@ -79,9 +79,10 @@ typedef enum { DEXEL_DILATE = 0, DEXEL_ERODE = 1, DEXEL_OPEN = 2, DEXEL_CLOSE = 
 #define DEXEL_FLAG_VALIDATE 2u /* check the input is canonical before computing          */
 #define DEXEL_FLAG_RAYS_X 4u   /* dexel_dexelize only: rays along x (grid over y, z)      */
 #define DEXEL_FLAG_RAYS_Y 8u   /* dexel_dexelize only: rays along y (grid over z, x)      */
-/* Offsets: evaluate every column with the general kernels, without the
- * tiled fast paths (the thin-column erosion filter and the single-interval
- * dilation test); for comparison, the result is the same, bit for bit. */
+/* Offsets: evaluate every column with the general (staged) kernels,
+ * without the direct evaluation of fragmented passes and the tiled fast
+ * paths (the thin-column erosion filter and the single-interval dilation
+ * test); for comparison, the result is the same, bit for bit. */
 #define DEXEL_FLAG_GENERAL 16u
 
 typedef struct dexel_ctx dexel_ctx;
@@ -127,7 +128,11 @@ dexel_status dexel_workspace_size(dexel_ctx* ctx, const dexel_grid_view* in, flo
                                   int64_t cap_hint, size_t* bytes);
 
 /* After a call completed (stream synchronised), read the capacity hint the
- * call needed from the workspace header (a small device-to-host copy). */
+ * call needed from the workspace header (a small device-to-host copy).
+ * After DEXEL_ERR_WORKSPACE it is at least what the stage that ran out asked
+ * for (a later stage may ask for more); after success it is the largest
+ * internal buffer, in intervals, that the call used, so a workspace sized
+ * with it holds the same call, with the same kernel variant, again. */
 dexel_status dexel_workspace_need(dexel_ctx* ctx, const void* ws, int64_t* cap_hint);
 
 /* Allocation-free dexel_offset, for callers that cannot allocate device
@@ -271,7 +276,7 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
 
 /* Profiling.  When enabled, every pass of every later call records HIP
  * events on its stream around each of its DEXEL_NPROF launch groups: column
- * gaps, thin-column erosion, chord-extreme dilation test, row offset, its
+ * gaps, direct evaluation, thin-column erosion, chord-extreme dilation test, row offset, its
  * replays, test against the row offset and gap cut, neighbour
  * intersection, its
  * replay, extrusion seeds, their replay, y dilation with per-column union,
@@ -279,7 +284,7 @@ dexel_status dexel_autotune(dexel_ctx* ctx, int32_t n, const dexel_batch_item* i
  * dexel_profile_read waits for the recorded events and returns the
  * accumulated milliseconds per group and the number of passes (a dilation or
  * erosion is one pass, open/close two); reset != 0 clears the accumulators. */
-#define DEXEL_NPROF 14
+#define DEXEL_NPROF 15
 dexel_status dexel_profile_enable(dexel_ctx* ctx, int on);
 dexel_status dexel_profile_read(dexel_ctx* ctx, double* ms, int64_t* passes, int reset);
 

@@ -63,8 +63,9 @@ class Engine:
         self.device = torch.device("cuda", self.device_index)
         self.ctx = dexel_ctx_create(self.device_index)
         self._ws = None
-        # capacity hint (intervals) that the last successful call of offset()
-        # or batch_offset() used; Plan and BatchPlan size their workspace with it
+        # capacity hint (intervals) for the call offset() or batch_offset()
+        # last completed: what it used plus a margin, or 0 (the library's
+        # default); Plan and BatchPlan size their workspace with it
         self.last_hint = 0
 
     def close(self):
@@ -79,10 +80,24 @@ class Engine:
             pass
 
     def workspace(self, nbytes: int) -> torch.Tensor:
+        """The engine's scratch workspace, at least `nbytes` long: one buffer
+        that only grows, so a call may run on more capacity than it asked for
+        (the library uses all of it).  The caller drops its own reference to
+        the old buffer before asking for a larger one, so the two are never
+        held at once."""
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = None
             self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         return self._ws
+
+    def _note_hint(self, ws: torch.Tensor, default_cap: int) -> None:
+        """Record the capacity hint a Plan or BatchPlan should size its own
+        workspace with: what the call just completed really used (read from
+        the workspace header), with a quarter's margin for the other kernel
+        variants, or 0 (the library's default) when that is enough."""
+        need = dexel_workspace_need(self.ctx, ws)
+        h = int(need * 1.25) + 1024
+        self.last_hint = h if h > default_cap else 0
 
     def offset(self, grid: DeviceGrid, r: float, op: str = "dilate", stream=None,
                out_cap: int | None = None, validate: bool = False, max_tries: int = 8,
@@ -98,8 +113,10 @@ class Engine:
         ncols = grid.nx * grid.ny
         cap = out_cap if out_cap is not None else nseg + ncols + 1024
         flags = int(flags) | DEXEL_FLAG_SYNC | (DEXEL_FLAG_VALIDATE if validate else 0)
+        ws = col = z = None
         for _ in range(max_tries):
             nbytes = dexel_workspace_size(self.ctx, view, r, code, hint)
+            ws = col = z = None  # the last try's buffers go before the next are made
             ws = self.workspace(nbytes)
             col = torch.empty(ncols + 1, dtype=torch.int64, device=self.device)
             z = torch.empty(2 * max(cap, 1), dtype=torch.float32, device=self.device)
@@ -108,7 +125,7 @@ class Engine:
             out = make_out(grid.nx, grid.ny, col, z, nout, status)
             st = dexel_offset(self.ctx, view, r, code, out, ws, stream, flags)
             if st == DEXEL_OK:
-                self.last_hint = hint
+                self._note_hint(ws, nseg + 2 * ncols + 1024)
                 return DeviceGrid(grid.nx, grid.ny, col, z)
             if st == DEXEL_ERR_WORKSPACE:
                 need = dexel_workspace_need(self.ctx, ws)
@@ -307,7 +324,9 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
     ops = list(ops)
     dev = engine.device
     caps = [g.nseg + g.nx * g.ny + 1024 for g in grids]
+    ws = outs = None
     for _ in range(max_tries):
+        ws = outs = None  # the last try's buffers go before the next are made
         outs = [(torch.empty(g.nx * g.ny + 1, dtype=torch.int64, device=dev),
                  torch.empty(2 * max(c, 1), dtype=torch.float32, device=dev),
                  torch.zeros(1, dtype=torch.int64, device=dev),
@@ -317,7 +336,7 @@ def batch_offset(engine: "Engine", grids, radii, ops, stream=None, max_tries: in
         ws = engine.workspace(nbytes)
         st = dexel_batch_offset(engine.ctx, items, ws, stream, DEXEL_FLAG_SYNC)
         if st == DEXEL_OK:
-            engine.last_hint = hint
+            engine._note_hint(ws, sum(g.nseg + 2 * g.nx * g.ny for g in grids) + 1024)
             return [DeviceGrid(g.nx, g.ny, o[0], o[1]) for g, o in zip(grids, outs)]
         if st == DEXEL_ERR_WORKSPACE:
             need = dexel_workspace_need(engine.ctx, ws)

@@ -124,12 +124,12 @@ EXPORTED = ["dexel_ctx_create", "dexel_ctx_destroy", "dexel_workspace_size",
             "dexel_csg_workspace_size", "dexel_csg", "dexel_dexelize_workspace_size",
             "dexel_dexelize", "dexel_canonicalize_workspace_size", "dexel_canonicalize"]
 NVARIANT = 4
-NPROF = 14
-PROFILE_STAGES = ["column_gaps", "thin_erosion", "chord_extremes", "row_offset", "row_offset_replay",
+NPROF = 15
+PROFILE_STAGES = ["column_gaps", "direct", "thin_erosion", "chord_extremes", "row_offset", "row_offset_replay",
                   "gap_cut", "neighbour", "neighbour_replay", "seeds", "seeds_replay", "y_union",
                   "y_union_replay", "result_scan", "compact"]
 # main HIP kernel of each profiled group (as rocprofv3 names it)
-PROFILE_KERNELS = ["k_col_gaps", "k_thin_erode", "k_solid_dilate", "k_row_offset", "k_row_offset_fb",
+PROFILE_KERNELS = ["k_col_gaps", "k_direct", "k_thin_erode", "k_solid_dilate", "k_row_offset", "k_row_offset_fb",
                    "k_gap_cut", "k_neighbour", "k_neighbour_fb", "k_seeds", "k_seeds_fb", "k_union",
                    "k_union_fb", "k_scan", "k_copy_out"]
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <set>
@@ -77,6 +78,11 @@ struct ItemInfo {
 };
 
 int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
+
+// Thresholds of the choice of evaluation (see enqueue_batch).
+constexpr double kDirectKmin = 6.0;
+constexpr double kDirectItems = 24000.0;
+constexpr double kSolidKmin = 8.0;
 
 bool is_chain(int op) { return op == DEXEL_OPEN || op == DEXEL_CLOSE; }
 
@@ -326,13 +332,35 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
             S.need = (uint8_t*)(w + L.need) + gbase;
             S.lu = (float4*)(w + L.lu) + gbase;
         };
-        // passes of radii whose tiles fit the LDS take a tiled fast path:
-        // erosions the thin-column filter, dilations the single-interval test
+        // How each pass is evaluated (every choice gives the same result,
+        // bit for bit; DEXEL_FLAG_GENERAL keeps the staged kernels throughout):
+        // * directly (FAST_DIRECT) when the input is fragmented and the
+        //   stencil small: at least DIRECT_KMIN items per column, R at most
+        //   DIRECT_RMAX, and at most DIRECT_ITEMS chords per output column
+        //   (stencil columns x items per column, one more for an erosion's
+        //   gaps).  The second pass of a chain is judged by the call's input.
+        // * else, where the tiles fit the LDS, an erosion by the thin-column
+        //   filter first, and a dilation of an input with at least SOLID_KMIN
+        //   items per column by the single-interval test first (on sparser
+        //   input most columns fail the test, which then only adds work);
+        // * else by the staged kernels alone.
+        const double kbar = (double)it.in.nseg / (double)std::max<int64_t>(ii.ncols, 1);
+        int64_t sten = 0;
+        for (int dy = -ii.R; dy <= ii.R; ++dy) {
+            int64_t w = (int64_t)std::sqrt((double)(ii.d2max - dy * dy));
+            while (w > 0 && w * w + dy * dy > ii.d2max) --w;
+            while ((w + 1) * (w + 1) + dy * dy <= ii.d2max) ++w;
+            sten += 2 * w + 1;
+        }
         auto fast_of = [&](int erode) {
+            if (flags & DEXEL_FLAG_GENERAL) return (int32_t)dexel::FAST_NONE;
+            if (ii.R <= dexel::DIRECT_RMAX && kbar >= kDirectKmin &&
+                (double)sten * (kbar + erode) <= kDirectItems)
+                return (int32_t)dexel::FAST_DIRECT;
             const int lds = erode ? dexel::thin_lds_bytes(ii.R, ii.d2max)
                                   : dexel::solid_lds_bytes(ii.R, ii.d2max);
-            if ((flags & DEXEL_FLAG_GENERAL) || ii.R > dexel::THIN_RMAX || lds > ctx->max_lds)
-                return (int32_t)dexel::FAST_NONE;
+            if (ii.R > dexel::THIN_RMAX || lds > ctx->max_lds) return (int32_t)dexel::FAST_NONE;
+            if (!erode && kbar < kSolidKmin) return (int32_t)dexel::FAST_NONE;
             return (int32_t)(erode ? dexel::FAST_THIN : dexel::FAST_SOLID);
         };
         dexel::Shape a;
@@ -387,7 +415,8 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         int32_t bt = 0, bs = 0;
         for (auto& S : sh) {
             S.tbase = t;
-            if (S.fast == dexel::FAST_NONE) continue;
+            if (S.fast == dexel::FAST_DIRECT) q->ndirect = 1;
+            if (S.fast == dexel::FAST_NONE || S.fast == dexel::FAST_DIRECT) continue;
             const bool thin = S.fast == dexel::FAST_THIN;
             const int ty = thin ? dexel::THIN_TY : dexel::SOLID_TY;
             t += (int64_t)((S.nx + dexel::THIN_TX - 1) / dexel::THIN_TX) * ((S.ny + ty - 1) / ty);
@@ -561,7 +590,9 @@ dexel_status dexel_workspace_need(dexel_ctx* ctx, const void* ws, int64_t* cap_h
     WsHeader h;
     hipError_t e = hipMemcpy(&h, ws, sizeof(h), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(ctx, DEXEL_ERR_HIP, hipGetErrorString(e));
-    *cap_hint = (int64_t)h.need_cap;
+    unsigned long long m = h.need_cap;
+    for (unsigned long long v : {h.bumpA, h.bumpI, h.bumpC, h.arena}) m = v > m ? v : m;
+    *cap_hint = (int64_t)m;
     return DEXEL_OK;
 }
 

@@ -12,13 +12,14 @@ namespace dexel {
 struct WsHeader {
     int32_t status;                 // dexel_status, first error wins (workspace-wide errors)
     int32_t abort;                  // nonzero: the remaining kernels of the call exit at once
-    unsigned long long need_cap;    // largest internal-buffer size (intervals) the call needed
+    unsigned long long need_cap;    // largest internal-buffer size (intervals) the call used or asked for
+                                    // (the current pass's counters are folded in when it is read)
     unsigned long long bumpA;       // bump allocators of the per-column lists
     unsigned long long bumpI;
     unsigned long long bumpC;
     unsigned long long arena;       // bump allocator of the overflow arena
     int64_t nseg_out;
-    int32_t novf[10];               // columns on each overflow / work list (Stage)
+    int32_t novf[11];               // columns on each overflow / work list (Stage)
     unsigned long long nseeds;      // kept extrusion seeds of the current pass
     int64_t reserved[2];
 };
@@ -27,11 +28,13 @@ static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 // Overflow lists: columns whose per-lane list overflowed in K1, K1b, K2 (seed
 // slot) and K3, replayed one lane per column; and columns deferred as heavy
 // in K2, K1b and K3, or overflowing K1's lane replay, replayed one wave per
-// column (z slabs); and the columns the tiled dilation test leaves to the
-// test against V0 (ST_SOLB) and to the gap cut (ST_GAP).
+// column (z slabs); the columns the tiled dilation test leaves to the test
+// against V0 (ST_SOLB) and to the gap cut (ST_GAP); and the columns of a
+// direct evaluation whose team slab lists overflowed (ST_DIRW).
 enum Stage {
     ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3,
-    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, ST_SOLB = 9, NSTAGE = 10
+    ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, ST_SOLB = 9, ST_DIRW = 10,
+    NSTAGE = 11
 };
 
 // Seed slots per column: the seeds of a column are written at
@@ -77,6 +80,7 @@ struct Shape {
     // columns the chord-extreme test, the test against V0 and the gap cut
     // settle; the shape's tiles are tbase .. of the pass.  gen[c] holds GEN_*
     // bits, need[c] the general stages column c must run (NEED_* bits).
+    // FAST_DIRECT: the shape is evaluated directly, without tiles.
     int32_t fast;
     int32_t pad1;
     int64_t tbase;
@@ -94,7 +98,7 @@ struct Pass {
     const Shape* shapes;      // [nshapes]
     const int64_t* sbase;     // [nshapes + 1] first global column of each shape; sbase[n] = gcols
     int32_t nshapes;
-    int32_t pad;
+    int32_t ndirect;          // the pass has shapes evaluated directly (FAST_DIRECT; 0 / 1)
     int64_t gcols;            // padded global column count of the pass
     int64_t ntiles;           // tiles of the tiled fast paths over the pass's shapes that have one
     int32_t thin_lds;         // dynamic LDS bytes of k_thin_erode (largest R of its shapes)
@@ -144,13 +148,18 @@ hipError_t launch_put_f32(float* dst, const float* host, int n, hipStream_t s);
 hipError_t launch_init_call(WsHeader* hdr, int32_t* shape_status, int nitems, hipStream_t s);
 hipError_t launch_init_pass(WsHeader* hdr, hipStream_t s);
 hipError_t launch_check_input(const Pass& p, int validate, hipStream_t s);
-// Profiled intervals of one pass, one per launch group: column gaps,
-// thin-column erosion, chord-extreme dilation test, row offset, its replays,
+// Profiled intervals of one pass, one per launch group: column gaps, direct
+// evaluation, thin-column erosion, chord-extreme dilation test, row offset, its replays,
 // test against V0 and gap cut (with the row offsets they still need),
 // neighbour intersection, its replays, seeds, their replays, y dilation +
 // union, its replays, result scan, compaction.
-constexpr int NPROF = 14;
-enum FastPath { FAST_NONE = 0, FAST_THIN = 1, FAST_SOLID = 2 };
+constexpr int NPROF = 15;
+// FAST_DIRECT: every column of the pass is the union of its stencil's chords,
+// evaluated by teams of lanes (k_direct); the staged kernels skip the shape.
+enum FastPath { FAST_NONE = 0, FAST_THIN = 1, FAST_SOLID = 2, FAST_DIRECT = 3 };
+// Direct evaluation is chosen for radii up to DIRECT_RMAX (its kernels stage
+// one stencil row's column pointers, at most 2 * DIRECT_RMAX + 2 of them).
+constexpr int DIRECT_RMAX = 16;
 // Tiled fast paths: tiles of THIN_TX x THIN_TY (thin erosion) or
 // THIN_TX x SOLID_TY (dilation test) output columns, radii up to THIN_RMAX.
 // LDS bytes a tile stages at integer radius R: per staged column one float2

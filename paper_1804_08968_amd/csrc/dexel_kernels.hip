@@ -1273,9 +1273,9 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const float hhi = fminf(fminf(h4.y, h4.w + hd), ze);
             if (hlo > hhi) continue;
             const SeedSpans sp = seed_spans(P, cc);
-            const float2* sv = sp.s[k & 1];
-            const uint8_t* tv = sp.t[k & 1];
-            int j0 = 0, nb = sp.n[k & 1];
+            const float2* sv = (k & 1) ? sp.s[1] : sp.s[0];
+            const uint8_t* tv = (k & 1) ? sp.t[1] : sp.t[0];
+            int j0 = 0, nb = (k & 1) ? sp.n[1] : sp.n[0];
             const int64_t ob = gld(&P.offB[cc]);
             if (ob < 0 && gld(&P.loB[cc]) < 0) {
                 // a replayed seed column is ordered by its own slabs: scan only
@@ -1483,6 +1483,7 @@ __device__ __forceinline__ Place place_block(const Pass& Q) {
 // not settle reach the row offset through its lane replay's list); in the
 // second on the FAST_SOLID columns whose V0 the general stages still need.
 __device__ __forceinline__ bool needs(const Pass& Q, const Shape& S, int64_t c, int bit) {
+    if (S.fast == FAST_DIRECT) return false;
     if (bit == NEED_ROW) {
         if (Q.k1_round == 2)
             return S.fast == FAST_SOLID && (gld(&S.need[c]) & NEED_ROW) && !(gld(&S.gen[c]) & GEN_V0);
@@ -2093,6 +2094,372 @@ __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
             }
         MemList M{(float2*)out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
         emit_lane(P, c, M, k, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// direct evaluation of fragmented passes by teams of lanes
+// ---------------------------------------------------------------------------
+//
+// When a pass's result stays fragmented at a small radius (tens of intervals
+// per column), the staged path does about the brute force's work (Sec. 4,
+// "Baseline Comparison": the seed rows K3 reads hold about as many chords as
+// the stencil's items) while its per-column lists overflow into the replays.
+// Such a pass (FAST_DIRECT) is evaluated directly: column c's result is the
+// union of the chords [a - H[d2], b + H[d2]] of the items [a, b] of every
+// column of its stencil (d2 = dx^2 + dy^2 <= floor(r^2); for an erosion the
+// items are the column's gaps, unbounded at the ends, and the result the
+// gaps of the union), which is the definition the staged path reaches.
+//
+// A team of T lanes evaluates one column, lane l keeping the union
+// restricted to the slab [b_l, b_l+1] of z (b_0 = -inf, b_T = +inf, the
+// others evenly spaced over the column's likely range): clipping commutes
+// with the union, and the pieces of an interval cut at a slab boundary touch
+// there and merge again when the team leader stitches the slabs.  The team
+// walks the stencil row by row, nearest rows first; a row of the stencil is
+// one contiguous span of the CSR, whose column pointers the team stages in
+// LDS.  Each stencil column's items are streamed in chunks of 4T: lane l
+// computes the chords of items l, l + T, l + 2T and l + 3T of the chunk into
+// the team's LDS buffer, and every lane then reads the whole buffer
+// (broadcast reads) and merges the chords, clipped to its slab, into its
+// list.  One stencil column's chords arrive in order of their starts (one
+// half-width for the whole column), so the merge is a forward walk: a cursor
+// in the lane's list only advances, and a chord inside the interval under the
+// cursor costs two compares.  A column whose slab list overflows goes to the
+// whole-wave evaluation (64 slabs, ST_DIRW), and a column that overflows that
+// too to the arena tier (one lane).
+constexpr int TEAM_BLOCKS = 4096;
+
+// Teams of T lanes (T a power of two dividing 64), aligned in the wave.
+// Boundary b_k (k = 0 .. T) of T slabs over [zmin, zmax].
+template <int T>
+__device__ __forceinline__ float team_bound(float zmin, float zmax, int k) {
+    if (k <= 0) return -DX_INF;
+    if (k >= T) return DX_INF;
+    return zmin + (zmax - zmin) * ((float)k * (1.0f / (float)T));
+}
+
+template <int T>
+__device__ __forceinline__ float team_min(float v) {
+#pragma unroll
+    for (int d = T / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+template <int T>
+__device__ __forceinline__ float team_max(float v) {
+#pragma unroll
+    for (int d = T / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Does any lane of this lane's team hold p?  (Called by whole teams.)
+template <int T>
+__device__ __forceinline__ bool team_any(bool p) {
+    const unsigned long long m = (unsigned long long)__ballot(p);
+    if (T == 64) return m != 0;
+    const int tb = (threadIdx.x & 63) & ~(T - 1);
+    return ((m >> tb) & ((1ull << (T & 63)) - 1)) != 0;
+}
+
+// Orders a wave's LDS writes before its later reads of what other lanes of
+// the wave wrote (a wave's LDS operations complete in order; the fences keep
+// the compiler from moving accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int DT = 4;        // lanes per column
+constexpr int DT_CAP = 24;   // slab list capacity per lane
+constexpr int DSPAN = 2 * DIRECT_RMAX + 2;
+
+// Merge [lo, hi] into a canonical list of size n at position i, where every
+// U[k] with k < i ends below lo and U[i] (if i < n) does not: as a new
+// interval before U[i], or joined with U[i] and every later interval starting
+// at or below hi.  Returns the new size (-1 if a new interval does not fit;
+// the list is unchanged then); *cur is the interval now at i.
+template <class L>
+__device__ int lv_merge_at(const L& U, int n, int i, float lo, float hi, float2* cur) {
+    if (i == n || U.get(i).x > hi) {
+        if (n >= U.cap) return -1;
+        for (int k = n; k > i; --k) U.set(k, U.get(k - 1));
+        *cur = make_float2(lo, hi);
+        U.set(i, *cur);
+        return n + 1;
+    }
+    const float2 ui = U.get(i);
+    int j = i;
+    float hj = ui.y;
+    while (j + 1 < n) {
+        const float2 v = U.get(j + 1);
+        if (v.x > hi) break;
+        hj = v.y;
+        ++j;
+    }
+    *cur = make_float2(fminf(lo, ui.x), fmaxf(hi, hj));
+    U.set(i, *cur);
+    const int sh = j - i;
+    if (sh > 0)
+        for (int k = j + 1; k < n; ++k) U.set(k - sh, U.get(k));
+    return n - sh;
+}
+
+// Half-width of row dy of the stencil: the largest w with w^2 + dy^2 <=
+// d2max (-1 if the row is outside).
+__device__ __forceinline__ int sten_width(int d2max, int dy2) {
+    const int rem = d2max - dy2;
+    if (rem < 0) return -1;
+    int w = (int)sqrtf((float)rem);
+    while (w > 0 && w * w > rem) --w;
+    while ((w + 1) * (w + 1) <= rem) ++w;
+    return w;
+}
+
+// Chord of item k of the column at z[b .. b + m) widened by h: the interval
+// itself, or for an erosion the column's gap k (k = 0 .. m, unbounded at the
+// ends).  Past the last item: an empty chord (lo > hi).
+__device__ __forceinline__ float2 item_chord(const float2* z, int64_t b, int m, int k, int erode,
+                                             float h) {
+    if (!erode) {
+        if (k >= m) return make_float2(DX_INF, -DX_INF);
+        const float2 v = gld(&z[b + k]);
+        return make_float2(v.x - h, v.y + h);
+    }
+    if (k > m) return make_float2(DX_INF, -DX_INF);
+    const float lo = k == 0 ? -DX_INF : gld(&z[b + k - 1]).y;
+    const float hi = k == m ? DX_INF : gld(&z[b + k]).x;
+    return make_float2(lo - h, hi + h);
+}
+
+// Direct evaluation of one column by one lane (the arena tier), and an upper
+// bound of its list: every chord of the stencil.
+template <class L>
+__device__ int direct_column(const OpParams& P, int64_t c, const L& U) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    int n = 0;
+    for (int dy = -P.R; dy <= P.R; ++dy) {
+        const int yy = y + dy;
+        const int w = sten_width(P.d2max, dy * dy);
+        if (yy < 0 || yy >= P.ny || w < 0) continue;
+        for (int dx = -w; dx <= w; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= P.nx) continue;
+            const float h = gld(&P.H[dx * dx + dy * dy]);
+            int64_t b;
+            const int m = col_len(P, (int64_t)yy * P.nx + xx, &b);
+            const int cnt = P.erode ? m + 1 : m;
+            for (int k = 0; k < cnt; ++k) {
+                const float2 ch = item_chord(P.z, b, m, k, P.erode, h);
+                n = lv_insert(U, n, ch.x, ch.y);
+                if (n < 0) return -1;
+            }
+        }
+    }
+    return n;
+}
+
+__device__ int64_t direct_bound(const OpParams& P, int64_t c) {
+    int x, y;
+    col_xy(P, c, &x, &y);
+    int64_t b = 1;
+    for (int dy = -P.R; dy <= P.R; ++dy) {
+        const int yy = y + dy;
+        const int w = sten_width(P.d2max, dy * dy);
+        if (yy < 0 || yy >= P.ny || w < 0) continue;
+        const int x0 = max(x - w, 0), x1 = min(x + w, P.nx - 1);
+        const int64_t rb = (int64_t)yy * P.nx;
+        b += gld(&P.col_ptr[rb + x1 + 1]) - gld(&P.col_ptr[rb + x0]) + (P.erode ? x1 - x0 + 1 : 0);
+    }
+    return b;
+}
+
+// wide == 0: every column of the pass's FAST_DIRECT shapes, teams of T lanes;
+// wide == 1: the columns on ST_DIRW, T = 64.
+template <int T, int CAP>
+__global__ void __launch_bounds__(WG) k_direct(Pass Q, int wide) {
+    constexpr int TPW = WG / T;
+    __shared__ float2 lds[CAP * WG];
+    __shared__ float2 chs[TPW][4 * T + 2];  // padded: the teams' buffers start on different banks
+    __shared__ int32_t cps[TPW][DSPAN];
+    __shared__ int nsh[WG];
+    if (Q.hdr->abort) return;
+    const int64_t total = wide ? (int64_t)Q.hdr->novf[ST_DIRW] : Q.gcols;
+    const int lane = threadIdx.x;
+    const int lt = lane & (T - 1);
+    const int tb = lane - lt;
+    const int tm = lane / T;
+    const LdsList U{&lds[lane], CAP};
+    for (int64_t e0 = (int64_t)blockIdx.x * TPW; e0 < total; e0 += (int64_t)gridDim.x * TPW) {
+        const int64_t e = e0 + tm;
+        const int64_t ei = e < total ? e : e0;
+        const int64_t g = wide ? (int64_t)Q.ovf[(int64_t)ST_DIRW * Q.gcols + ei] : ei;
+        const int s = find_shape(Q, g);
+        const Shape& S = Q.shapes[s];
+        const int64_t c = g - Q.sbase[s];
+        const bool live = e < total && S.fast == FAST_DIRECT && c < S.ncols;  // the same for a team
+        const OpParams P = make_op(Q, S);
+        int n = 0;
+        bool ok = true;
+        if (live) {
+            int x, y;
+            col_xy(P, c, &x, &y);
+            // slab range: the items of the stencil's central row and column,
+            // widened by r (the slabs only balance the lanes' work)
+            float zmin = DX_INF, zmax = -DX_INF;
+            const int half = 2 * P.R + 1;
+            for (int p = lt; p < 2 * half; p += T) {
+                const int xx = p < half ? x : x + (p - half) - P.R;
+                const int yy = p < half ? y + p - P.R : y;
+                if (xx < 0 || xx >= P.nx || yy < 0 || yy >= P.ny) continue;
+                const int64_t cc = (int64_t)yy * P.nx + xx;
+                if (gld(&P.gap[cc]) < 0.0f) continue;  // empty column
+                const float4 e4 = gld(&P.ends[cc]);
+                widen(&zmin, &zmax, e4.x);
+                widen(&zmin, &zmax, e4.w);
+            }
+            zmin = team_min<T>(zmin);
+            zmax = team_max<T>(zmax);
+            if (zmin <= zmax) {
+                const float h0 = gld(&P.H[0]);
+                zmin -= h0;
+                zmax += h0;
+            }
+            const float2 rg = slab_range(zmin, zmax);
+            const float zs = team_bound<T>(rg.x, rg.y, lt), ze = team_bound<T>(rg.x, rg.y, lt + 1);
+            bool fail = false;
+            for (int i = 0; i <= 2 * P.R && !fail; ++i) {
+                const int dy = (i & 1) ? -((i + 1) >> 1) : (i >> 1);  // 0, -1, 1, -2, 2, ...
+                const int yy = y + dy;
+                const int dy2 = dy * dy;
+                const int w = sten_width(P.d2max, dy2);
+                if (yy < 0 || yy >= P.ny || w < 0) continue;
+                const int x0 = max(x - w, 0), x1 = min(x + w, P.nx - 1);
+                const int64_t rb = (int64_t)yy * P.nx + x0;
+                const int64_t zb = gld(&P.col_ptr[rb]);
+                for (int j = lt; j <= x1 - x0 + 1; j += T) cps[tm][j] = (int32_t)(gld(&P.col_ptr[rb + j]) - zb);
+                wave_lds_sync();
+                for (int v = 0; v <= 2 * w && !fail; ++v) {
+                    const int xx = visit_col(x, v);
+                    if (xx < x0 || xx > x1) continue;
+                    const int dx = xx - x;
+                    const float h = gld(&P.H[dx * dx + dy2]);
+                    const int o = cps[tm][xx - x0];
+                    const int m = cps[tm][xx - x0 + 1] - o;
+                    const int64_t b = zb + o;
+                    const int cnt = P.erode ? m + 1 : m;
+                    // merge cursor: U[ci] = cur is the first interval not ending below
+                    // the chords still to come (ci = n: none)
+                    int ci = 0;
+                    float2 cur = n > 0 ? U.get(0) : make_float2(DX_INF, DX_INF);
+                    for (int k0 = 0; k0 < cnt && !fail; k0 += 4 * T) {
+                        float2 q4[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) q4[q] = item_chord(P.z, b, m, k0 + q * T + lt, P.erode, h);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) chs[tm][q * T + lt] = q4[q];
+                        wave_lds_sync();
+                        // the chunk in blocks of SB chords, each read into registers at once
+                        constexpr int SB = 4 * T < 16 ? 4 * T : 16;
+                        for (int u0 = 0; u0 < 4 * T; u0 += SB) {
+                            float2 cq[SB];
+#pragma unroll
+                            for (int u = 0; u < SB; ++u) cq[u] = chs[tm][u0 + u];
+#pragma unroll
+                            for (int u = 0; u < SB; ++u) {
+                                // chords past the column's last item are empty
+                                const float lo = fmaxf(cq[u].x, zs), hi = fminf(cq[u].y, ze);
+                                if (!ok || !(lo <= hi)) continue;
+                                while (cur.y < lo) {
+                                    ++ci;
+                                    cur = ci < n ? U.get(ci) : make_float2(DX_INF, DX_INF);
+                                }
+                                if (cur.x <= lo && hi <= cur.y) continue;  // inside
+                                const int nn = lv_merge_at(U, n, ci, lo, hi, &cur);
+                                if (nn < 0) ok = false; else n = nn;
+                            }
+                        }
+                        wave_lds_sync();  // the buffer is read before the next chunk is written
+                        fail = team_any<T>(!ok);
+                    }
+                }
+            }
+        }
+        const bool fail = team_any<T>(live && !ok);
+        nsh[lane] = n;
+        __syncthreads();  // every slab list and its size are written
+        // the team leader stitches the slab lists: count first
+        int outn = 0;
+        if (live && !fail && lt == 0) {
+            int m = 0;
+            float py = 0.0f;
+            for (int l = 0; l < T; ++l)
+                for (int i = 0, nl = nsh[tb + l]; i < nl; ++i) {
+                    const float2 v = lds[i * WG + tb + l];
+                    if (m > 0 && v.x <= py) {
+                        py = fmaxf(py, v.y);
+                    } else {
+                        ++m;
+                        py = v.y;
+                    }
+                }
+            outn = P.erode ? (m > 0 ? m - 1 : 0) : m;
+        }
+        int tot;
+        const int pre = wave_excl_scan(outn, &tot);
+        unsigned long long base = 0;
+        if (lane == 0 && tot > 0) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+        base = __shfl(base, 0, 64);
+        const unsigned long long end = base + (unsigned long long)tot;
+        const bool fits = end <= (unsigned long long)Q.cap;
+        if (!fits && lane == 0) {
+            note_need(Q.hdr, end);
+            set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+        }
+        if (live && lt == 0) {
+            if (fail && !wide) {
+                push_overflow(Q, ST_DIRW, g);
+            } else if (fail) {
+                arena_eval(P, 1, direct_bound(P, c), [&](const MemList& M, const MemList&) {
+                    const int nn = direct_column(P, c, M);
+                    if (nn >= 0) emit_lane(P, c, M, nn, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+                    return nn;
+                });
+            } else {
+                gst(&P.offC[c], (int64_t)(base + pre));
+                gst(&P.cntC[c], fits ? outn : 0);
+                if (fits) {
+                    // again, writing: the merged intervals, or the gaps
+                    // between them for an erosion
+                    float2* d = P.C + base + pre;
+                    int m = 0;
+                    float2 cur = make_float2(0.0f, 0.0f);
+                    float prev_hi = 0.0f;
+                    for (int l = 0; l < T; ++l)
+                        for (int i = 0, nl = nsh[tb + l]; i < nl; ++i) {
+                            const float2 v = lds[i * WG + tb + l];
+                            if (m > 0 && v.x <= cur.y) {
+                                cur.y = fmaxf(cur.y, v.y);
+                                continue;
+                            }
+                            if (m > 0) {
+                                if (!P.erode) gst(&d[m - 1], cur);
+                                else if (m >= 2) gst(&d[m - 2], make_float2(prev_hi, cur.x));
+                                prev_hi = cur.y;
+                            }
+                            cur = v;
+                            ++m;
+                        }
+                    if (m > 0) {
+                        if (!P.erode) gst(&d[m - 1], cur);
+                        else if (m >= 2) gst(&d[m - 2], make_float2(prev_hi, cur.x));
+                    }
+                }
+            }
+        }
+        __syncthreads();  // the leaders have read the lists before they are reused
     }
 }
 
@@ -2768,9 +3135,11 @@ __global__ void __launch_bounds__(WG) k_copy_out(Pass Q) {
     const int64_t total = S.scanC[S.ncols] - base;
     const int64_t zb = S.out_zoff ? *S.out_zoff : 0;
     const bool fits = zb + total <= S.out_cap;
+    // the intermediate grid of a chain lives in the workspace: its size
+    // counts toward the call's capacity need whether or not it fits
+    if (pl.c == 0 && S.out_is_intermediate) note_need(Q.hdr, (unsigned long long)(zb + total));
     if (!fits && pl.c == 0) {
         if (S.out_is_intermediate) {
-            note_need(Q.hdr, (unsigned long long)(zb + total));
             set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
         } else {
             atomicCAS(&Q.shape_status[S.index], 0, DEXEL_ERR_CAPACITY);
@@ -2803,6 +3172,14 @@ __global__ void k_init_call(WsHeader* h, int32_t* shape_status, int nitems) {
 __global__ void k_init_pass(WsHeader* h) {
     if (threadIdx.x < NSTAGE) h->novf[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
+        // the first pass's use of the per-column lists and the arena counts
+        // toward the call's capacity need before the counters restart
+        unsigned long long m = h->need_cap;
+        m = m > h->bumpA ? m : h->bumpA;
+        m = m > h->bumpI ? m : h->bumpI;
+        m = m > h->bumpC ? m : h->bumpC;
+        m = m > h->arena ? m : h->arena;
+        h->need_cap = m;
         h->bumpA = h->bumpI = h->bumpC = h->arena = 0;
         h->nseeds = 0;
     }
@@ -3531,21 +3908,27 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(0);
     hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
+    if (p.ndirect) {
+        const int64_t nt = (p.gcols + WG / DT - 1) / (WG / DT);
+        hipLaunchKernelGGL((k_direct<DT, DT_CAP>), dim3((unsigned)(nt < TEAM_BLOCKS ? nt : TEAM_BLOCKS)), b, 0, s, p, 0);
+        hipLaunchKernelGGL((k_direct<64, CAP_Z>), gf, b, 0, s, p, 1);
+    }
+    DX_MARK(2);
     if (p.ntiles > 0 && p.nthin > 0) {
         hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.thin_lds, s, p);
         hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_THIN);
     }
-    DX_MARK(2);
+    DX_MARK(3);
     if (p.ntiles > 0 && p.nsolid > 0)
         hipLaunchKernelGGL(k_solid_dilate, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.solid_lds, s, p);
-    DX_MARK(3);
+    DX_MARK(4);
     Pass p1 = p;
     p1.k1_round = 1;
     hipLaunchKernelGGL(k_row_offset<C1>, g, b, 0, s, p1);
-    DX_MARK(4);
+    DX_MARK(5);
     hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_row_offset_heavy, gf, b, 0, s, p);
-    DX_MARK(5);
+    DX_MARK(6);
     if (p.ntiles > 0 && p.nsolid > 0) {
         hipLaunchKernelGGL(k_solid_b, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
@@ -3558,27 +3941,27 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
         hipLaunchKernelGGL(k_row_offset_fb, g, b, 0, s, p);
         hipLaunchKernelGGL(k_row_offset_heavy, gf, b, 0, s, p);
     }
-    DX_MARK(6);
-    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
     DX_MARK(7);
+    hipLaunchKernelGGL(k_neighbour<C1B>, g, b, 0, s, p);
+    DX_MARK(8);
     hipLaunchKernelGGL(k_neighbour_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_neighbour_heavy, gf, b, 0, s, p);
-    DX_MARK(8);
-    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
     DX_MARK(9);
+    hipLaunchKernelGGL(k_seeds<C2>, g, b, 0, s, p);
+    DX_MARK(10);
     hipLaunchKernelGGL(k_seeds_fb<C2>, g, b, 0, s, p);
     hipLaunchKernelGGL(k_seeds_heavy<C2>, gf, b, 0, s, p);
-    DX_MARK(10);
-    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
     DX_MARK(11);
+    hipLaunchKernelGGL(k_union<C3>, g, b, 0, s, p);
+    DX_MARK(12);
     hipLaunchKernelGGL(k_union_fb, g, b, 0, s, p);
     hipLaunchKernelGGL(k_union_heavy, gf, b, 0, s, p);
-    DX_MARK(12);
+    DX_MARK(13);
     e = scan_counts(p.cntC_g, p.gcols, p.bsum, p.scanC_g, p.hdr, s);
     if (e != hipSuccess) return e;
-    DX_MARK(13);
-    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
     DX_MARK(14);
+    hipLaunchKernelGGL(k_copy_out, g, b, 0, s, p);
+    DX_MARK(15);
 #undef DX_MARK
     return hipGetLastError();
 }

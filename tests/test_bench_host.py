@@ -60,10 +60,10 @@ def test_traffic_only_for_the_profiled_source(monkeypatch, tmp_path):
 
 
 class _Dx:
-    PROFILE_STAGES = ["column_gaps", "thin_erosion", "chord_extremes", "row_offset", "row_offset_replay",
+    PROFILE_STAGES = ["column_gaps", "direct", "thin_erosion", "chord_extremes", "row_offset", "row_offset_replay",
                       "gap_cut", "neighbour", "neighbour_replay", "seeds", "seeds_replay", "y_union",
                       "y_union_replay", "result_scan", "compact"]
-    PROFILE_KERNELS = ["k_col_gaps", "k_thin_erode", "k_solid_dilate", "k_row_offset", "k_row_offset_fb",
+    PROFILE_KERNELS = ["k_col_gaps", "k_direct", "k_thin_erode", "k_solid_dilate", "k_row_offset", "k_row_offset_fb",
                        "k_gap_cut", "k_neighbour", "k_neighbour_fb", "k_seeds", "k_seeds_fb", "k_union",
                        "k_union_fb", "k_scan", "k_copy_out"]
 

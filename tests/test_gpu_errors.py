@@ -229,6 +229,78 @@ def test_engine_retries_to_exact_result(engine, oracle_lib):
         fresh.close()
 
 
+def _points_grid(nx, ny, k, height, seed):
+    """k short intervals per column at random heights: a dilation's row
+    unions hold several times more intervals than the input, so the call
+    needs more internal capacity than the library's default (with k = 5 the
+    staged kernels evaluate it: too few items per column for the direct
+    evaluation or the single-interval test)."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for _ in range(nx * ny):
+        a = np.sort(rng.choice(int(height), size=k, replace=False)).astype(np.float64)
+        cols.append([(float(v), float(v) + 0.25) for v in a])
+    return grid_from_columns(nx, ny, cols)
+
+
+def test_need_after_success_sizes_workspace(engine, oracle_lib):
+    """After a call that succeeded on a roomy workspace, dexel_workspace_need
+    is the largest internal buffer it used: a workspace sized with it holds
+    the call again, one sized with half of it does not."""
+    import torch
+    dx = _dx()
+    hg = _points_grid(48, 40, 5, 1500.0, 11)
+    dg = dx.DeviceGrid.from_host(hg)
+    r, code = 4.0, dx.OPS["dilate"]
+    ref = oracle_lib.run(hg, r, "dilate", "f32model")
+    default = hg.nseg + 2 * hg.nx * hg.ny + 1024
+    print(f"[case] need after success nseg={hg.nseg}", flush=True)
+
+    def call(hint):
+        nbytes = dx.dexel_workspace_size(engine.ctx, dg.view(), r, code, hint)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        out, bufs = _out(dg, int(ref.col_ptr[-1]) + 1)
+        st = dx.dexel_offset(engine.ctx, dg.view(), r, code, out, ws, None, dx.DEXEL_FLAG_SYNC)
+        return st, ws, bufs
+
+    st, ws, _ = call(20 * default)
+    assert st == dx.DEXEL_OK, dx.dexel_last_error(engine.ctx)
+    need = dx.dexel_workspace_need(engine.ctx, ws)
+    assert need > default, (need, default)
+    st, _, bufs = call(need)
+    assert st == dx.DEXEL_OK, dx.dexel_last_error(engine.ctx)
+    assert np.array_equal(bufs[0].cpu().numpy(), ref.col_ptr)
+    n = int(ref.col_ptr[-1])
+    assert np.array_equal(bufs[1].cpu().numpy()[: 2 * n].astype(np.float64), ref.z)
+    st, _, _ = call(need // 2)
+    assert st == dx.DEXEL_ERR_WORKSPACE
+
+
+def test_plan_after_larger_call(oracle_lib):
+    """A Plan built after the engine ran a larger call (whose workspace the
+    engine keeps) sizes its own workspace from what its call used, so
+    autotuning finds a variant that fits and the plan's result is exact."""
+    dx = _dx()
+    fresh = dx.Engine(0)
+    try:
+        big = dx.DeviceGrid.from_host(HostGrid(*_as_tuple(gen.config_grid("c2", 0))))
+        print("[case] plan after larger call", flush=True)
+        fresh.offset(big, 8.0, "dilate")
+        hg = _points_grid(48, 40, 5, 1500.0, 12)
+        dg = dx.DeviceGrid.from_host(hg)
+        plan = dx.Plan(fresh, dg, 4.0, "dilate")
+        assert fresh.last_hint > hg.nseg + 2 * hg.nx * hg.ny + 1024
+        plan.autotune(reps=1)
+        plan.enqueue(flags=dx.DEXEL_FLAG_SYNC)
+        assert plan.status() == dx.DEXEL_OK
+        col, z = plan.result().to_host()
+        ref = oracle_lib.run(hg, 4.0, "dilate", "f32model")
+        assert np.array_equal(col, ref.col_ptr)
+        assert np.array_equal(z[: 2 * col[-1]].astype(np.float64), ref.z)
+    finally:
+        fresh.close()
+
+
 def _as_tuple(g):
     return g.nx, g.ny, g.col_ptr, g.z
 
