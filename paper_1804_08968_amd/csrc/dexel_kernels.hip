@@ -2125,9 +2125,12 @@ __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
 // list.  One stencil column's chords arrive in order of their starts (one
 // half-width for the whole column), so the merge is a forward walk: a cursor
 // in the lane's list only advances, and a chord inside the interval under the
-// cursor costs two compares.  A column whose slab list overflows goes to the
-// whole-wave evaluation (64 slabs, ST_DIRW), and a column that overflows that
-// too to the arena tier (one lane).
+// cursor costs two compares.
+//
+// The first tier (k_direct1) gives each column one lane and one list, with
+// no slabs: every chord is merged once.  A column whose list overflows goes
+// to a team of DT lanes (ST_DIRT), then to a whole wave (64 slabs, ST_DIRW),
+// then to the arena tier (one lane).
 constexpr int TEAM_BLOCKS = 4096;
 
 // Teams of T lanes (T a power of two dividing 64), aligned in the wave.
@@ -2171,8 +2174,9 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int DT = 4;        // lanes per column
-constexpr int DT_CAP = 24;   // slab list capacity per lane
+constexpr int D1_CAP = 48;   // list capacity of the lane-per-column tier
+constexpr int DT = 4;        // lanes per column of the team tier
+constexpr int DT_CAP = 24;   // its slab list capacity per lane
 constexpr int DSPAN = 2 * DIRECT_RMAX + 2;
 
 // Merge [lo, hi] into a canonical list of size n at position i, where every
@@ -2276,17 +2280,95 @@ __device__ int64_t direct_bound(const OpParams& P, int64_t c) {
     return b;
 }
 
-// wide == 0: every column of the pass's FAST_DIRECT shapes, teams of T lanes;
-// wide == 1: the columns on ST_DIRW, T = 64.
+// Lane-per-column tier over every column of the pass's FAST_DIRECT shapes
+// (64 consecutive columns per wave).  Each lane walks its stencil row by row
+// (nearest rows first, a row's columns in memory order, the next column's
+// end pointer loaded ahead) and merges each stencil column's chords, loaded
+// eight at a time, into its list with a forward cursor; the list entry after
+// the cursor is kept loaded ahead, so the walk waits on LDS only after an
+// insertion or a second step for one chord.
+template <int CAP>
+__global__ void __launch_bounds__(WG) k_direct1(Pass Q) {
+    __shared__ float2 lds[CAP * WG];
+    if (Q.hdr->abort) return;
+    const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
+    const int s = find_shape(Q, g < Q.gcols ? g : Q.gcols - 1);
+    const Shape& S = Q.shapes[s];
+    const int64_t c = g - Q.sbase[s];
+    const bool live = g < Q.gcols && S.fast == FAST_DIRECT && c < S.ncols;
+    if (!__any(live)) return;
+    const OpParams P = make_op(Q, S);
+    const LdsList U{&lds[threadIdx.x], CAP};
+    const float2 NONE = make_float2(DX_INF, DX_INF);
+    int n = 0;
+    bool ok = live;
+    if (live) {
+        int x, y;
+        col_xy(P, c, &x, &y);
+        for (int i = 0; i <= 2 * P.R && ok; ++i) {
+            const int dy = (i & 1) ? -((i + 1) >> 1) : (i >> 1);  // 0, -1, 1, -2, 2, ...
+            const int yy = y + dy;
+            const int dy2 = dy * dy;
+            const int w = sten_width(P.d2max, dy2);
+            if (yy < 0 || yy >= P.ny || w < 0) continue;
+            const int x0 = max(x - w, 0), x1 = min(x + w, P.nx - 1);
+            const int64_t rb = (int64_t)yy * P.nx;
+            int64_t b = gld(&P.col_ptr[rb + x0]);
+            int64_t e = gld(&P.col_ptr[rb + x0 + 1]);
+            for (int xx = x0; xx <= x1 && ok; ++xx) {
+                const int64_t en = xx < x1 ? gld(&P.col_ptr[rb + xx + 2]) : e;  // ahead
+                const int dx = xx - x;
+                const float h = gld(&P.H[dx * dx + dy2]);
+                const int m = (int)(e - b);
+                const int cnt = P.erode ? m + 1 : m;
+                int ci = 0;
+                float2 cur = n > 0 ? U.get(0) : NONE;
+                float2 nxt = n > 1 ? U.get(1) : NONE;
+                for (int k0 = 0; k0 < cnt && ok; k0 += 8) {
+                    float2 cq[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) cq[q] = item_chord(P.z, b, m, k0 + q, P.erode, h);
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const float lo = cq[q].x, hi = cq[q].y;
+                        if (!ok || !(lo <= hi)) continue;  // past the column's last item
+                        while (cur.y < lo) {
+                            ++ci;
+                            cur = nxt;
+                            nxt = ci + 1 < n ? U.get(ci + 1) : NONE;
+                        }
+                        if (cur.x <= lo && hi <= cur.y) continue;  // inside
+                        const int nn = lv_merge_at(U, n, ci, lo, hi, &cur);
+                        if (nn < 0) {
+                            ok = false;
+                        } else {
+                            n = nn;
+                            nxt = ci + 1 < n ? U.get(ci + 1) : NONE;
+                        }
+                    }
+                }
+                b = e;
+                e = en;
+            }
+        }
+    }
+    // overflowing columns go to the team tier; the others are emitted
+    if (live && !ok) push_overflow(Q, ST_DIRT, g);
+    emit_wave(P, c, live && ok, U, ok ? n : 0, P.erode, &Q.hdr->bumpC, P.offC, P.cntC, P.C);
+}
+
+// Team tiers: the columns on list `src` (ST_DIRT or ST_DIRW) by teams of T
+// lanes; a column whose slab list overflows goes on list `dst`, or with dst
+// < 0 to the arena tier.
 template <int T, int CAP>
-__global__ void __launch_bounds__(WG) k_direct(Pass Q, int wide) {
+__global__ void __launch_bounds__(WG) k_direct(Pass Q, int src, int dst) {
     constexpr int TPW = WG / T;
     __shared__ float2 lds[CAP * WG];
     __shared__ float2 chs[TPW][4 * T + 2];  // padded: the teams' buffers start on different banks
     __shared__ int32_t cps[TPW][DSPAN];
     __shared__ int nsh[WG];
     if (Q.hdr->abort) return;
-    const int64_t total = wide ? (int64_t)Q.hdr->novf[ST_DIRW] : Q.gcols;
+    const int64_t total = Q.hdr->novf[src];
     const int lane = threadIdx.x;
     const int lt = lane & (T - 1);
     const int tb = lane - lt;
@@ -2295,7 +2377,7 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int wide) {
     for (int64_t e0 = (int64_t)blockIdx.x * TPW; e0 < total; e0 += (int64_t)gridDim.x * TPW) {
         const int64_t e = e0 + tm;
         const int64_t ei = e < total ? e : e0;
-        const int64_t g = wide ? (int64_t)Q.ovf[(int64_t)ST_DIRW * Q.gcols + ei] : ei;
+        const int64_t g = Q.ovf[(int64_t)src * Q.gcols + ei];
         const int s = find_shape(Q, g);
         const Shape& S = Q.shapes[s];
         const int64_t c = g - Q.sbase[s];
@@ -2419,8 +2501,8 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int wide) {
             set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
         }
         if (live && lt == 0) {
-            if (fail && !wide) {
-                push_overflow(Q, ST_DIRW, g);
+            if (fail && dst >= 0) {
+                push_overflow(Q, dst, g);
             } else if (fail) {
                 arena_eval(P, 1, direct_bound(P, c), [&](const MemList& M, const MemList&) {
                     const int nn = direct_column(P, c, M);
@@ -3909,9 +3991,9 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     hipLaunchKernelGGL(k_col_gaps, dim3((unsigned)(p.gcols / (WG / GAP_LANES))), b, 0, s, p);
     DX_MARK(1);
     if (p.ndirect) {
-        const int64_t nt = (p.gcols + WG / DT - 1) / (WG / DT);
-        hipLaunchKernelGGL((k_direct<DT, DT_CAP>), dim3((unsigned)(nt < TEAM_BLOCKS ? nt : TEAM_BLOCKS)), b, 0, s, p, 0);
-        hipLaunchKernelGGL((k_direct<64, CAP_Z>), gf, b, 0, s, p, 1);
+        hipLaunchKernelGGL(k_direct1<D1_CAP>, g, b, 0, s, p);
+        hipLaunchKernelGGL((k_direct<DT, DT_CAP>), dim3(TEAM_BLOCKS), b, 0, s, p, (int)ST_DIRT, (int)ST_DIRW);
+        hipLaunchKernelGGL((k_direct<64, CAP_Z>), gf, b, 0, s, p, (int)ST_DIRW, -1);
     }
     DX_MARK(2);
     if (p.ntiles > 0 && p.nthin > 0) {
