@@ -2174,7 +2174,7 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int D1_CAP = 48;   // list capacity of the lane-per-column tier
+constexpr int D1_CAP = 32;   // list capacity of the lane-per-column tier
 constexpr int DT = 4;        // lanes per column of the team tier
 constexpr int DT_CAP = 24;   // its slab list capacity per lane
 constexpr int DSPAN = 2 * DIRECT_RMAX + 2;
@@ -2282,14 +2282,23 @@ __device__ int64_t direct_bound(const OpParams& P, int64_t c) {
 
 // Lane-per-column tier over every column of the pass's FAST_DIRECT shapes
 // (64 consecutive columns per wave).  Each lane walks its stencil row by row
-// (nearest rows first, a row's columns in memory order, the next column's
-// end pointer loaded ahead) and merges each stencil column's chords, loaded
-// eight at a time, into its list with a forward cursor; the list entry after
-// the cursor is kept loaded ahead, so the walk waits on LDS only after an
-// insertion or a second step for one chord.
+// and each row from the centre out (the widest chords first, which keeps the
+// partial union short), and merges each stencil column's chords, loaded
+// eight at a time a chunk ahead, into its list with a forward cursor.  The
+// lanes of a wave run in lockstep, so a case that is rare for one lane is
+// common for the wave; every case but one therefore runs without a branch: a
+// chord inside the interval under the cursor (after one predicated step),
+// one that extends that interval without reaching the next, and one past the
+// end of the list (appended).  The remaining chords (starting a new interval
+// inside the list, or joining several) are parked in a short per-lane
+// pending list and inserted when the stencil column ends (or the pending
+// list is full): the union does not depend on the order of its chords.
+constexpr int D1_PEND = 8;
+
 template <int CAP>
 __global__ void __launch_bounds__(WG) k_direct1(Pass Q) {
     __shared__ float2 lds[CAP * WG];
+    __shared__ float2 pend[D1_PEND * WG];
     if (Q.hdr->abort) return;
     const int64_t g = (int64_t)blockIdx.x * WG + threadIdx.x;
     const int s = find_shape(Q, g < Q.gcols ? g : Q.gcols - 1);
@@ -2299,9 +2308,19 @@ __global__ void __launch_bounds__(WG) k_direct1(Pass Q) {
     if (!__any(live)) return;
     const OpParams P = make_op(Q, S);
     const LdsList U{&lds[threadIdx.x], CAP};
+    const LdsList Pd{&pend[threadIdx.x], D1_PEND};
     const float2 NONE = make_float2(DX_INF, DX_INF);
-    int n = 0;
+    int n = 0, np = 0;
     bool ok = live;
+    // insert the pending chords into the list
+    auto flush = [&]() {
+        for (int p = 0; p < np && ok; ++p) {
+            const float2 v = Pd.get(p);
+            const int nn = lv_insert(U, n, v.x, v.y);
+            if (nn < 0) ok = false; else n = nn;
+        }
+        np = 0;
+    };
     if (live) {
         int x, y;
         col_xy(P, c, &x, &y);
@@ -2311,44 +2330,97 @@ __global__ void __launch_bounds__(WG) k_direct1(Pass Q) {
             const int dy2 = dy * dy;
             const int w = sten_width(P.d2max, dy2);
             if (yy < 0 || yy >= P.ny || w < 0) continue;
-            const int x0 = max(x - w, 0), x1 = min(x + w, P.nx - 1);
             const int64_t rb = (int64_t)yy * P.nx;
-            int64_t b = gld(&P.col_ptr[rb + x0]);
-            int64_t e = gld(&P.col_ptr[rb + x0 + 1]);
-            for (int xx = x0; xx <= x1 && ok; ++xx) {
-                const int64_t en = xx < x1 ? gld(&P.col_ptr[rb + xx + 2]) : e;  // ahead
-                const int dx = xx - x;
-                const float h = gld(&P.H[dx * dx + dy2]);
+            // the row's stencil columns in visit order (x, x - 1, x + 1, ...),
+            // eight items a chunk; the next chunk's pointers and items are
+            // loaded while the current one is merged
+            int v = 0, k0 = 0;
+            int64_t b = gld(&P.col_ptr[rb + x]), e = gld(&P.col_ptr[rb + x + 1]);
+            float h = gld(&P.H[dy2]);
+            float2 cq[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cq[q] = item_chord(P.z, b, (int)(e - b), q, P.erode, h);
+            int ci = 0;
+            float2 cur = NONE, nxt = NONE;
+            while (v <= 2 * w && ok) {
                 const int m = (int)(e - b);
-                const int cnt = P.erode ? m + 1 : m;
-                int ci = 0;
-                float2 cur = n > 0 ? U.get(0) : NONE;
-                float2 nxt = n > 1 ? U.get(1) : NONE;
-                for (int k0 = 0; k0 < cnt && ok; k0 += 8) {
-                    float2 cq[8];
+                int nv = v, nk = k0 + 8;
+                int64_t nb = b, ne = e;
+                float nhh = h;
+                if (nk >= (P.erode ? m + 1 : m)) {
+                    nk = 0;
+                    for (nv = v + 1; nv <= 2 * w; ++nv) {
+                        const int xx = visit_col(x, nv);
+                        if (xx >= 0 && xx < P.nx) break;
+                    }
+                    if (nv <= 2 * w) {
+                        const int xx = visit_col(x, nv);
+                        nb = gld(&P.col_ptr[rb + xx]);
+                        ne = gld(&P.col_ptr[rb + xx + 1]);
+                        nhh = gld(&P.H[(xx - x) * (xx - x) + dy2]);
+                    }
+                }
+                float2 pq[8];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) cq[q] = item_chord(P.z, b, m, k0 + q, P.erode, h);
+                for (int q = 0; q < 8; ++q)
+                    pq[q] = nv <= 2 * w ? item_chord(P.z, nb, (int)(ne - nb), nk + q, P.erode, nhh)
+                                        : make_float2(DX_INF, -DX_INF);
+                if (k0 == 0) {  // a new stencil column: the cursor restarts
+                    ci = 0;
+                    cur = n > 0 ? U.get(0) : NONE;
+                    nxt = n > 1 ? U.get(1) : NONE;
+                }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const float lo = cq[q].x, hi = cq[q].y;
-                        if (!ok || !(lo <= hi)) continue;  // past the column's last item
+                for (int q = 0; q < 8; ++q) {
+                    const float lo = cq[q].x, hi = cq[q].y;
+                    // chords past the column's last item are empty (lo > hi)
+                    const bool val = ok && lo <= hi;
+                    // one predicated step of the cursor: U[ci] = cur is the first
+                    // interval not ending below lo, nxt = U[ci + 1] (NONE past the end)
+                    const bool adv = val && cur.y < lo;
+                    const float2 t = U.get(min(ci + 2, CAP - 1));
+                    ci += adv ? 1 : 0;
+                    cur = adv ? nxt : cur;
+                    nxt = adv ? (ci + 1 < n ? t : NONE) : nxt;
+                    if (val && cur.y < lo) {  // more steps (rare)
                         while (cur.y < lo) {
                             ++ci;
                             cur = nxt;
                             nxt = ci + 1 < n ? U.get(ci + 1) : NONE;
                         }
-                        if (cur.x <= lo && hi <= cur.y) continue;  // inside
-                        const int nn = lv_merge_at(U, n, ci, lo, hi, &cur);
-                        if (nn < 0) {
-                            ok = false;
-                        } else {
-                            n = nn;
-                            nxt = ci + 1 < n ? U.get(ci + 1) : NONE;
-                        }
+                    }
+                    // classify: inside cur; extends cur without reaching nxt;
+                    // past the end (appended); anything else (parked)
+                    const bool inside = cur.x <= lo && hi <= cur.y;
+                    const bool atend = ci >= n;
+                    const bool ext = val && !inside && !atend && cur.x <= hi && hi < nxt.x;
+                    const bool app = val && atend && n < CAP;
+                    const bool park = val && !inside && !atend && !ext;
+                    if (val && atend && n >= CAP) ok = false;
+                    const float2 wv = app ? make_float2(lo, hi)
+                                          : make_float2(fminf(cur.x, lo), fmaxf(cur.y, hi));
+                    const int wi = app ? n : ci;
+                    if (ext || app) U.set(wi, wv);
+                    cur = (ext || app) ? wv : cur;
+                    ci = wi;
+                    n += app ? 1 : 0;
+                    if (park) Pd.set(np, make_float2(lo, hi));
+                    np += park ? 1 : 0;
+                    if (np == D1_PEND) {  // the pending list is full (rare)
+                        flush();
+                        ci = 0;
+                        cur = n > 0 ? U.get(0) : NONE;
+                        nxt = n > 1 ? U.get(1) : NONE;
                     }
                 }
-                b = e;
-                e = en;
+                if (nk == 0 && np > 0) flush();  // the stencil column ends
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cq[q] = pq[q];
+                v = nv;
+                k0 = nk;
+                b = nb;
+                e = ne;
+                h = nhh;
             }
         }
     }
@@ -2421,51 +2493,104 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int src, int dst) {
                 const int x0 = max(x - w, 0), x1 = min(x + w, P.nx - 1);
                 const int64_t rb = (int64_t)yy * P.nx + x0;
                 const int64_t zb = gld(&P.col_ptr[rb]);
+                wave_lds_sync();  // the last row's pointers are read
                 for (int j = lt; j <= x1 - x0 + 1; j += T) cps[tm][j] = (int32_t)(gld(&P.col_ptr[rb + j]) - zb);
                 wave_lds_sync();
-                for (int v = 0; v <= 2 * w && !fail; ++v) {
+                // the row's chunks in order: stencil columns in visit order,
+                // 4T items each; the next chunk's items are loaded while the
+                // current one is merged
+                int cv = -1, cm = 0;
+                int64_t cb = 0;
+                float chh = 0.0f;
+                for (int v = 0; v <= 2 * w; ++v) {
                     const int xx = visit_col(x, v);
                     if (xx < x0 || xx > x1) continue;
-                    const int dx = xx - x;
-                    const float h = gld(&P.H[dx * dx + dy2]);
                     const int o = cps[tm][xx - x0];
-                    const int m = cps[tm][xx - x0 + 1] - o;
-                    const int64_t b = zb + o;
-                    const int cnt = P.erode ? m + 1 : m;
-                    // merge cursor: U[ci] = cur is the first interval not ending below
-                    // the chords still to come (ci = n: none)
-                    int ci = 0;
-                    float2 cur = n > 0 ? U.get(0) : make_float2(DX_INF, DX_INF);
-                    for (int k0 = 0; k0 < cnt && !fail; k0 += 4 * T) {
-                        float2 q4[4];
+                    cm = cps[tm][xx - x0 + 1] - o;
+                    if (!P.erode && cm == 0) continue;  // an empty column adds nothing
+                    cb = zb + o;
+                    chh = gld(&P.H[(xx - x) * (xx - x) + dy2]);
+                    cv = v;
+                    break;
+                }
+                int ck = 0;
+                float2 q4[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) q4[q] = item_chord(P.z, b, m, k0 + q * T + lt, P.erode, h);
+                for (int q = 0; q < 4; ++q)
+                    q4[q] = cv >= 0 ? item_chord(P.z, cb, cm, q * T + lt, P.erode, chh)
+                                    : make_float2(DX_INF, -DX_INF);
+                // merge cursor: U[ci] = cur is the first interval not ending below
+                // the chords still to come in this stencil column (ci = n: none);
+                // nxt = U[ci + 1], loaded ahead
+                int ci = 0;
+                float2 cur = make_float2(DX_INF, DX_INF), nxt = cur;
+                while (cv >= 0 && !fail) {
+                    int nv = cv, nk = ck + 4 * T, nm = cm;
+                    int64_t nb = cb;
+                    float nh = chh;
+                    if (nk >= (P.erode ? cm + 1 : cm)) {
+                        nk = 0;
+                        nv = -1;
+                        for (int v = cv + 1; v <= 2 * w; ++v) {
+                            const int xx = visit_col(x, v);
+                            if (xx < x0 || xx > x1) continue;
+                            const int o = cps[tm][xx - x0];
+                            nm = cps[tm][xx - x0 + 1] - o;
+                            if (!P.erode && nm == 0) continue;
+                            nb = zb + o;
+                            nh = gld(&P.H[(xx - x) * (xx - x) + dy2]);
+                            nv = v;
+                            break;
+                        }
+                    }
+                    float2 p4[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) chs[tm][q * T + lt] = q4[q];
-                        wave_lds_sync();
-                        // the chunk in blocks of SB chords, each read into registers at once
-                        constexpr int SB = 4 * T < 16 ? 4 * T : 16;
-                        for (int u0 = 0; u0 < 4 * T; u0 += SB) {
-                            float2 cq[SB];
+                    for (int q = 0; q < 4; ++q)
+                        p4[q] = nv >= 0 ? item_chord(P.z, nb, nm, nk + q * T + lt, P.erode, nh)
+                                        : make_float2(DX_INF, -DX_INF);
+                    if (ck == 0) {  // a new stencil column: the cursor restarts
+                        ci = 0;
+                        cur = n > 0 ? U.get(0) : make_float2(DX_INF, DX_INF);
+                        nxt = n > 1 ? U.get(1) : make_float2(DX_INF, DX_INF);
+                    }
 #pragma unroll
-                            for (int u = 0; u < SB; ++u) cq[u] = chs[tm][u0 + u];
+                    for (int q = 0; q < 4; ++q) chs[tm][q * T + lt] = q4[q];
+                    wave_lds_sync();
+                    // the chunk in blocks of SB chords, each read into registers at once
+                    constexpr int SB = 4 * T < 16 ? 4 * T : 16;
+                    for (int u0 = 0; u0 < 4 * T; u0 += SB) {
+                        float2 cq[SB];
 #pragma unroll
-                            for (int u = 0; u < SB; ++u) {
-                                // chords past the column's last item are empty
-                                const float lo = fmaxf(cq[u].x, zs), hi = fminf(cq[u].y, ze);
-                                if (!ok || !(lo <= hi)) continue;
-                                while (cur.y < lo) {
-                                    ++ci;
-                                    cur = ci < n ? U.get(ci) : make_float2(DX_INF, DX_INF);
-                                }
-                                if (cur.x <= lo && hi <= cur.y) continue;  // inside
-                                const int nn = lv_merge_at(U, n, ci, lo, hi, &cur);
-                                if (nn < 0) ok = false; else n = nn;
+                        for (int u = 0; u < SB; ++u) cq[u] = chs[tm][u0 + u];
+#pragma unroll
+                        for (int u = 0; u < SB; ++u) {
+                            // chords past the column's last item are empty
+                            const float lo = fmaxf(cq[u].x, zs), hi = fminf(cq[u].y, ze);
+                            if (!ok || !(lo <= hi)) continue;
+                            while (cur.y < lo) {
+                                ++ci;
+                                cur = nxt;
+                                nxt = ci + 1 < n ? U.get(ci + 1) : make_float2(DX_INF, DX_INF);
+                            }
+                            if (cur.x <= lo && hi <= cur.y) continue;  // inside
+                            const int nn = lv_merge_at(U, n, ci, lo, hi, &cur);
+                            if (nn < 0) {
+                                ok = false;
+                            } else {
+                                n = nn;
+                                nxt = ci + 1 < n ? U.get(ci + 1) : make_float2(DX_INF, DX_INF);
                             }
                         }
-                        wave_lds_sync();  // the buffer is read before the next chunk is written
-                        fail = team_any<T>(!ok);
                     }
+                    wave_lds_sync();  // the buffer is read before the next chunk is written
+                    fail = team_any<T>(!ok);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) q4[q] = p4[q];
+                    cv = nv;
+                    ck = nk;
+                    cm = nm;
+                    cb = nb;
+                    chh = nh;
                 }
             }
         }
