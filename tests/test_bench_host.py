@@ -69,18 +69,28 @@ class _Dx:
 
 
 def test_dominant_stage_counts_its_replay():
-    """The dominant stage is the costliest by main plus replay time; frac is
-    its main kernel's, stage_frac charges the replay too."""
+    """The dominant stage is the costliest by main plus replay time; the
+    reported kernel is the launch group carrying >= 90% of it, or both."""
     st = {"row_offset": 100, "neighbour": 100, "seeds": 1000, "result": 100}
+    b = bench.kernel_bytes("row_offset", 64, 500, st)
     per = {k: 0.0 for k in _Dx.PROFILE_STAGES}
     per.update(row_offset=2.0, row_offset_replay=6.0, y_union=5.0, y_union_replay=0.5)
     roof = bench.stage_roofline(_Dx, per, [(500, st), (500, st)], 64)
-    assert roof["stage"] == "row_offset" and roof["kernel"] == "k_row_offset"
-    assert roof["kernel_ms"] == 1.0 and roof["stage_ms"] == 4.0
-    b = bench.kernel_bytes("row_offset", 64, 500, st)
+    assert roof["stage"] == "row_offset" and roof["kernel"] == "k_row_offset + k_row_offset_fb"
+    assert roof["kernel_ms"] == 4.0 and roof["stage_ms"] == 4.0
     assert roof["bytes_per_launch"] == b
-    assert abs(roof["frac"] - b / 1e-3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-5
-    assert abs(roof["stage_frac"] - roof["frac"] / 4.0) < 1e-5
+    assert abs(roof["frac"] - b / 4e-3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-5
+    assert abs(roof["stage_frac"] - roof["frac"]) < 1e-5
+    # the replay does the stage's work: it is the kernel
+    per.update(row_offset=0.2, row_offset_replay=7.8)
+    roof = bench.stage_roofline(_Dx, per, [(500, st), (500, st)], 64)
+    assert roof["kernel"] == "k_row_offset_fb" and roof["kernel_ms"] == 3.9
+    assert abs(roof["frac"] - b / 3.9e-3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-5
+    assert abs(roof["stage_frac"] - b / 4e-3 / 1e9 / bench.HBM_PEAK_GBS) < 1e-5
+    # the main kernel does it
+    per.update(row_offset=7.8, row_offset_replay=0.2)
+    roof = bench.stage_roofline(_Dx, per, [(500, st), (500, st)], 64)
+    assert roof["kernel"] == "k_row_offset" and roof["kernel_ms"] == 3.9
 
 
 def test_step_bytes():
