@@ -2778,8 +2778,8 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
 // (+inf, -inf), so that MA = +inf; outside the grid: (-inf, +inf), which
 // changes nothing; a column of two or more intervals: NaN), then each wave
 // evaluates THIN_TY / 4 output rows, one lane per column.  An output column
-// whose stencil holds a longer column is marked general (gen = 1) and left
-// to the general kernels; k_thin_spread marks the columns those must
+// whose stencil holds a longer column is marked general (GEN_GENERAL) and
+// left to the general kernels; k_fast_spread marks the columns those must
 // evaluate for it (need[]).
 constexpr int THIN_T = 256;
 
