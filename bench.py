@@ -942,9 +942,9 @@ def run_serving(args, dx, torch):
         return out
 
     # warm the library (LUTs, kernel code) and measure the plain service rate
-    serve.Server(eng, pool, mode="plain").run(make(4, None, 99))
+    serve.Server(eng, pool, mode="plain", keep_results=False).run(make(4, None, 99))
     sat_reqs = make(args.serve_requests, None, 2)  # the same mix as the loaded runs
-    sat_done = serve.Server(eng, pool, mode="plain").run(sat_reqs)
+    sat_done = serve.Server(eng, pool, mode="plain", keep_results=False).run(sat_reqs)
     sat = serve.summarize(sat_done)
     print(f"[bench] saturation run {sat}", file=sys.stderr, flush=True)
     # service time of each request of the plain run (one request on the GPU at
@@ -972,7 +972,8 @@ def run_serving(args, dx, torch):
         reqs = make(args.serve_requests, f * mu, 2)
         row = {"load": f, "rate_req_s": f * mu}
         for mode in ("continuous", "plain"):
-            srv = serve.Server(eng, pool, mode=mode, max_batch=16, slots=2)
+            srv = serve.Server(eng, pool, mode=mode, max_batch=16, slots=2, keep_results=False,
+                               policy=args.serve_policy)
             row[mode] = serve.summarize(srv.run(reqs))
             print(f"[bench] load {f}: {mode} {row[mode]}", file=sys.stderr, flush=True)
         table.append(row)
@@ -992,6 +993,7 @@ def run_serving(args, dx, torch):
         "data": "synthetic",
         "config": {"workload": f"c5: {WORKLOADS['c5']['desc']}",
                    "requests_per_load": args.serve_requests, "max_batch": 16, "slots": 2,
+                   "policy": args.serve_policy,
                    "budget_bytes": 64 << 30},
         "serving": {"saturation_req_s_plain": mu, "loads": table, "slowest_plain": slowest,
                     "service_ms_total_plain": round(sum(v["service_ms"] for v in svc), 1)},
@@ -1011,6 +1013,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-policy", default="fifo", choices=["fifo", "sjf"],
+                    help="c5 continuous server's admission order")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one elementwise kernel over this many MiB (reads and writes "
                          "a known number of bytes: the reference for HBM byte counters)")

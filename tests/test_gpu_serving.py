@@ -85,3 +85,35 @@ def test_admission_rejects_oversized(engine):
     assert all(d.status == -4 for d in done)
     summary = serve.summarize(done)
     assert summary["completed"] == 0 and summary["rejected"] == 6
+
+
+def test_admission_counts_held_memory(engine):
+    """The budget covers slot workspaces and every output still held: at the
+    end of a run the server holds exactly its slot workspaces plus every
+    result (keep_results) or each session's last result (otherwise).  With
+    results dropped as their session moves on, a budget of about two
+    requests' footprint serves the whole stream without passing it."""
+    import paper_1804_08968_amd as dx
+    from paper_1804_08968_amd import serve
+    _, pool = _pool(dx)
+    reqs = _requests(serve, 12, None, 7)
+    probe = serve.Server(engine, pool)
+    for g in pool:
+        g.nseg_cached = g.nseg
+    fps = [probe.footprint(pool[q.shape], q.r, q.op) for q in reqs if not q.chain]
+    budget = int(2.6 * max(fps))
+    print(f"[case] serving budget {budget}", flush=True)
+    for keep in (False, True):
+        srv = serve.Server(engine, pool, budget_bytes=budget, max_batch=4, slots=2, keep_results=keep)
+        done = srv.run(reqs)
+        ok = [d for d in done if d.status == 0]
+        assert all(d.status in (0, -4) for d in done)
+        assert 0 < srv.peak_bytes <= budget
+        ws = sum(w.numel() for w in srv.ws if w is not None)
+        if keep:
+            held = sum(serve.Server._grid_bytes(d.result) for d in ok)
+            assert srv.held_bytes == ws + held, (srv.held_bytes, ws, held)
+        else:
+            # every request served; only the sessions' last results stay
+            assert len(ok) == len(done) and all(d.result is None for d in done)
+            assert ws < srv.held_bytes <= srv.peak_bytes
