@@ -1535,7 +1535,7 @@ __device__ void arena_eval(const OpParams& P, int nl, int64_t bound, F eval) {
 // difference (0 if that is 0: equal floats), so that it bounds every exact
 // gap from above; -1 marks an empty column.  K1 reads these per-column arrays with coalesced loads
 // instead of two scattered item loads per visited column.
-constexpr int GAP_LANES = 16;
+constexpr int GAP_LANES = 4;
 
 __global__ void __launch_bounds__(WG) k_col_gaps(Pass Q) {
     if (Q.hdr->abort) return;
