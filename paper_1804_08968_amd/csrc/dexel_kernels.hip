@@ -291,15 +291,19 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
     float prevy = -DX_INF;              // E: end of the previous item
     float2 cur = make_float2(0.f, 0.f);  // the open output interval
     int i = 0, k = 0;
-    bool open = false, bad = false;
+    // per-lane flags as integers, so that the divergent loops around push()
+    // carry them in vector registers instead of merging lane masks at every
+    // branch; push() itself runs without a branch but for the one store
+    int open = 0, bad = 0;
     auto push = [&](float2 v) {
-        const bool ext = open && v.x <= cur.y;
-        if (open && !ext) {
-            if (k <= top + i && k < U.cap) U.set(k, cur); else bad = true;
-            ++k;
-        }
+        const int ext = open & (v.x <= cur.y ? 1 : 0);
+        const int emit = open & (ext ^ 1);
+        const int room = (k <= top + i ? 1 : 0) & (k < U.cap ? 1 : 0);
+        if (emit & room) U.set(k, cur);
+        bad |= emit & (room ^ 1);
+        k += emit;
         cur = ext ? make_float2(cur.x, fmaxf(cur.y, v.y)) : v;
-        open = true;
+        open = 1;
     };
     auto step = [&](const float2 it, int j) {
         if (j >= cnt) return;
