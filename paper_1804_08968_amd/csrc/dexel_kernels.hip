@@ -2787,11 +2787,13 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
 // evaluate for it (need[]).
 constexpr int THIN_T = 256;
 
-// min / max by comparison: the staged values hold no NaN that matters (the
-// thin filter's NaN markers only reach columns whose result is discarded), so
-// IEEE minNum / maxNum, which also quiet the operands, are not needed.
-__device__ __forceinline__ float mn(float a, float b) { return a < b ? a : b; }
-__device__ __forceinline__ float mx(float a, float b) { return a > b ? a : b; }
+// min / max as the median of the two and an infinity (one v_med3_f32, no
+// operand canonicalisation): the staged values hold no NaN that matters (the
+// thin filter's NaN markers only reach columns whose result is discarded, and
+// it detects them by its own test), so IEEE minNum / maxNum semantics, and
+// the compare-and-select pair, are not needed.
+__device__ __forceinline__ float mn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -DX_INF); }
+__device__ __forceinline__ float mx(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, DX_INF); }
 
 // One stencil row of the tiled filters: f(v, hh) for dx = -w .. w with
 // v = row[dx] and hh = hr[dx * dx], the LDS loads of four points issued
