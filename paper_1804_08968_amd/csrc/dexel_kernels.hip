@@ -73,6 +73,14 @@ __device__ __forceinline__ void gst(int64_t* p, int64_t v) { *(DX_GLOBAL int64_t
 __device__ __forceinline__ void gst(int32_t* p, int32_t v) { *(DX_GLOBAL int32_t*)p = v; }
 __device__ __forceinline__ void gst(uint8_t* p, uint8_t v) { *(DX_GLOBAL uint8_t*)p = v; }
 
+// min / max as the median of the two and an infinity (one v_med3_f32, no
+// operand canonicalisation, unlike fminf / fmaxf): every value these kernels
+// compare is a float endpoint, finite or infinite, so IEEE minNum / maxNum
+// semantics are not needed; the thin filter's NaN markers only reach columns
+// whose result is discarded, and it detects them by its own test.
+__device__ __forceinline__ float mn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -DX_INF); }
+__device__ __forceinline__ float mx(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, DX_INF); }
+
 // Per-column view used by the algorithms: one shape's fields plus the
 // shared buffers.
 struct OpParams {
@@ -184,8 +192,8 @@ __device__ int lv_insert(const L& U, int n, float lo, float hi) {
         if (U.get(m).x <= hi) l = m + 1; else h = m;
     }
     int j = l - 1;
-    float nlo = fminf(lo, ui.x);
-    float nhi = fmaxf(hi, U.get(j).y);
+    float nlo = mn(lo, ui.x);
+    float nhi = mx(hi, U.get(j).y);
     U.set(i, make_float2(nlo, nhi));
     int sh = j - i;
     if (sh > 0)
@@ -211,7 +219,7 @@ __device__ int lv_insert_fwd(const L& U, int n, float lo, float hi, int* hint) {
     if (ui.x <= lo && hi <= ui.y) return n;
     int j = i;
     while (j + 1 < n && U.get(j + 1).x <= hi) ++j;
-    U.set(i, make_float2(fminf(lo, ui.x), fmaxf(hi, U.get(j).y)));
+    U.set(i, make_float2(mn(lo, ui.x), mx(hi, U.get(j).y)));
     int sh = j - i;
     if (sh > 0)
         for (int k = j + 1; k < n; ++k) U.set(k - sh, U.get(k));
@@ -302,7 +310,7 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
         if (emit & room) U.set(k, cur);
         bad |= emit & (room ^ 1);
         k += emit;
-        cur = ext ? make_float2(cur.x, fmaxf(cur.y, v.y)) : v;
+        cur = ext ? make_float2(cur.x, mx(cur.y, v.y)) : v;
         open = 1;
     };
     auto step = [&](const float2 it, int j) {
@@ -457,7 +465,7 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
         if (E && m == 1 && n == 2) {
             const float2 u0 = U.get(0), u1 = U.get(1);
             if (u0.x == -DX_INF && u1.y == DX_INF) {
-                const float lo = fmaxf(u0.y, ec4.x + h), hi = fminf(u1.x, ec4.w - h);
+                const float lo = mx(u0.y, ec4.x + h), hi = mn(u1.x, ec4.w - h);
                 if (hi <= lo) {
                     U.set(0, make_float2(-DX_INF, DX_INF));
                     n = 1;
@@ -583,7 +591,7 @@ __device__ int k1b_column(const OpParams& P, int64_t c, const L& L0, const L& L1
             int i = 0, j = 0, k = 0;
             while (i < n && j < m) {
                 float2 a = S.get(i), bb = gld(&J[j]);
-                float lo = fmaxf(a.x, bb.x), hi = fminf(a.y, bb.y);
+                float lo = mx(a.x, bb.x), hi = mn(a.y, bb.y);
                 if (lo < hi) {
                     if (k >= D.cap) return -1;
                     D.set(k++, make_float2(lo, hi));
@@ -668,10 +676,10 @@ __device__ __forceinline__ SeedSink sink_make(float2* dlo, uint8_t* tlo, float2*
 }
 
 __device__ __forceinline__ void hull_add(float4* h, float p, float q, float h1) {
-    h->x = fminf(h->x, p - h1);
-    h->y = fmaxf(h->y, q + h1);
-    h->z = fminf(h->z, p);
-    h->w = fmaxf(h->w, q);
+    h->x = mn(h->x, p - h1);
+    h->y = mx(h->y, q + h1);
+    h->z = mn(h->z, p);
+    h->w = mx(h->w, q);
 }
 
 __device__ __forceinline__ void k2_emit(float p, float q, float h1, int t, SeedSink& o) {
@@ -757,7 +765,7 @@ __device__ __forceinline__ void k2_segment(Ptr Ip, int ni, float2 i0, const L& U
                 q = u.x;
                 cand = u.x > p;
                 more = u.y < e;
-                pn = fmaxf(p, u.y);
+                pn = mx(p, u.y);
                 ++idx;
             }
         } else {
@@ -982,7 +990,7 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
             // widest half-width at this dy); skip the group when the tighter
             // of the two bounds is inside the union.
             if (h4.x > h4.y) continue;
-            const float hlo = fmaxf(h4.x, h4.z - hd), hhi = fminf(h4.y, h4.w + hd);
+            const float hlo = mx(h4.x, h4.z - hd), hhi = mn(h4.y, h4.w + hd);
             if (n <= 2) {
                 if (n >= 1 && u0.x <= hlo && hhi <= u0.y) continue;
                 if (n == 2 && u1.x <= hlo && hhi <= u1.y) continue;
@@ -1065,13 +1073,13 @@ __device__ int64_t k3_bound(const OpParams& P, int64_t c) {
 
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    for (int d = 32; d > 0; d >>= 1) v = mn(v, __shfl_xor(v, d, 64));
     return v;
 }
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
-    for (int d = 32; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    for (int d = 32; d > 0; d >>= 1) v = mx(v, __shfl_xor(v, d, 64));
     return v;
 }
 
@@ -1097,8 +1105,8 @@ __device__ __forceinline__ float2 lane_slab(float zmin, float zmax) {
 
 __device__ __forceinline__ void widen(float* zmin, float* zmax, float v) {
     if (v > -DX_INF && v < DX_INF) {
-        *zmin = fminf(*zmin, v);
-        *zmax = fmaxf(*zmax, v);
+        *zmin = mn(*zmin, v);
+        *zmax = mx(*zmax, v);
     }
 }
 
@@ -1130,7 +1138,7 @@ __device__ int k1b_slab(const OpParams& P, int64_t c, float zs, float ze, const 
             while (i < n && j < m) {
                 const float2 a = S.get(i), bb = gld(&J[j]);
                 if (bb.x > ze) break;
-                const float lo = fmaxf(a.x, bb.x), hi = fminf(a.y, bb.y);
+                const float lo = mx(a.x, bb.x), hi = mn(a.y, bb.y);
                 if (lo < hi) {
                     if (k >= D.cap) return -1;
                     D.set(k++, make_float2(lo, hi));
@@ -1173,7 +1181,7 @@ __device__ int k1_slab_e(const OpParams& P, int64_t c, float zs, float ze, const
             const float2 it = col_item<E>(P.z, b, m, k);
             const float lo = it.x - h, hi = it.y + h;
             if (lo > ze) break;
-            n = lv_insert_fwd(U, n, fmaxf(lo, zs), fminf(hi, ze), &hint);
+            n = lv_insert_fwd(U, n, mx(lo, zs), mn(hi, ze), &hint);
             if (n < 0) return -1;
         }
         if (n == 1 && U.get(0).x <= zs && U.get(0).y >= ze) break;
@@ -1211,7 +1219,7 @@ __device__ int k2_slab_e(const OpParams& P, int64_t c, float zs, float ze, Ptr I
             for (int k = l; k < cnt; ++k) {
                 const float2 sg = col_item<E>(P.z, b, m, k);
                 if (sg.x > ze) break;
-                k2_segment(Ip, ni, i0, U, &n, fmaxf(sg.x, zs), fminf(sg.y, ze), h1, t, o);
+                k2_segment(Ip, ni, i0, U, &n, mx(sg.x, zs), mn(sg.y, ze), h1, t, o);
             }
         }
     }
@@ -1241,7 +1249,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
     const int n0 = gld(&P.cntA[c]);
     for (int i = 0; i < n0 && ok; ++i) {
         const float2 v = gld(&V[i]);
-        const float lo = fmaxf(v.x, zs), hi = fminf(v.y, ze);
+        const float lo = mx(v.x, zs), hi = mn(v.y, ze);
         if (lo > hi) continue;
         if (n >= U.cap) ok = false; else U.set(n++, make_float2(lo, hi));
     }
@@ -1256,7 +1264,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
         __syncthreads();
         if (busy) {
             const float2 e = env[dy];
-            const float lo = fmaxf(e.x, zs), hi = fminf(e.y, ze);
+            const float lo = mx(e.x, zs), hi = mn(e.y, ze);
             if (lo > hi) {
                 busy = false;
             } else {
@@ -1273,8 +1281,8 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
             const int64_t cc = (int64_t)yy * P.nx + x;
             const float4 h4 = gld(&P.hullB[2 * cc + (k & 1)]);
             if (h4.x > h4.y) continue;
-            const float hlo = fmaxf(fmaxf(h4.x, h4.z - hd), zs);
-            const float hhi = fminf(fminf(h4.y, h4.w + hd), ze);
+            const float hlo = mx(mx(h4.x, h4.z - hd), zs);
+            const float hhi = mn(mn(h4.y, h4.w + hd), ze);
             if (hlo > hhi) continue;
             const SeedSpans sp = seed_spans(P, cc);
             const float2* sv = (k & 1) ? sp.s[1] : sp.s[0];
@@ -1319,7 +1327,7 @@ __device__ int k3_slab(const OpParams& P, int64_t c, float zs, float ze, const L
                     if (j + q >= nb) break;
                     const float h = tab[tq[q]];
                     if (h < 0.0f) continue;
-                    const float lo = fmaxf(pq[q].x - h, zs), hi = fminf(pq[q].y + h, ze);
+                    const float lo = mx(pq[q].x - h, zs), hi = mn(pq[q].y + h, ze);
                     if (lo > hi) continue;
                     n = lv_insert(U, n, lo, hi);
                     if (n < 0) {
@@ -1561,15 +1569,15 @@ __global__ void __launch_bounds__(WG) k_col_gaps(Pass Q) {
         if (P.erode) {
             for (int i = l; i < m; i += GAP_LANES) {
                 const float2 v = gld(&P.z[b + i]);
-                G = fmaxf(G, v.y - v.x);
+                G = mx(G, v.y - v.x);
             }
         } else {
             for (int i = l; i + 1 < m; i += GAP_LANES)
-                G = fmaxf(G, gld(&P.z[b + i + 1]).x - gld(&P.z[b + i]).y);
+                G = mx(G, gld(&P.z[b + i + 1]).x - gld(&P.z[b + i]).y);
         }
     }
 #pragma unroll
-    for (int d = GAP_LANES / 2; d > 0; d >>= 1) G = fmaxf(G, __shfl_xor(G, d, 64));
+    for (int d = GAP_LANES / 2; d > 0; d >>= 1) G = mx(G, __shfl_xor(G, d, 64));
     if (valid && l == 0) gst(&Q.shapes[s].gap[c], m == 0 ? -1.f : (G > 0.f ? nextafterf(G, DX_INF) : 0.f));
 }
 
@@ -1666,7 +1674,7 @@ __global__ void __launch_bounds__(WG) k_row_offset_heavy(Pass Q) {
         for (int l = 0; l < WG; ++l)
             for (int i = 0; i < nsh[l]; ++i) {
                 const float2 v = lds[i * WG + l];
-                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = mx(out[k - 1].y, v.y);
                 else out[k++] = v;
             }
         MemList M{out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
@@ -1796,7 +1804,7 @@ __global__ void __launch_bounds__(WG) k_neighbour_heavy(Pass Q) {
             const int base = rsh[l] ? CAP_Z * WG : 0;
             for (int i = 0; i < nsh[l]; ++i) {
                 const float2 v = lds[base + i * WG + l];
-                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = mx(out[k - 1].y, v.y);
                 else out[k++] = v;
             }
         }
@@ -2051,8 +2059,8 @@ __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
                     if (yy < 0 || yy >= P.ny) continue;
                     const float4 h4 = gld(&P.hullB[2 * ((int64_t)yy * P.nx + x) + (k & 1)]);
                     if (h4.x > h4.y) continue;
-                    acc.x = fminf(acc.x, fmaxf(h4.x, h4.z - hd));
-                    acc.y = fmaxf(acc.y, fminf(h4.y, h4.w + hd));
+                    acc.x = mn(acc.x, mx(h4.x, h4.z - hd));
+                    acc.y = mx(acc.y, mn(h4.y, h4.w + hd));
                 }
                 env[dy] = acc;
             }
@@ -2093,7 +2101,7 @@ __global__ void __launch_bounds__(WG) k_union_heavy(Pass Q) {
         for (int l = 0; l < WG; ++l)
             for (int i = 0; i < nsh[l]; ++i) {
                 const float2 v = lds[i * WG + l];
-                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = fmaxf(out[k - 1].y, v.y);
+                if (k > 0 && v.x <= out[k - 1].y) out[k - 1].y = mx(out[k - 1].y, v.y);
                 else out[k++] = v;
             }
         MemList M{(float2*)out, (int)min<int64_t>(tot > 0 ? tot : 1, 0x7fffffff)};
@@ -2149,14 +2157,14 @@ __device__ __forceinline__ float team_bound(float zmin, float zmax, int k) {
 template <int T>
 __device__ __forceinline__ float team_min(float v) {
 #pragma unroll
-    for (int d = T / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    for (int d = T / 2; d > 0; d >>= 1) v = mn(v, __shfl_xor(v, d, 64));
     return v;
 }
 
 template <int T>
 __device__ __forceinline__ float team_max(float v) {
 #pragma unroll
-    for (int d = T / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    for (int d = T / 2; d > 0; d >>= 1) v = mx(v, __shfl_xor(v, d, 64));
     return v;
 }
 
@@ -2206,7 +2214,7 @@ __device__ int lv_merge_at(const L& U, int n, int i, float lo, float hi, float2*
         hj = v.y;
         ++j;
     }
-    *cur = make_float2(fminf(lo, ui.x), fmaxf(hi, hj));
+    *cur = make_float2(mn(lo, ui.x), mx(hi, hj));
     U.set(i, *cur);
     const int sh = j - i;
     if (sh > 0)
@@ -2402,7 +2410,7 @@ __global__ void __launch_bounds__(WG) k_direct1(Pass Q) {
                     const bool park = val && !inside && !atend && !ext;
                     if (val && atend && n >= CAP) ok = false;
                     const float2 wv = app ? make_float2(lo, hi)
-                                          : make_float2(fminf(cur.x, lo), fmaxf(cur.y, hi));
+                                          : make_float2(mn(cur.x, lo), mx(cur.y, hi));
                     const int wi = app ? n : ci;
                     if (ext || app) U.set(wi, wv);
                     cur = (ext || app) ? wv : cur;
@@ -2569,7 +2577,7 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int src, int dst) {
 #pragma unroll
                         for (int u = 0; u < SB; ++u) {
                             // chords past the column's last item are empty
-                            const float lo = fmaxf(cq[u].x, zs), hi = fminf(cq[u].y, ze);
+                            const float lo = mx(cq[u].x, zs), hi = mn(cq[u].y, ze);
                             if (!ok || !(lo <= hi)) continue;
                             while (cur.y < lo) {
                                 ++ci;
@@ -2610,7 +2618,7 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int src, int dst) {
                 for (int i = 0, nl = nsh[tb + l]; i < nl; ++i) {
                     const float2 v = lds[i * WG + tb + l];
                     if (m > 0 && v.x <= py) {
-                        py = fmaxf(py, v.y);
+                        py = mx(py, v.y);
                     } else {
                         ++m;
                         py = v.y;
@@ -2652,7 +2660,7 @@ __global__ void __launch_bounds__(WG) k_direct(Pass Q, int src, int dst) {
                         for (int i = 0, nl = nsh[tb + l]; i < nl; ++i) {
                             const float2 v = lds[i * WG + tb + l];
                             if (m > 0 && v.x <= cur.y) {
-                                cur.y = fmaxf(cur.y, v.y);
+                                cur.y = mx(cur.y, v.y);
                                 continue;
                             }
                             if (m > 0) {
@@ -2787,13 +2795,6 @@ static hipError_t scan_counts(const int32_t* cnt, int64_t n, int64_t* bsum, int6
 // evaluate for it (need[]).
 constexpr int THIN_T = 256;
 
-// min / max as the median of the two and an infinity (one v_med3_f32, no
-// operand canonicalisation): the staged values hold no NaN that matters (the
-// thin filter's NaN markers only reach columns whose result is discarded, and
-// it detects them by its own test), so IEEE minNum / maxNum semantics, and
-// the compare-and-select pair, are not needed.
-__device__ __forceinline__ float mn(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -DX_INF); }
-__device__ __forceinline__ float mx(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, DX_INF); }
 
 // One stencil row of the tiled filters: f(v, hh) for dx = -w .. w with
 // v = row[dx] and hh = hr[dx * dx], the LDS loads of four points issued
@@ -3116,7 +3117,7 @@ __global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
         for (int j = 0; j < n0 && ng <= GC_CAP; ++j) {
             const float2 v = gld(&V[j]);
             if (v.x > prev) ++ng;
-            prev = fmaxf(prev, v.y);
+            prev = mx(prev, v.y);
         }
         if (lu.z > prev) ++ng;
     }
@@ -3212,7 +3213,7 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
                     if (nn >= GC_CAP) return false;
                     oth->set(nn++, make_float2(cl, A));
                 }
-                cl = fmaxf(cl, it.y + h);
+                cl = mx(cl, it.y + h);
                 if (!(cl < g.y)) break;
             }
             if (cl < g.y) {
@@ -3275,7 +3276,7 @@ __global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
             if (v.x > prev) {
                 if (ng < GC_CAP) G.set(ng++, make_float2(prev, v.x)); else ng = -1;
             }
-            prev = fmaxf(prev, v.y);
+            prev = mx(prev, v.y);
         }
         if (ng >= 0 && lu.w > prev) {
             if (ng < GC_CAP) G.set(ng++, make_float2(prev, lu.w)); else ng = -1;
@@ -3540,7 +3541,7 @@ __device__ int csg_column(const CsgArgs& A, int64_t c, float2* dst) {
             }
             if (!(v.x < v.y)) continue;
             if (open && v.x <= cur.y) {
-                cur.y = fmaxf(cur.y, v.y);
+                cur.y = mx(cur.y, v.y);
             } else {
                 if (open) put(cur.x, cur.y);
                 cur = v;
@@ -3553,7 +3554,7 @@ __device__ int csg_column(const CsgArgs& A, int64_t c, float2* dst) {
         int i = 0, j = 0;
         float2 va = na > 0 ? gld(&az[0]) : none, vb = nb > 0 ? gld(&bz[0]) : none;
         while (i < na && j < nb) {
-            const float lo = fmaxf(va.x, vb.x), hi = fminf(va.y, vb.y);
+            const float lo = mx(va.x, vb.x), hi = mn(va.y, vb.y);
             if (lo < hi) put(lo, hi);
             if (va.y < vb.y) {
                 ++i;
@@ -3576,7 +3577,7 @@ __device__ int csg_column(const CsgArgs& A, int64_t c, float2* dst) {
                 if (!(vb.x < va.y)) break;
                 if (!(vb.x < vb.y)) continue;
                 if (vb.x > lo) put(lo, vb.x);
-                lo = fmaxf(lo, vb.y);
+                lo = mx(lo, vb.y);
             }
             if (lo < va.y) put(lo, va.y);
         }
@@ -3778,7 +3779,7 @@ __global__ void __launch_bounds__(WG) k_canon_long(CanonArgs A) {
         for (int64_t k = 0; k < m; ++k) {
             const float2 v = s[k];
             if (n > 0 && v.x <= cur.y) {
-                cur.y = fmaxf(cur.y, v.y);
+                cur.y = mx(cur.y, v.y);
             } else {
                 if (n > 0 && put) gst(&A.out_z[off + n - 1], cur);
                 cur = v;
