@@ -19,7 +19,7 @@ struct WsHeader {
     unsigned long long bumpC;
     unsigned long long arena;       // bump allocator of the overflow arena
     int64_t nseg_out;
-    int32_t novf[12];               // columns on each overflow / work list (Stage)
+    int32_t novf[13];               // columns on each overflow / work list (Stage)
     unsigned long long nseeds;      // kept extrusion seeds of the current pass
     int64_t reserved[2];
 };
@@ -29,13 +29,14 @@ static_assert(sizeof(WsHeader) <= 256, "header must fit its slot");
 // slot) and K3, replayed one lane per column; and columns deferred as heavy
 // in K2, K1b and K3, or overflowing K1's lane replay, replayed one wave per
 // column (z slabs); the columns the tiled dilation test leaves to the test
-// against V0 (ST_SOLB) and to the gap cut (ST_GAP); and the columns of a
-// direct evaluation whose list overflowed: the lane's (ST_DIRT, to a team of
-// lanes) and the team's (ST_DIRW, to a whole wave).
+// against V0 (ST_SOLB), to the gap cut (ST_GAP) and to the wide gap cut
+// (ST_GAPW: more gaps, one wave per column); and the columns of a direct
+// evaluation whose list overflowed: the lane's (ST_DIRT, to a team of lanes)
+// and the team's (ST_DIRW, to a whole wave).
 enum Stage {
     ST_K1 = 0, ST_K1B = 1, ST_K2 = 2, ST_K3 = 3,
     ST_K2H = 4, ST_K1BH = 5, ST_K3H = 6, ST_K1H = 7, ST_GAP = 8, ST_SOLB = 9, ST_DIRT = 10,
-    ST_DIRW = 11, NSTAGE = 12
+    ST_DIRW = 11, ST_GAPW = 12, NSTAGE = 13
 };
 
 // Seed slots per column: the seeds of a column are written at

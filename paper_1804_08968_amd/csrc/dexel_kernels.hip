@@ -2969,9 +2969,12 @@ __device__ __forceinline__ void stage_stencil(const OpParams& P, float* Hs, int*
 // gaps of [L, E1] U V0 U [S1, U] inside [L, U] that no chord of another row
 // covers.  A column without such a gap is settled; one with at most GC_CAP
 // goes to the gap cut (k_gap_cut), which applies the chords of the other
-// rows to them; every other column is left to the general kernels.
-constexpr int GC_CAP = 4;      // open gaps the gap cut tracks per column
+// rows to them, one with at most GCW_MAX to the wide gap cut (one wave per
+// column, one gap per lane: at the grid's x border the one-sided row window
+// leaves tens of gaps); every other column is left to the general kernels.
+constexpr int GC_CAP = 4;      // open gaps the gap cut tracks per column (pieces per lane in the wide one)
 constexpr int GC_BUDGET = 160; // stencil columns meeting a gap it visits before giving up
+constexpr int GCW_MAX = 64;    // gaps the wide gap cut takes (one lane each)
 
 __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
     extern __shared__ float2 solid_lds[];
@@ -3108,13 +3111,13 @@ __global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
     const OpParams P = make_op(Q, S);
     const int64_t c = g - Q.sbase[s];
     const float4 lu = gld(&S.lu[c]);  // (L, E1, S1, U)
-    // gaps of [L, E1] U V0 U [S1, U] inside [L, U]; more than GC_CAP: give up
+    // gaps of [L, E1] U V0 U [S1, U] inside [L, U]; more than GCW_MAX: give up
     int ng = 0;
     if (live) {
         const int n0 = gld(&P.cntA[c]);
         const float2* V = P.A + gld(&P.offA[c]);
         float prev = lu.y;
-        for (int j = 0; j < n0 && ng <= GC_CAP; ++j) {
+        for (int j = 0; j < n0 && ng <= GCW_MAX; ++j) {
             const float2 v = gld(&V[j]);
             if (v.x > prev) ++ng;
             prev = mx(prev, v.y);
@@ -3123,6 +3126,7 @@ __global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
     }
     const bool done = live && ng == 0;
     const bool cut = live && ng > 0 && ng <= GC_CAP;
+    const bool wide = live && ng > GC_CAP && ng <= GCW_MAX;
     const int outn = done ? 1 : 0;
     int tot;
     const int pre = wave_excl_scan(outn, &tot);
@@ -3136,10 +3140,10 @@ __global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
         set_error(P.hdr, DEXEL_ERR_WORKSPACE);
     }
     if (!live) return;
-    if (cut) {
+    if (cut || wide) {
         // the gap cut reads (L, U) and the range its gaps are taken from
         gst(&S.lu[c], make_float4(lu.x, lu.w, lu.y, lu.z));
-        push_overflow(Q, ST_GAP, g);
+        push_overflow(Q, cut ? ST_GAP : ST_GAPW, g);
         return;
     }
     if (!done) {
@@ -3312,6 +3316,90 @@ __global__ void __launch_bounds__(WG) k_gap_cut(Pass Q) {
         a = gp.y;
     }
     gst(&d[ng], make_float2(a, lu.y));
+}
+
+// The columns k_solid_b found with more than GC_CAP (at most GCW_MAX) gaps,
+// one wave each, one gap per lane: the gaps are disjoint and what a chord
+// removes from one does not depend on the others, so each lane cuts its own
+// gap with the other rows' chords (gap_cut on a one-gap list, the pieces it
+// splits into at most GC_CAP), and lane 0 writes [L, U] minus the pieces
+// left, in order.  A lane giving up leaves the column to the general kernels.
+__global__ void __launch_bounds__(WG) k_gap_cut_wide(Pass Q) {
+    __shared__ float2 lds[2 * GC_CAP * WG];
+    __shared__ int pcnt[WG];
+    if (Q.hdr->abort) return;
+    const int cnt = Q.hdr->novf[ST_GAPW];
+    const int lane = threadIdx.x;
+    const LdsList G{&lds[lane], GC_CAP};
+    const LdsList T{&lds[GC_CAP * WG + lane], GC_CAP};
+    for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+        const int64_t g = Q.ovf[(int64_t)ST_GAPW * Q.gcols + e];
+        const int s = find_shape(Q, g);
+        const Shape& S = Q.shapes[s];
+        const OpParams P = make_op(Q, S);
+        const int64_t c = g - Q.sbase[s];
+        int x, y;
+        col_xy(P, c, &x, &y);
+        const float4 lu = gld(&S.lu[c]);
+        // the gaps of V0 inside [lu.z, lu.w], in order (every lane walks V0;
+        // lane k keeps gap k)
+        const int n0 = gld(&P.cntA[c]);
+        const float2* V = P.A + gld(&P.offA[c]);
+        int k = 0;
+        float prev = lu.z;
+        float2 mine = make_float2(0.0f, 0.0f);
+        for (int j = 0; j < n0; ++j) {
+            const float2 v = gld(&V[j]);
+            if (v.x > prev) {
+                if (k == lane) mine = make_float2(prev, v.x);
+                ++k;
+            }
+            prev = mx(prev, v.y);
+        }
+        if (lu.w > prev) {
+            if (k == lane) mine = make_float2(prev, lu.w);
+            ++k;
+        }
+        const bool have = lane < k;
+        int np = 0;
+        if (have) {
+            G.set(0, mine);
+            np = gap_cut(P, x, y, G, T, 1);
+        }
+        const bool fail = __any(have && np < 0) || k > GCW_MAX;
+        pcnt[lane] = have ? np : 0;
+        __syncthreads();  // every lane's pieces and count are written
+        if (lane == 0) {
+            if (fail) {
+                gst(&S.gen[c], (uint8_t)(GEN_V0 | GEN_GENERAL));
+            } else {
+                int tot = 1;
+                for (int l = 0; l < k; ++l) tot += pcnt[l];
+                const unsigned long long base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)tot);
+                const unsigned long long end = base + (unsigned long long)tot;
+                const bool ok = end <= (unsigned long long)Q.cap;
+                if (!ok) {
+                    note_need(Q.hdr, end);
+                    set_error(Q.hdr, DEXEL_ERR_WORKSPACE);
+                }
+                gst(&P.offC[c], (int64_t)base);
+                gst(&P.cntC[c], ok ? tot : 0);
+                if (ok) {
+                    float2* d = P.C + base;
+                    float a = lu.x;  // the union is [L, U] minus the pieces left
+                    int o = 0;
+                    for (int l = 0; l < k; ++l)
+                        for (int i = 0; i < pcnt[l]; ++i) {
+                            const float2 gp = lds[i * WG + l];  // lane l's list, element i
+                            gst(&d[o++], make_float2(a, gp.x));
+                            a = gp.y;
+                        }
+                    gst(&d[o], make_float2(a, lu.y));
+                }
+            }
+        }
+        __syncthreads();  // lane 0 has read the lists before they are reused
+    }
 }
 
 // need[c] of every column of the shapes with fast path `mode`: NEED_UNION if
@@ -4146,6 +4234,7 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     if (p.ntiles > 0 && p.nsolid > 0) {
         hipLaunchKernelGGL(k_solid_b, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
+        hipLaunchKernelGGL(k_gap_cut_wide, gf, b, 0, s, p);
         hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_SOLID);
         // the row offsets the general columns' stages still need
         hipLaunchKernelGGL(k_reset_k1, dim3(1), dim3(64), 0, s, p);
