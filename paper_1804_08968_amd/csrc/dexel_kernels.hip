@@ -3171,8 +3171,10 @@ __global__ void k_reset_k1(Pass Q) {
 template <class L>
 __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, int ng) {
     int budget = GC_BUDGET;
-    const L* cur = &G;
-    const L* oth = &T;
+    // the current gap list and the one the next visit writes, swapped after
+    // each visit (list views held by value, so nothing is address-taken)
+    L cur = G, oth = T;
+    bool in_g = true;
     auto visit = [&](int dx, int dy) -> bool {  // false: give up
         const int xx = x + dx, yy = y + dy;
         if (xx < 0 || xx >= P.nx || yy < 0 || yy >= P.ny) return true;
@@ -3185,7 +3187,7 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
         const float A0 = e4.x - h, B1 = e4.w + h;
         bool meet = false;
         for (int j = 0; j < ng; ++j) {
-            const float2 g = cur->get(j);
+            const float2 g = cur.get(j);
             meet = meet || (A0 < g.y && B1 > g.x);
         }
         if (!meet) return true;
@@ -3195,10 +3197,10 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
         const float2* zc = P.z + b;
         int k = 0, nn = 0;
         for (int j = 0; j < ng; ++j) {
-            const float2 g = cur->get(j);
+            const float2 g = cur.get(j);
             if (!(A0 < g.y && B1 > g.x)) {
                 if (nn >= GC_CAP) return false;
-                oth->set(nn++, g);
+                oth.set(nn++, g);
                 continue;
             }
             // first chord ending above the gap's start (chord ends increase)
@@ -3215,22 +3217,23 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
                 if (!(A < g.y)) break;
                 if (A > cl) {
                     if (nn >= GC_CAP) return false;
-                    oth->set(nn++, make_float2(cl, A));
+                    oth.set(nn++, make_float2(cl, A));
                 }
                 cl = mx(cl, it.y + h);
                 if (!(cl < g.y)) break;
             }
             if (cl < g.y) {
                 if (nn >= GC_CAP) return false;
-                oth->set(nn++, make_float2(cl, g.y));
+                oth.set(nn++, make_float2(cl, g.y));
             }
             // the next gap starts above this one: resume at the last chord seen
             if (k > 0) --k;
         }
         ng = nn;
-        const L* tmp = cur;
+        const L tmp = cur;
         cur = oth;
         oth = tmp;
+        in_g = !in_g;
         return true;
     };
     for (int r = 1; r <= P.R && ng > 0; ++r) {
@@ -3243,8 +3246,8 @@ __device__ int gap_cut(const OpParams& P, int x, int y, const L& G, const L& T, 
                 if (dy != 0 && !visit(s * r, dy)) return -1;
         }
     }
-    if (cur != &G)
-        for (int j = 0; j < ng; ++j) G.set(j, cur->get(j));
+    if (!in_g)
+        for (int j = 0; j < ng; ++j) G.set(j, cur.get(j));
     return ng;
 }
 
