@@ -303,31 +303,41 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
     // carry them in vector registers instead of merging lane masks at every
     // branch; push() itself runs without a branch but for the one store
     int open = 0, bad = 0;
-    auto push = [&](float2 v) {
+    // push v if `doit`: every update is a select but the one store
+    auto push_if = [&](bool doit, float2 v) {
+        const int d = doit ? 1 : 0;
         const int ext = open & (v.x <= cur.y ? 1 : 0);
-        const int emit = open & (ext ^ 1);
+        const int emit = d & open & (ext ^ 1);
         const int room = (k <= top + i ? 1 : 0) & (k < U.cap ? 1 : 0);
         if (emit & room) U.set(k, cur);
         bad |= emit & (room ^ 1);
         k += emit;
-        cur = ext ? make_float2(cur.x, mx(cur.y, v.y)) : v;
-        open = 1;
+        const float2 nc = ext ? make_float2(cur.x, mx(cur.y, v.y)) : v;
+        cur = doit ? nc : cur;
+        open |= d;
     };
     auto step = [&](const float2 it, int j) {
-        if (j >= cnt) return;
+        const bool live = j < cnt;
         float2 c;
         if (E) {
             c = make_float2(prevy - h, (j < m ? it.x : DX_INF) + h);
-            prevy = it.y;
+            prevy = live ? it.y : prevy;
         } else {
             c = make_float2(it.x - h, it.y + h);
         }
-        while (i < n && u0.x <= c.x) {
-            push(u0);
+        // the entries of U starting at or below c's start go first: one
+        // predicated step (the usual case), then a loop for the rest
+        const bool t1 = live && i < n && u0.x <= c.x;
+        push_if(t1, u0);
+        const float2 un = U.get(min(top + i + 1, last));
+        i += t1 ? 1 : 0;
+        u0 = t1 ? un : u0;
+        while (live && i < n && u0.x <= c.x) {
+            push_if(true, u0);
             ++i;
             u0 = U.get(min(top + i, last));
         }
-        push(c);
+        push_if(live, c);
     };
     for (int j = 0; j < cnt; j += AHEAD) {
 #pragma unroll
@@ -338,7 +348,7 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
         }
     }
     while (i < n) {
-        push(u0);
+        push_if(true, u0);
         ++i;
         u0 = U.get(min(top + i, last));
     }
