@@ -952,11 +952,13 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
     int x = 0, y = 0;
     if (live) col_xy(P, c, &x, &y);
     int n = 0;
-    bool ok = live;
+    // a per-lane flag as an integer: the divergent insert branches carry it
+    // in a vector register instead of merging lane masks
+    int ok = live ? 1 : 0;
     if (ok) {
         const int n0 = gld(&P.cntA[c]);
         if (n0 > U.cap) {
-            ok = false;
+            ok = 0;
         } else {
             const float2* V = P.A + gld(&P.offA[c]);
             for (int i = 0; i < n0; ++i) U.set(i, gld(&V[i]));
@@ -1040,7 +1042,7 @@ __device__ int k3_column(const OpParams& P, int64_t c, bool live, const L& U, fl
                     if (ok && j + q < nb && h >= 0.0f && !inside) {
                         n = lv_insert(U, n, lo, hi);
                         if (n < 0) {
-                            ok = false;
+                            ok = 0;
                             n = 0;
                         } else if (n <= 2) {
                             u0 = U.get(0);
