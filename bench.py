@@ -860,6 +860,10 @@ def run_batch(args, dx, torch):
     prof_ms, passes = dx.dexel_profile_read(eng.ctx, reset=True)
     per = {s: prof_ms[i] for i, s in enumerate(dx.PROFILE_STAGES)}
     dom = max(per, key=per.get)
+    # the batch is one pass over every shape's columns: its list sizes are
+    # the workspace header's totals, its launches one per stage
+    ncols_b = sum(g.nx * g.ny for g in grids)
+    roof = stage_roofline(dx, per, [(n_in, dx.dexel_workspace_stats(eng.ctx, bp.ws))], ncols_b)
 
     ms_step = float(np.median(batch_ms))
     value = n_in / (ms_step / 1000.0)
@@ -885,6 +889,7 @@ def run_batch(args, dx, torch):
                   "segments_per_s": n_in / (float(np.median(plain_ms)) / 1000.0),
                   "latency_ms_p50": pct(lat_plain, 50), "latency_ms_p99": pct(lat_plain, 99)},
         "speedup_vs_plain": float(np.median(plain_ms)) / ms_step,
+        "roofline": roof,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in per.items()},
         "dominant_kernel": dx.PROFILE_KERNELS[dx.PROFILE_STAGES.index(dom)],
     }
