@@ -165,17 +165,22 @@ constexpr int DIRECT_RMAX = 16;
 // Tiled fast paths: tiles of THIN_TX x THIN_TY (thin erosion) or
 // THIN_TX x SOLID_TY (dilation test) output columns, radii up to THIN_RMAX.
 // LDS bytes a tile stages at integer radius R: per staged column one float2
-// (thin) or two float2 and a float (dilation), then the half-width table and
-// the stencil's row widths.
+// (thin) or two float2 and a float (dilation), then the stencil's half-widths
+// row by row (row |dy| = k holds H[dx^2 + k^2] for dx = -w_k .. w_k, padded
+// to a multiple of four floats, so that four of them are one 16-byte load;
+// (R + 1) (2R + 4) floats bound the table, and the kernels place what
+// follows it there), and per row its width w_k and its offset in the table.
 constexpr int THIN_TX = 64;
 constexpr int THIN_TY = 16;
 constexpr int SOLID_TY = 8;
 constexpr int THIN_RMAX = 32;
 inline int thin_lds_bytes(int R, int d2max) {
-    return (THIN_TX + 2 * R) * (THIN_TY + 2 * R) * 8 + 4 * (d2max + 1) + 4 * (R + 1);
+    (void)d2max;
+    return (THIN_TX + 2 * R) * (THIN_TY + 2 * R) * 8 + 4 * (R + 1) * (2 * R + 4) + 8 * (R + 1);
 }
 inline int solid_lds_bytes(int R, int d2max) {
-    return (THIN_TX + 2 * R) * (SOLID_TY + 2 * R) * 20 + 4 * (d2max + 1) + 4 * (R + 1);
+    (void)d2max;
+    return (THIN_TX + 2 * R) * (SOLID_TY + 2 * R) * 20 + 4 * (R + 1) * (2 * R + 4) + 8 * (R + 1);
 }
 // need[] bits: stages of the general kernels a column runs.
 constexpr int NEED_UNION = 1;   // y union (the column is general itself)

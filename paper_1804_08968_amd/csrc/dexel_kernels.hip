@@ -2845,42 +2845,68 @@ constexpr int THIN_T = 256;
 
 
 // One stencil row of the tiled filters: f(v, hh) for dx = -w .. w with
-// v = row[dx] and hh = hr[dx * dx], the LDS loads of four points issued
-// together.
+// v = row[dx] and hh = hq[dx + w] (the row's half-widths, contiguous and
+// 16-byte aligned), the LDS loads of four points issued together and their
+// four half-widths one load (the same address in every lane).
 template <class T, class F>
-__device__ __forceinline__ void sweep_row(const T* row, const float* hr, int w, F f) {
+__device__ __forceinline__ void sweep_row(const T* row, const float* hq, int w, F f) {
+    const float4* h4 = (const float4*)hq;
     int dx = -w;
-    for (; dx + 3 <= w; dx += 4) {
+    for (; dx + 3 <= w; dx += 4, ++h4) {
         const T v0 = row[dx], v1 = row[dx + 1], v2 = row[dx + 2], v3 = row[dx + 3];
-        const float h0 = hr[dx * dx], h1 = hr[(dx + 1) * (dx + 1)];
-        const float h2 = hr[(dx + 2) * (dx + 2)], h3 = hr[(dx + 3) * (dx + 3)];
-        f(v0, h0);
-        f(v1, h1);
-        f(v2, h2);
-        f(v3, h3);
+        const float4 h = *h4;
+        f(v0, h.x);
+        f(v1, h.y);
+        f(v2, h.z);
+        f(v3, h.w);
     }
-    for (; dx <= w; ++dx) f(row[dx], hr[dx * dx]);
+    const float* ht = (const float*)h4;
+    for (int k = 0; dx <= w; ++dx, ++k) f(row[dx], ht[k]);
 }
 
 // The same over two staged arrays: f(v, u, hh), v = ra[dx], u = rb[dx].
 template <class T, class F>
-__device__ __forceinline__ void sweep_row2(const T* ra, const T* rb, const float* hr, int w, F f) {
+__device__ __forceinline__ void sweep_row2(const T* ra, const T* rb, const float* hq, int w, F f) {
+    const float4* h4 = (const float4*)hq;
     int dx = -w;
-    for (; dx + 3 <= w; dx += 4) {
+    for (; dx + 3 <= w; dx += 4, ++h4) {
         const T v0 = ra[dx], v1 = ra[dx + 1], v2 = ra[dx + 2], v3 = ra[dx + 3];
         const T u0 = rb[dx], u1 = rb[dx + 1], u2 = rb[dx + 2], u3 = rb[dx + 3];
-        const float h0 = hr[dx * dx], h1 = hr[(dx + 1) * (dx + 1)];
-        const float h2 = hr[(dx + 2) * (dx + 2)], h3 = hr[(dx + 3) * (dx + 3)];
-        f(v0, u0, h0);
-        f(v1, u1, h1);
-        f(v2, u2, h2);
-        f(v3, u3, h3);
+        const float4 h = *h4;
+        f(v0, u0, h.x);
+        f(v1, u1, h.y);
+        f(v2, u2, h.z);
+        f(v3, u3, h.w);
     }
-    for (; dx <= w; ++dx) f(ra[dx], rb[dx], hr[dx * dx]);
+    const float* ht = (const float*)h4;
+    for (int k = 0; dx <= w; ++dx, ++k) f(ra[dx], rb[dx], ht[k]);
+}
+
+// The stencil tables of the tiled filters, staged by the whole block (the
+// caller synchronises before reading them): wd[k] = w_k, the largest |dx| of
+// stencil row |dy| = k; ro[k], the offset of that row in Hr (a multiple of
+// four); Hr[ro[k] + i] = H[(i - w_k)^2 + k^2] for i = 0 .. 2 w_k.  Each
+// thread k works out w_j of the rows j <= k itself, so the offsets need no
+// synchronisation of their own.
+__device__ __forceinline__ int row_width(int d2max, int k) {
+    int w = 0;
+    while ((w + 1) * (w + 1) + k * k <= d2max) ++w;
+    return w;
+}
+
+__device__ __forceinline__ void stage_stencil(const OpParams& P, float* Hr, int* ro, int* wd) {
+    for (int k = threadIdx.x; k <= P.R; k += blockDim.x) {
+        int off = 0;
+        for (int j = 0; j < k; ++j) off += (2 * row_width(P.d2max, j) + 4) & ~3;
+        const int w = row_width(P.d2max, k);
+        wd[k] = w;
+        ro[k] = off;
+        for (int i = 0; i <= 2 * w; ++i) Hr[off + i] = gld(&P.H[(i - w) * (i - w) + k * k]);
+    }
 }
 
 __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
-    extern __shared__ float2 thin_lds[];
+    extern __shared__ float4 thin_lds[];
     if (Q.hdr->abort) return;
     const int64_t t = map_block(Q.ntiles);
     int lo = 0, hi = Q.nshapes;  // the last shape whose tiles start at or before t
@@ -2896,16 +2922,11 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
     const int64_t tl = t - S.tbase;
     const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * THIN_TY;
     const int SW = THIN_TX + 2 * R, SH = THIN_TY + 2 * R;
-    float2* st = thin_lds;
-    float* Hs = (float*)(st + SW * SH);
-    int* wd = (int*)(Hs + P.d2max + 1);
-    for (int i = threadIdx.x; i <= P.d2max; i += THIN_T) Hs[i] = gld(&P.H[i]);
-    // wd[k]: largest |dx| of the stencil row at |dy| = k
-    for (int k = threadIdx.x; k <= R; k += THIN_T) {
-        int w = 0;
-        while ((w + 1) * (w + 1) + k * k <= P.d2max) ++w;
-        wd[k] = w;
-    }
+    float2* st = (float2*)thin_lds;
+    float* Hr = (float*)(st + SW * SH);  // 16-byte aligned: SW * SH is even
+    int* wd = (int*)(Hr + (P.R + 1) * (2 * P.R + 4));  // the table's bound
+    int* ro = wd + (P.R + 1);
+    stage_stencil(P, Hr, ro, wd);
     int thick = 0;
     for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
         const int sy = i / SW, sx = i - sy * SW;
@@ -2940,7 +2961,7 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
         for (int dy = -R; dy <= R; ++dy) {
             const int w = wd[dy < 0 ? -dy : dy];
             const float2* row = ctr + dy * SW;
-            const float* hr = Hs + dy * dy;
+            const float* hr = Hr + ro[dy < 0 ? -dy : dy];
             if (any_thick) {
                 sweep_row(row, hr, w, [&](float2 v, float hh) {
                     thk |= v.x != v.x;
@@ -2974,17 +2995,6 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
         gst(&P.offC[c], (int64_t)(base + pre));
         gst(&P.cntC[c], ok ? outn : 0);
         if (ok && outn) gst(&P.C[base + pre], make_float2(MA, MB));
-    }
-}
-
-// Tile shapes of the tiled fast paths: the stencil's half-width table and
-// row widths wd[k] (largest |dx| at |dy| = k), staged by the whole block.
-__device__ __forceinline__ void stage_stencil(const OpParams& P, float* Hs, int* wd) {
-    for (int i = threadIdx.x; i <= P.d2max; i += THIN_T) Hs[i] = gld(&P.H[i]);
-    for (int k = threadIdx.x; k <= P.R; k += THIN_T) {
-        int w = 0;
-        while ((w + 1) * (w + 1) + k * k <= P.d2max) ++w;
-        wd[k] = w;
     }
 }
 
@@ -3025,7 +3035,7 @@ constexpr int GC_BUDGET = 160; // stencil columns meeting a gap it visits before
 constexpr int GCW_MAX = 64;    // gaps the wide gap cut takes (one lane each)
 
 __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
-    extern __shared__ float2 solid_lds[];
+    extern __shared__ float4 solid_lds[];
     if (Q.hdr->abort) return;
     const int64_t t = map_block(Q.ntiles);
     int lo = 0, hi = Q.nshapes;
@@ -3041,12 +3051,13 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
     const int64_t tl = t - S.tbase;
     const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * SOLID_TY;
     const int SW = THIN_TX + 2 * R, SH = SOLID_TY + 2 * R;
-    float2* sab = solid_lds;                 // (af, bl)
+    float2* sab = (float2*)solid_lds;        // (af, bl)
     float2* sba = sab + SW * SH;             // (bf, al)
     float* sg = (float*)(sba + SW * SH);     // half the largest-gap bound
-    float* Hs = sg + SW * SH;
-    int* wd = (int*)(Hs + P.d2max + 1);
-    stage_stencil(P, Hs, wd);
+    float* Hr = sg + SW * SH;                // 16-byte aligned: SW * SH is a multiple of 4
+    int* wd = (int*)(Hr + (P.R + 1) * (2 * P.R + 4));  // the table's bound
+    int* ro = wd + (P.R + 1);
+    stage_stencil(P, Hr, ro, wd);
     // empty and off-grid columns stage (+inf, -inf), (+inf, -inf) and -1:
     // they change no filter and are never a hull
     for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
@@ -3081,7 +3092,7 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         float L = DX_INF, U = -DX_INF;
         for (int dy = -R; dy <= R; ++dy) {
             const int w = wd[dy < 0 ? -dy : dy];
-            const float* hr = Hs + dy * dy;
+            const float* hr = Hr + ro[dy < 0 ? -dy : dy];
             sweep_row(sab + ci + dy * SW, hr, w, [&](float2 v, float hh) {
                 L = mn(L, v.x - hh);
                 U = mx(U, v.y + hh);
@@ -3093,7 +3104,7 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         for (int dy = -R; dy <= R; ++dy) {
             const int w = wd[dy < 0 ? -dy : dy];
             const int ri = ci + dy * SW;
-            const float* hr = Hs + dy * dy;
+            const float* hr = Hr + ro[dy < 0 ? -dy : dy];
             sweep_row2(sab + ri, sba + ri, hr, w, [&](float2 v, float2 u, float hh) {
                 E1 = mx(E1, v.x - hh == L ? u.x + hh : -DX_INF);
                 S1 = mn(S1, v.y + hh == U ? u.y - hh : DX_INF);
@@ -3103,13 +3114,14 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         if (E1 < S1) {
             for (int dy = -R; dy <= R; ++dy) {
                 if (dy * dy > d2in) continue;
-                int w = wd[dy < 0 ? -dy : dy];
+                const int wf = wd[dy < 0 ? -dy : dy];
+                int w = wf;
                 while (w * w + dy * dy > d2in) --w;
                 const int ri = ci + dy * SW;
-                const float* hr = Hs + dy * dy;
+                const float* hr = Hr + ro[dy < 0 ? -dy : dy] + wf;  // hr[dx]: H[dx^2 + dy^2]
                 for (int dx = -w; dx <= w; ++dx) {
                     const float2 v = sab[ri + dx];
-                    const float hh = hr[dx * dx];
+                    const float hh = hr[dx];
                     hull = hull || (sg[ri + dx] <= hh && v.x - hh <= E1 && v.y + hh >= S1);
                 }
             }
