@@ -1588,7 +1588,7 @@ __device__ void arena_eval(const OpParams& P, int nl, int64_t bound, F eval) {
     }
 }
 
-// Summary of every input column of the pass, 16 lanes per column: its
+// Summary of every input column of the pass, GAP_LANES lanes per column: its
 // first and last item, and its largest gap: between consecutive intervals
 // for a dilation, the intervals' own lengths for an erosion (the gaps of the
 // complement).  The gap is stored one float step above the largest float
@@ -1620,8 +1620,18 @@ __global__ void __launch_bounds__(WG) k_col_gaps(Pass Q) {
                 G = mx(G, v.y - v.x);
             }
         } else {
-            for (int i = l; i + 1 < m; i += GAP_LANES)
-                G = mx(G, gld(&P.z[b + i + 1]).x - gld(&P.z[b + i]).y);
+            // lane l holds items l, l + GAP_LANES, ...: the start of the item
+            // after its item is the next lane's (for the group's last lane, the
+            // first lane's of the next round), so each item is loaded once
+            float2 v = l < m ? gld(&P.z[b + l]) : make_float2(DX_INF, DX_INF);
+            for (int i0 = 0; i0 < m; i0 += GAP_LANES) {
+                const int i = i0 + l;
+                const float2 nv = i + GAP_LANES < m ? gld(&P.z[b + i + GAP_LANES]) : make_float2(DX_INF, DX_INF);
+                const float s_in = __shfl(v.x, (l + 1) % GAP_LANES, GAP_LANES);
+                const float s_nx = __shfl(nv.x, 0, GAP_LANES);
+                if (i + 1 < m) G = mx(G, (l + 1 < GAP_LANES ? s_in : s_nx) - v.y);
+                v = nv;
+            }
         }
     }
 #pragma unroll
