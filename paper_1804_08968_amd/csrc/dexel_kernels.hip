@@ -3479,21 +3479,58 @@ __global__ void __launch_bounds__(WG) k_gap_cut_wide(Pass Q) {
 // the column is general itself, NEED_SEEDS if a general column lies within R
 // rows of it (its seeds and intersection feed that column's y union),
 // NEED_ROW if one lies within 2R rows (its row offset feeds those
-// intersections).
+// intersections).  One wave per tile of the fast path (THIN_TX columns x TY
+// rows), one lane per column: the distance from each of the tile's rows to
+// the nearest general row of its column comes from one scan down and one up
+// over the tile's rows and 2R rows beyond them, so each gen[] entry is read
+// about twice instead of once per row within 2R.
+template <int TY>
 __global__ void __launch_bounds__(WG) k_fast_spread(Pass Q, int mode) {
     if (Q.hdr->abort) return;
-    const Place pl = place_block(Q);
-    const Shape& S = Q.shapes[pl.s];
-    if (S.fast != mode || !pl.valid) return;
-    const int y = (int)(pl.c / S.nx), x = (int)(pl.c - (int64_t)y * S.nx);
-    int bits = (gld(&S.gen[pl.c]) & GEN_GENERAL) ? NEED_UNION | NEED_SEEDS | NEED_ROW : 0;
-    for (int d = 1; d <= 2 * S.R && !(bits & NEED_SEEDS) && !(bits && d > S.R); ++d) {
-        const bool lo_in = y - d >= 0, hi_in = y + d < S.ny;
-        const bool g = (lo_in && (gld(&S.gen[pl.c - (int64_t)d * S.nx]) & GEN_GENERAL)) ||
-                       (hi_in && (gld(&S.gen[pl.c + (int64_t)d * S.nx]) & GEN_GENERAL));
-        if (g) bits |= d <= S.R ? NEED_SEEDS | NEED_ROW : NEED_ROW;
+    const int64_t t = blockIdx.x;
+    int lo = 0, hi = Q.nshapes;  // the last shape whose tiles start at or before t
+    while (hi - lo > 1) {
+        const int m = (lo + hi) >> 1;
+        if (Q.shapes[m].tbase <= t) lo = m; else hi = m;
     }
-    gst(&S.need[pl.c], (uint8_t)bits);
+    const Shape& S = Q.shapes[lo];
+    if (S.fast != mode) return;
+    const int ntx = (S.nx + THIN_TX - 1) / THIN_TX;
+    const int64_t tl = t - S.tbase;
+    const int x = (int)(tl % ntx) * THIN_TX + (int)threadIdx.x;
+    const int y0 = (int)(tl / ntx) * TY;
+    if (x >= S.nx) return;
+    const int R2 = 2 * S.R;
+    auto general = [&](int y) { return (gld(&S.gen[(int64_t)y * S.nx + x]) & GEN_GENERAL) != 0; };
+    constexpr int FAR = 1 << 30;
+    // downwards: the last general row at or above each tile row
+    int last = -FAR;
+    for (int y = max(0, y0 - R2); y < y0; ++y)
+        if (general(y)) last = y;
+    int gmask = 0;       // the tile's general rows
+    int dup[TY];         // distance to the last general row at or above
+#pragma unroll
+    for (int k = 0; k < TY; ++k) {
+        const int y = y0 + k;
+        const bool g = y < S.ny && general(y);
+        gmask |= g ? 1 << k : 0;
+        last = g ? y : last;
+        dup[k] = y - last;
+    }
+    // upwards: the next general row at or below, and the bits
+    int next = FAR;
+    for (int y = min(S.ny - 1, y0 + TY - 1 + R2); y >= y0 + TY; --y)
+        if (general(y)) next = y;
+#pragma unroll
+    for (int k = TY - 1; k >= 0; --k) {
+        const int y = y0 + k;
+        if ((gmask >> k) & 1) next = y;
+        const int d = min(dup[k], next - y);
+        const int bits = d == 0 ? NEED_UNION | NEED_SEEDS | NEED_ROW
+                       : d <= S.R ? NEED_SEEDS | NEED_ROW
+                       : d <= R2 ? NEED_ROW : 0;
+        if (y < S.ny) gst(&S.need[(int64_t)y * S.nx + x], (uint8_t)bits);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -4291,7 +4328,7 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     DX_MARK(2);
     if (p.ntiles > 0 && p.nthin > 0) {
         hipLaunchKernelGGL(k_thin_erode, dim3((unsigned)p.ntiles), dim3(THIN_T), (unsigned)p.thin_lds, s, p);
-        hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_THIN);
+        hipLaunchKernelGGL(k_fast_spread<THIN_TY>, dim3((unsigned)p.ntiles), b, 0, s, p, (int)FAST_THIN);
     }
     DX_MARK(3);
     if (p.ntiles > 0 && p.nsolid > 0)
@@ -4308,7 +4345,7 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
         hipLaunchKernelGGL(k_solid_b, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut_wide, gf, b, 0, s, p);
-        hipLaunchKernelGGL(k_fast_spread, g, b, 0, s, p, (int)FAST_SOLID);
+        hipLaunchKernelGGL(k_fast_spread<SOLID_TY>, dim3((unsigned)p.ntiles), b, 0, s, p, (int)FAST_SOLID);
         // the row offsets the general columns' stages still need
         hipLaunchKernelGGL(k_reset_k1, dim3(1), dim3(64), 0, s, p);
         Pass p2 = p;
