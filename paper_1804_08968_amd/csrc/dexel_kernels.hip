@@ -2861,34 +2861,59 @@ constexpr int THIN_T = 256;
 template <class T, class F>
 __device__ __forceinline__ void sweep_row(const T* row, const float* hq, int w, F f) {
     const float4* h4 = (const float4*)hq;
+    const int ng = (2 * w + 1) >> 2;
     int dx = -w;
-    for (; dx + 3 <= w; dx += 4, ++h4) {
-        const T v0 = row[dx], v1 = row[dx + 1], v2 = row[dx + 2], v3 = row[dx + 3];
-        const float4 h = *h4;
+    if (ng > 0) {
+        T v0 = row[dx], v1 = row[dx + 1], v2 = row[dx + 2], v3 = row[dx + 3];
+        float4 h = h4[0];
+        for (int g = 1; g < ng; ++g) {
+            const T n0 = row[dx + 4], n1 = row[dx + 5], n2 = row[dx + 6], n3 = row[dx + 7];
+            const float4 nh = h4[g];
+            f(v0, h.x);
+            f(v1, h.y);
+            f(v2, h.z);
+            f(v3, h.w);
+            v0 = n0; v1 = n1; v2 = n2; v3 = n3; h = nh;
+            dx += 4;
+        }
         f(v0, h.x);
         f(v1, h.y);
         f(v2, h.z);
         f(v3, h.w);
+        dx += 4;
     }
-    const float* ht = (const float*)h4;
+    const float* ht = (const float*)(h4 + ng);
     for (int k = 0; dx <= w; ++dx, ++k) f(row[dx], ht[k]);
 }
 
-// The same over two staged arrays: f(v, u, hh), v = ra[dx], u = rb[dx].
 template <class T, class F>
 __device__ __forceinline__ void sweep_row2(const T* ra, const T* rb, const float* hq, int w, F f) {
     const float4* h4 = (const float4*)hq;
+    const int ng = (2 * w + 1) >> 2;
     int dx = -w;
-    for (; dx + 3 <= w; dx += 4, ++h4) {
-        const T v0 = ra[dx], v1 = ra[dx + 1], v2 = ra[dx + 2], v3 = ra[dx + 3];
-        const T u0 = rb[dx], u1 = rb[dx + 1], u2 = rb[dx + 2], u3 = rb[dx + 3];
-        const float4 h = *h4;
+    if (ng > 0) {
+        T v0 = ra[dx], v1 = ra[dx + 1], v2 = ra[dx + 2], v3 = ra[dx + 3];
+        T u0 = rb[dx], u1 = rb[dx + 1], u2 = rb[dx + 2], u3 = rb[dx + 3];
+        float4 h = h4[0];
+        for (int g = 1; g < ng; ++g) {
+            const T n0 = ra[dx + 4], n1 = ra[dx + 5], n2 = ra[dx + 6], n3 = ra[dx + 7];
+            const T m0 = rb[dx + 4], m1 = rb[dx + 5], m2 = rb[dx + 6], m3 = rb[dx + 7];
+            const float4 nh = h4[g];
+            f(v0, u0, h.x);
+            f(v1, u1, h.y);
+            f(v2, u2, h.z);
+            f(v3, u3, h.w);
+            v0 = n0; v1 = n1; v2 = n2; v3 = n3;
+            u0 = m0; u1 = m1; u2 = m2; u3 = m3; h = nh;
+            dx += 4;
+        }
         f(v0, u0, h.x);
         f(v1, u1, h.y);
         f(v2, u2, h.z);
         f(v3, u3, h.w);
+        dx += 4;
     }
-    const float* ht = (const float*)h4;
+    const float* ht = (const float*)(h4 + ng);
     for (int k = 0; dx <= w; ++dx, ++k) f(ra[dx], rb[dx], ht[k]);
 }
 
@@ -3098,20 +3123,33 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         const int y = y0 + ly;
         if (y >= P.ny) break;  // wave-uniform
         const int ci = (ly + R) * SW + lane + R;
-        // L and U over the whole stencil
+        // L and U over the whole stencil, row by row, with the rows whose
+        // chords reach L (mL) or U (mU): bit dy + R, while 2R + 1 <= 64
         float L = DX_INF, U = -DX_INF;
+        uint64_t mL = 0, mU = 0;
+        const bool masks = 2 * R + 1 <= 64;
         for (int dy = -R; dy <= R; ++dy) {
             const int w = wd[dy < 0 ? -dy : dy];
             const float* hr = Hr + ro[dy < 0 ? -dy : dy];
+            float rL = DX_INF, rU = -DX_INF;
             sweep_row(sab + ci + dy * SW, hr, w, [&](float2 v, float hh) {
-                L = mn(L, v.x - hh);
-                U = mx(U, v.y + hh);
+                rL = mn(rL, v.x - hh);
+                rU = mx(rU, v.y + hh);
             });
+            const uint64_t bit = masks ? 1ull << (dy + R) : 0ull;
+            mL = rL < L ? bit : (rL == L ? mL | bit : mL);
+            mU = rU > U ? bit : (rU == U ? mU | bit : mU);
+            L = mn(L, rL);
+            U = mx(U, rU);
         }
-        // E1 and S1 over the whole stencil, then a connecting hull in its
-        // inner part
+        // E1 and S1: a row without a chord starting at L or ending at U adds
+        // nothing to them, so the wave visits only the rows some lane's masks
+        // name (all of them if the masks do not cover the stencil); then a
+        // connecting hull in the stencil's inner part
+        const uint64_t need = masks ? (mL | mU) : ~0ull;
         float E1 = -DX_INF, S1 = DX_INF;
         for (int dy = -R; dy <= R; ++dy) {
+            if (!__any(masks ? ((need >> (dy + R)) & 1ull) != 0 : true)) continue;
             const int w = wd[dy < 0 ? -dy : dy];
             const int ri = ci + dy * SW;
             const float* hr = Hr + ro[dy < 0 ? -dy : dy];
