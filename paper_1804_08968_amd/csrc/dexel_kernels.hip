@@ -428,8 +428,12 @@ struct SpreadOrder {
     }
 };
 
+// K1_COVERED: the fold stopped because the partial union holds one interval
+// containing the caller's range `cover` (see k_row_offset_fb).
+constexpr int K1_COVERED = -2;
+
 template <bool E, int AHEAD, class L>
-__device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
+__device__ int k1_column_e(const OpParams& P, int64_t c, const L& U, float2 cover) {
     int x, y;
     col_xy(P, c, &x, &y);
     const int64_t row = (int64_t)y * P.nx;
@@ -540,6 +544,7 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
         // time (independent loads, clamped to the column), so a visit waits
         // for memory about once per run instead of once per item.
         const float2 u = U.get(0);
+        if (cover.x <= cover.y && u.x <= cover.x && cover.y <= u.y) return K1_COVERED;
         int k0 = 0, k1 = cnt;
         if (f.x - h < u.x) {
             k0 = 1;
@@ -591,9 +596,12 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U) {
 
 constexpr int MERGE_AHEAD = 8;
 
+// `cover` (lo <= hi) lets the fold stop with K1_COVERED once the partial
+// union holds one interval containing [lo, hi]; (+inf, -inf) never stops it.
 template <int AHEAD = MERGE_AHEAD, class L>
-__device__ int k1_column(const OpParams& P, int64_t c, const L& U) {
-    return P.erode ? k1_column_e<true, AHEAD>(P, c, U) : k1_column_e<false, AHEAD>(P, c, U);
+__device__ int k1_column(const OpParams& P, int64_t c, const L& U,
+                         float2 cover = make_float2(DX_INF, -DX_INF)) {
+    return P.erode ? k1_column_e<true, AHEAD>(P, c, U, cover) : k1_column_e<false, AHEAD>(P, c, U, cover);
 }
 
 __device__ int64_t k1_bound(const OpParams& P, int64_t c) {
@@ -1660,6 +1668,15 @@ __global__ void __launch_bounds__(WG) k_row_offset(Pass Q) {
 // Replay of K1 for columns whose list overflowed: one lane per column with a
 // K1_FB_CAP-entry LDS list; a column that overflows it too goes on to the
 // slab replay (k_row_offset_heavy).
+//
+// A column the single-interval dilation test left (its gen[] is GEN_V0, its
+// lu[] (L, E1, S1, U)) is settled here if the fold reaches one interval
+// containing [E1, S1]: the union of [L, E1], V0 and [S1, U] is then all of
+// [L, U], so the column's dilation is [L, U] (what the test against V0 would
+// conclude) and the rest of its row need not be merged.  It is written like
+// a column the test settled, without V0: its gen[] is cleared, so the test
+// against V0 skips it and the second row-offset round evaluates its V0 if a
+// general column needs it.
 __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     __shared__ float2 lds[K1_FB_CAP * WG];
     if (Q.hdr->abort) return;
@@ -1669,10 +1686,38 @@ __global__ void __launch_bounds__(WG) k_row_offset_fb(Pass Q) {
     if (i >= cnt) return;
     const int64_t g = Q.ovf[(int64_t)ST_K1 * Q.gcols + i];
     const int s = find_shape(Q, g);
-    const OpParams P = make_op(Q, Q.shapes[s]);
+    const Shape& S = Q.shapes[s];
+    const OpParams P = make_op(Q, S);
     const int64_t c = g - Q.sbase[s];
+    const bool solid = S.fast == FAST_SOLID && gld(&S.gen[c]) == GEN_V0;
+    float4 lu = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (solid) lu = gld(&S.lu[c]);
     LdsList L{&lds[threadIdx.x], K1_FB_CAP};
-    const int n = k1_column(P, c, L);
+    const int n = k1_column(P, c, L, solid ? make_float2(lu.y, lu.z) : make_float2(DX_INF, -DX_INF));
+    // the settled columns' results, one allocation per wave
+    const bool done = n == K1_COVERED;
+    const unsigned long long dm = __ballot(done);
+    if (dm) {
+        const int lane = (int)(threadIdx.x & 63);
+        const int lead = __ffsll((unsigned long long)__ballot(1)) - 1;
+        unsigned long long base = 0;
+        if (lane == lead) base = atomicAdd(&Q.hdr->bumpC, (unsigned long long)__popcll(dm));
+        base = __shfl(base, lead, 64);
+        const unsigned long long end = base + (unsigned long long)__popcll(dm);
+        const bool ok = end <= (unsigned long long)P.cap;
+        if (!ok && lane == lead) {
+            note_need(P.hdr, end);
+            set_error(P.hdr, DEXEL_ERR_WORKSPACE);
+        }
+        if (done) {
+            const unsigned long long pos = base + (unsigned long long)__popcll(dm & ((1ull << lane) - 1ull));
+            gst(&S.gen[c], (uint8_t)0);
+            gst(&P.offC[c], (int64_t)pos);
+            gst(&P.cntC[c], ok ? 1 : 0);
+            if (ok) gst(&P.C[pos], make_float2(lu.x, lu.w));
+        }
+    }
+    if (done) return;
     if (n >= 0) emit_lane(P, c, L, n, 0, &Q.hdr->bumpA, P.offA, P.cntA, P.A);
     else push_overflow(Q, ST_K1H, g);  // long partial union: the slab replay
 }
@@ -3212,12 +3257,14 @@ __global__ void __launch_bounds__(WG) k_solid_b(Pass Q) {
     const int cnt = Q.hdr->novf[ST_SOLB];
     if ((int64_t)blockIdx.x * WG >= cnt) return;
     const int i = blockIdx.x * WG + threadIdx.x;
-    const bool live = i < cnt;
-    const int64_t g = Q.ovf[(int64_t)ST_SOLB * Q.gcols + (live ? i : 0)];
+    const bool live0 = i < cnt;
+    const int64_t g = Q.ovf[(int64_t)ST_SOLB * Q.gcols + (live0 ? i : 0)];
     const int s = find_shape(Q, g);
     const Shape& S = Q.shapes[s];
     const OpParams P = make_op(Q, S);
     const int64_t c = g - Q.sbase[s];
+    // (columns the row offset's replay settled have no V0 and gen[] 0)
+    const bool live = live0 && gld(&S.gen[c]) == GEN_V0;
     const float4 lu = gld(&S.lu[c]);  // (L, E1, S1, U)
     // gaps of [L, E1] U V0 U [S1, U] inside [L, U]; more than GCW_MAX: give up
     int ng = 0;
