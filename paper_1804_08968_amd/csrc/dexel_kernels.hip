@@ -377,22 +377,26 @@ __device__ __forceinline__ int visit_col(int x, int v) {
 }
 
 // Visit order of the row offset's second pass, one offset of [-R, R] per
-// call: first the spread magnitudes t_j = round(j R / 8) in the order j = 4,
-// 2, 6, 1, 3, 5, 7 (each magnitude once, as -t then +t), then 0, then the
-// other magnitudes from 1 outwards.  Neighbouring columns of a solid with
-// through-channels tend to share the channel's gaps, so a partial union of
-// near columns keeps every gap until a column far enough away fills it;
-// columns spread over the window first close most gaps early, and the later
-// columns take the short single-interval path (on a thin-walled gyroid at
-// r = 16, a CPU count of merge steps per column gave about a quarter of a
-// centre-out order's).
+// call: first the centre (the widest chords), then the spread magnitudes
+// t_j = round(j R / 8) in the order j = 4, 2, 6, 1, 3, 5, 7 (each magnitude
+// once, as -t then +t), then the other magnitudes from 1 outwards.
+// Neighbouring columns of a solid with through-channels tend to share the
+// channel's gaps, so a partial union of near columns keeps every gap until a
+// column far enough away fills it; columns spread over the window close
+// most gaps early, and the later columns take the short single-interval
+// path (on a thin-walled gyroid at r = 16, a CPU count of merge steps per
+// column gave about a quarter of a centre-out order's).  The centre comes
+// first because a far column's narrower chords, merged first with another
+// far column's of another phase, can leave more intervals than the lane's
+// list holds.
 struct SpreadOrder {
     int R;
-    int i = 0;    // next spread index (0 .. 6), 7: the centre next, 8: the rest
+    int i = 0;    // 0: the centre next, 1 .. 7: the next spread index + 1, 8: the rest
     int t = 0;    // the current magnitude
+    int r = 0;    // the last magnitude of the rest
     int pos = 0;  // +t is due next
-    __host__ __device__ static int mag(int R, int i) {
-        const int j = (0x7531624 >> (4 * i)) & 15;  // 4, 2, 6, 1, 3, 5, 7
+    __host__ __device__ static int mag(int R, int k) {
+        const int j = (0x7531624 >> (4 * k)) & 15;  // 4, 2, 6, 1, 3, 5, 7
         return (R * j + 4) >> 3;
     }
     __host__ __device__ bool spread(int tt) const {
@@ -405,10 +409,15 @@ struct SpreadOrder {
             pos = 0;
             return t;
         }
-        while (i < 7) {
-            const int tt = mag(R, i);
+        if (i == 0) {
+            i = 1;
+            return 0;
+        }
+        while (i < 8) {
+            const int k = i - 1;
+            const int tt = mag(R, k);
             bool dup = tt == 0;
-            for (int k = 0; k < i; ++k) dup = dup || mag(R, k) == tt;
+            for (int q = 0; q < k; ++q) dup = dup || mag(R, q) == tt;
             ++i;
             if (!dup) {
                 t = tt;
@@ -416,13 +425,9 @@ struct SpreadOrder {
                 return -t;
             }
         }
-        if (i == 7) {
-            i = 8;
-            t = 0;
-            return 0;
+        for (++r; r <= R && spread(r); ++r) {
         }
-        for (++t; t <= R && spread(t); ++t) {
-        }
+        t = r;
         pos = 1;
         return -t;
     }
