@@ -444,37 +444,41 @@ __device__ int k1_column_e(const OpParams& P, int64_t c, const L& U, float2 cove
     const int64_t row = (int64_t)y * P.nx;
     int n = 0;
     // Pass 1: the columns whose gaps are all within 2h contribute their hull
-    // alone, read from the column summary (coalesced across the wave).  On
-    // most inputs this leaves the union a single interval, so that pass 2
-    // takes the short path for nearly every column.  The union does not
-    // depend on the order its chords are inserted in.
-    {
-        float gp = gld(&P.gap[row + x]);
-        float4 en = gld(&P.ends[row + x]);
-        bool inr = true;
-        for (int v = 0; v <= 2 * P.R; ++v) {
-            const int t = (v + 1) >> 1;
-            const float h = gld(&P.H[t * t]);
-            const float gc = gp;
-            const float4 ec4 = en;
-            const bool inc = inr;
-            if (v < 2 * P.R) {
-                const int xn = visit_col(x, v + 1);
-                inr = xn >= 0 && xn < P.nx;
-                if (inr) {
-                    gp = gld(&P.gap[row + xn]);
-                    en = gld(&P.ends[row + xn]);
-                }
-            }
+    // alone, read from the column summary (coalesced across the wave, four
+    // visits' summaries loaded together).  On most inputs this leaves the
+    // union a single interval, so that pass 2 takes the short path for
+    // nearly every column.  The union does not depend on the order its
+    // chords are inserted in.
+    for (int v0 = 0; v0 <= 2 * P.R; v0 += 4) {
+        float gq[4], hq[4];
+        float4 eq[4];
+        bool iq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int v = v0 + q;
+            const int xn = visit_col(x, v);
+            const int t = min((v + 1) >> 1, P.R);
+            iq[q] = v <= 2 * P.R && xn >= 0 && xn < P.nx;
+            hq[q] = gld(&P.H[t * t]);
+            gq[q] = iq[q] ? gld(&P.gap[row + xn]) : -1.f;
+            eq[q] = iq[q] ? gld(&P.ends[row + xn]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float gc = gq[q], h = hq[q];
             const bool empty = gc < 0.f;
             // an empty column has no chord, its complement the whole line;
             // a complemented column's hull is the whole line too
-            if (!inc || (empty && !E) || !(empty || gc <= 2.f * h)) continue;
-            const float lo = E ? -DX_INF : ec4.x - h;
-            const float hi = E ? DX_INF : ec4.w + h;
+            if (!iq[q] || (empty && !E) || !(empty || gc <= 2.f * h)) continue;
+            const float lo = E ? -DX_INF : eq[q].x - h;
+            const float hi = E ? DX_INF : eq[q].w + h;
             n = lv_insert(U, n, lo, hi);
             if (n < 0) return -1;
         }
+    }
+    if (n == 1 && cover.x <= cover.y) {
+        const float2 u = U.get(0);
+        if (u.x <= cover.x && cover.y <= u.y) return K1_COVERED;
     }
     // Pass 2: the other columns, in the spread order.  Column pointers and
     // summaries of the next visit are loaded one visit ahead.
