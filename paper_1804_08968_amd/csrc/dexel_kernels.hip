@@ -3212,20 +3212,21 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
                 S1 = mn(S1, v.y + hh == U ? u.y - hh : DX_INF);
             });
         }
+        // (the inner disk's rows from the centre out, where the half-widths
+        // are largest; the wave stops once no lane still looks for a hull)
         bool hull = false;
-        if (E1 < S1) {
-            for (int dy = -R; dy <= R; ++dy) {
-                if (dy * dy > d2in) continue;
-                const int wf = wd[dy < 0 ? -dy : dy];
-                int w = wf;
-                while (w * w + dy * dy > d2in) --w;
-                const int ri = ci + dy * SW;
-                const float* hr = Hr + ro[dy < 0 ? -dy : dy] + wf;  // hr[dx]: H[dx^2 + dy^2]
-                for (int dx = -w; dx <= w; ++dx) {
-                    const float2 v = sab[ri + dx];
-                    const float hh = hr[dx];
-                    hull = hull || (sg[ri + dx] <= hh && v.x - hh <= E1 && v.y + hh >= S1);
-                }
+        for (int i = 0; i <= 2 * R; ++i) {
+            const int dy = (i & 1) ? -((i + 1) >> 1) : (i >> 1);  // 0, -1, 1, -2, 2, ...
+            if (dy * dy > d2in || !__any(E1 < S1 && !hull)) break;
+            const int wf = wd[dy < 0 ? -dy : dy];
+            int w = wf;
+            while (w * w + dy * dy > d2in) --w;
+            const int ri = ci + dy * SW;
+            const float* hr = Hr + ro[dy < 0 ? -dy : dy] + wf;  // hr[dx]: H[dx^2 + dy^2]
+            for (int dx = -w; dx <= w; ++dx) {
+                const float2 v = sab[ri + dx];
+                const float hh = hr[dx];
+                hull = hull || (sg[ri + dx] <= hh && v.x - hh <= E1 && v.y + hh >= S1);
             }
         }
         const bool live = x < P.nx;
