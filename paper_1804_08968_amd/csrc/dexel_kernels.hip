@@ -109,6 +109,9 @@ constexpr int WG = 64;
 // (typically heavy) replayed columns are spread over many waves instead of
 // being packed 64 to a wave and run in lockstep.
 constexpr int FALLBACK_BLOCKS = 1024;
+// The wide gap cut's columns (one wave each, little LDS) are spread over more
+// blocks: at the grid's x border a closing has thousands of them.
+constexpr int GAPW_BLOCKS = 8192;
 // K2 defers a column to its replay kernel when I(c) has more intervals than
 // this, K3 when V0(c) has; CAP_Z is the per-lane list capacity of the z-slab
 // replays.
@@ -4439,7 +4442,7 @@ static hipError_t pass_variant(const Pass& p, hipStream_t s, hipEvent_t* ev) {
     if (p.ntiles > 0 && p.nsolid > 0) {
         hipLaunchKernelGGL(k_solid_b, g, b, 0, s, p);
         hipLaunchKernelGGL(k_gap_cut, g, b, 0, s, p);
-        hipLaunchKernelGGL(k_gap_cut_wide, gf, b, 0, s, p);
+        hipLaunchKernelGGL(k_gap_cut_wide, dim3(GAPW_BLOCKS), b, 0, s, p);
         hipLaunchKernelGGL(k_fast_spread<SOLID_TY>, dim3((unsigned)p.ntiles), b, 0, s, p, (int)FAST_SOLID);
         // the row offsets the general columns' stages still need
         hipLaunchKernelGGL(k_reset_k1, dim3(1), dim3(64), 0, s, p);
