@@ -3050,20 +3050,29 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
         const float2* ctr = st + (ly + R) * SW + lane + R;
         float MA = -DX_INF, MB = DX_INF;
         bool thk = false;
-        for (int dy = -R; dy <= R; ++dy) {
-            const int w = wd[dy < 0 ? -dy : dy];
-            const float2* row = ctr + dy * SW;
-            const float* hr = Hr + ro[dy < 0 ? -dy : dy];
-            if (any_thick) {
-                sweep_row(row, hr, w, [&](float2 v, float hh) {
+        // the rows y - k and y + k together: they share their half-widths,
+        // and rounding is monotone, so max(fl(a + h), fl(b + h)) =
+        // fl(max(a, b) + h) (a column marked thick is left general whatever
+        // its MA and MB)
+        for (int k = 0; k <= R; ++k) {
+            const int w = wd[k];
+            const float* hr = Hr + ro[k];
+            if (k == 0) {
+                sweep_row(ctr, hr, w, [&](float2 v, float hh) {
                     thk |= v.x != v.x;
                     MA = mx(MA, v.x + hh);
                     MB = mn(MB, v.y - hh);
                 });
+            } else if (any_thick) {
+                sweep_row2(ctr + k * SW, ctr - k * SW, hr, w, [&](float2 a, float2 b, float hh) {
+                    thk |= (a.x != a.x) | (b.x != b.x);
+                    MA = mx(MA, mx(a.x, b.x) + hh);
+                    MB = mn(MB, mn(a.y, b.y) - hh);
+                });
             } else {
-                sweep_row(row, hr, w, [&](float2 v, float hh) {
-                    MA = mx(MA, v.x + hh);
-                    MB = mn(MB, v.y - hh);
+                sweep_row2(ctr + k * SW, ctr - k * SW, hr, w, [&](float2 a, float2 b, float hh) {
+                    MA = mx(MA, mx(a.x, b.x) + hh);
+                    MB = mn(MB, mn(a.y, b.y) - hh);
                 });
             }
         }
@@ -3181,7 +3190,10 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         if (y >= P.ny) break;  // wave-uniform
         const int ci = (ly + R) * SW + lane + R;
         // L and U over the whole stencil, row by row, with the rows whose
-        // chords reach L (mL) or U (mU): bit dy + R, while 2R + 1 <= 64
+        // chords reach L (mL) or U (mU): bit dy + R, while 2R + 1 <= 64.
+        // (Taking the rows y - k and y + k together, as the thin filter does,
+        // would name both rows of a pair in the masks and double the rows
+        // the E1 / S1 sweep visits.)
         float L = DX_INF, U = -DX_INF;
         uint64_t mL = 0, mU = 0;
         const bool masks = 2 * R + 1 <= 64;
