@@ -67,6 +67,7 @@ struct Layout {
     size_t gap, ends, offA, cntA, offI, cntI, offB, cntB, loB, hullB, offC, cntC, scanC, gen, need, lu;
     size_t A, I, B, tagB, C, ovf, arena, arena_tag, bsum, mid_ptr, mid_z, total;
     int64_t gcols1, gcols2, gmax, mid_cols;
+    int seed_slot;
     std::vector<size_t> lut_off;  // per item: byte offset of its radius table (shared per radius)
 };
 
@@ -105,6 +106,12 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     }
     L.gmax = L.gcols1 > L.gcols2 ? L.gcols1 : L.gcols2;
     const size_t g = (size_t)L.gmax, cp = (size_t)cap;
+    int rmax = 0;
+    for (const auto& it : items) rmax = it.R > rmax ? it.R : rmax;
+    L.seed_slot = rmax >= dexel::SEED_WIDE_R &&
+                          (long long)g * dexel::SEED_SLOT_WIDE * 9 <= dexel::SEED_WIDE_BYTES
+                      ? dexel::SEED_SLOT_WIDE
+                      : dexel::SEED_SLOT;
     L.hdr = take(256);
     L.shape_status = take(4 * n);
     L.zbase = take(8 * n);
@@ -142,8 +149,8 @@ Layout make_layout(const std::vector<ItemInfo>& items, int64_t cap) {
     L.lu = take(16 * g);
     L.A = take(8 * cp);
     L.I = take(8 * cp);
-    L.B = take(8 * g * dexel::SEED_SLOT);
-    L.tagB = take(g * dexel::SEED_SLOT);
+    L.B = take(8 * g * (size_t)L.seed_slot);
+    L.tagB = take(g * (size_t)L.seed_slot);
     L.C = take(8 * cp);
     L.ovf = take(4 * g * dexel::NSTAGE);
     L.arena = take(8 * cp);
@@ -446,6 +453,7 @@ dexel_status enqueue_batch(dexel_ctx* ctx, int32_t n, const dexel_batch_item* it
         q.I = (float2*)(w + L.I);
         q.B = (float2*)(w + L.B);
         q.tagB = (uint8_t*)(w + L.tagB);
+        q.seed_slot = L.seed_slot;
         q.C = (float2*)(w + L.C);
         q.cntC_g = (int32_t*)(w + L.cntC);
         q.scanC_g = (int64_t*)(w + L.scanC);

@@ -40,9 +40,17 @@ enum Stage {
 };
 
 // Seed slots per column: the seeds of a column are written at
-// B[g * SEED_SLOT ...] (g = global column); a column with more seeds is
-// recomputed into the workspace arena and its offset stored as -(pos + 1).
+// B[g * slot ...] (g = global column, slot = Pass::seed_slot); a column with
+// more seeds is recomputed into the workspace arena and its offset stored as
+// -(pos + 1).  The slot is SEED_SLOT entries, or SEED_SLOT_WIDE for a call
+// with a radius of at least SEED_WIDE_R whose wide slots take at most
+// SEED_WIDE_BYTES (at such radii many columns keep more than 64 seeds, and
+// each of them is evaluated twice; on large grids the wide slots would cost
+// more memory than the second evaluation costs time).
 constexpr int SEED_SLOT = 64;
+constexpr int SEED_SLOT_WIDE = 128;
+constexpr int SEED_WIDE_R = 24;
+constexpr long long SEED_WIDE_BYTES = 1ll << 30;
 
 // One shape of one pass, in device memory.  Per-column arrays are already
 // offset to the shape's first global column, so kernels index them with the
@@ -107,12 +115,13 @@ struct Pass {
     int32_t solid_lds;        // dynamic LDS bytes of k_solid_dilate (largest R of its shapes)
     int16_t nthin, nsolid;    // the pass has shapes with each fast path (0 / 1)
     int32_t k1_round;         // k_row_offset's launch: 1 before the dilation tests' V0 stage, 2 after
+    int32_t seed_slot;        // seed slot entries per column (SEED_SLOT or SEED_SLOT_WIDE)
     WsHeader* hdr;
     int32_t* shape_status;    // [items] per-item status (output capacity)
     int64_t cap;              // capacity (intervals) of A, I, B, C and of the arena
     float2* A;
     float2* I;
-    float2* B;                // [gcols * SEED_SLOT] seed slots, tags in tagB
+    float2* B;                // [gcols * seed_slot] seed slots, tags in tagB
     uint8_t* tagB;
     float2* C;
     int32_t* cntC_g;          // global views of the per-column result arrays (for the scan)

@@ -102,6 +102,7 @@ struct OpParams {
     int64_t* offC; int32_t* cntC; float2* C;
     float2* arena;
     uint8_t* arena_tag;
+    int32_t slot;  // seed slot entries per column
 };
 
 constexpr int WG = 64;
@@ -981,12 +982,12 @@ __device__ __forceinline__ SeedSpans seed_spans_of(const OpParams& P, int64_t ob
     SeedSpans r;
     const int lo = seed_lo(lov);
     if (ob >= 0) {
-        r.n[0] = min(lo, SEED_SLOT);
-        r.n[1] = min(cnt - lo, SEED_SLOT - r.n[0]);
+        r.n[0] = min(lo, P.slot);
+        r.n[1] = min(cnt - lo, P.slot - r.n[0]);
         r.s[0] = P.B + ob;
         r.t[0] = P.tagB + ob;
-        r.s[1] = P.B + ob + SEED_SLOT - r.n[1];
-        r.t[1] = P.tagB + ob + SEED_SLOT - r.n[1];
+        r.s[1] = P.B + ob + P.slot - r.n[1];
+        r.t[1] = P.tagB + ob + P.slot - r.n[1];
     } else {
         const int64_t a = -ob - 1;
         r.n[0] = lo;
@@ -1523,6 +1524,7 @@ __device__ __forceinline__ OpParams make_op(const Pass& Q, const Shape& S) {
     p.offC = S.offC; p.cntC = S.cntC; p.C = Q.C;
     p.arena = Q.arena;
     p.arena_tag = Q.arena_tag;
+    p.slot = Q.seed_slot;
     return p;
 }
 
@@ -1930,7 +1932,7 @@ __global__ void __launch_bounds__(WG) k_neighbour_heavy(Pass Q) {
 
 // One traversal per column: the seeds go to the column's slot.  A column
 // tested against a fragmented I(c) is deferred, and one with more than
-// SEED_SLOT seeds is redone, by k_seeds_fb.
+// P.slot seeds is redone, by k_seeds_fb.
 template <int CAP>
 __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
     __shared__ float2 lds[CAP * WG];
@@ -1947,18 +1949,18 @@ __global__ void __launch_bounds__(WG) k_seeds(Pass Q) {
             push_overflow(Q, ST_K2H, g);
         } else {
             LdsList U{&lds[threadIdx.x], CAP};
-            float2* slot = P.B + g * SEED_SLOT;
-            uint8_t* tslot = P.tagB + g * SEED_SLOT;
-            SeedSink o = sink_make(slot, tslot, slot + SEED_SLOT - 1, tslot + SEED_SLOT - 1, SEED_SLOT,
+            float2* slot = P.B + g * P.slot;
+            uint8_t* tslot = P.tagB + g * P.slot;
+            SeedSink o = sink_make(slot, tslot, slot + P.slot - 1, tslot + P.slot - 1, P.slot,
                                    0, 0, seed_split(P, pl.c));
             np = k2_column(P, pl.c, U, o);
             sink_flush(o);
-            gst(&P.offB[pl.c], g * SEED_SLOT);
+            gst(&P.offB[pl.c], g * P.slot);
             gst(&P.cntB[pl.c], np);
             gst(&P.loB[pl.c], o.nlo);
             gst(&P.hullB[2 * pl.c], o.hlo);
             gst(&P.hullB[2 * pl.c + 1], o.hhi);
-            if (np > SEED_SLOT) push_overflow(Q, ST_K2, g);
+            if (np > P.slot) push_overflow(Q, ST_K2, g);
         }
     }
     int tot;
