@@ -174,7 +174,7 @@ constexpr int DIRECT_RMAX = 16;
 // Tiled fast paths: tiles of THIN_TX x THIN_TY (thin erosion) or
 // THIN_TX x SOLID_TY (dilation test) output columns, radii up to THIN_RMAX.
 // LDS bytes a tile stages at integer radius R: per staged column one float2
-// (thin) or two float2 and a float (dilation), then the stencil's half-widths
+// (thin) or the first start and last end (dilation), then the stencil's half-widths
 // row by row (row |dy| = k holds H[dx^2 + k^2] for dx = -w_k .. w_k, padded
 // to a multiple of four floats, so that four of them are one 16-byte load;
 // (R + 1) (2R + 4) floats bound the table, and the kernels place what
@@ -189,7 +189,7 @@ inline int thin_lds_bytes(int R, int d2max) {
 }
 inline int solid_lds_bytes(int R, int d2max) {
     (void)d2max;
-    return (THIN_TX + 2 * R) * (SOLID_TY + 2 * R) * 20 + 4 * (R + 1) * (2 * R + 4) + 8 * (R + 1);
+    return (THIN_TX + 2 * R) * (SOLID_TY + 2 * R) * 8 + 4 * (R + 1) * (2 * R + 4) + 8 * (R + 1);
 }
 // need[] bits: stages of the general kernels a column runs.
 constexpr int NEED_UNION = 1;   // y union (the column is general itself)

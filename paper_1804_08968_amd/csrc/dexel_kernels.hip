@@ -3155,32 +3155,27 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
     const int x0 = (int)(tl % ntx) * THIN_TX, y0 = (int)(tl / ntx) * SOLID_TY;
     const int SW = THIN_TX + 2 * R, SH = SOLID_TY + 2 * R;
     float2* sab = (float2*)solid_lds;        // (af, bl)
-    float2* sba = sab + SW * SH;             // (bf, al)
-    float* sg = (float*)(sba + SW * SH);     // half the largest-gap bound
-    float* Hr = sg + SW * SH;                // 16-byte aligned: SW * SH is a multiple of 4
+    float* Hr = (float*)(sab + SW * SH);     // 16-byte aligned: SW * SH is even
     int* wd = (int*)(Hr + (P.R + 1) * (2 * P.R + 4));  // the table's bound
     int* ro = wd + (P.R + 1);
     stage_stencil(P, Hr, ro, wd);
-    // empty and off-grid columns stage (+inf, -inf), (+inf, -inf) and -1:
-    // they change no filter and are never a hull
+    // Only (af, bl) of each neighbourhood column is staged ((+inf, -inf) for
+    // an empty or off-grid one: it changes no filter and is never a hull);
+    // (bf, al) and the largest-gap bound are read from the column summaries
+    // at the few stencil points that need them, which leaves room in LDS for
+    // twice the resident tiles.
     for (int i = threadIdx.x; i < SW * SH; i += THIN_T) {
         const int sy = i / SW, sx = i - sy * SW;
         const int xx = x0 - R + sx, yy = y0 - R + sy;
-        float2 ab = make_float2(DX_INF, -DX_INF), ba = make_float2(DX_INF, -DX_INF);
-        float gp = -1.f;
+        float2 ab = make_float2(DX_INF, -DX_INF);
         if (xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
             const int64_t c = (int64_t)yy * P.nx + xx;
-            gp = gld(&P.gap[c]);
-            if (gp >= 0.f) {
+            if (gld(&P.gap[c]) >= 0.f) {
                 const float4 e4 = gld(&P.ends[c]);
                 ab = make_float2(e4.x, e4.w);
-                ba = make_float2(e4.y, e4.z);
-                gp *= 0.5f;
             }
         }
         sab[i] = ab;
-        sba[i] = ba;
-        sg[i] = gp;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -3215,40 +3210,55 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         }
         // E1 and S1: a row without a chord starting at L or ending at U adds
         // nothing to them, so the wave visits only the rows some lane's masks
-        // name (all of them if the masks do not cover the stencil); then a
-        // connecting hull in the stencil's inner part
+        // name (all of them if the masks do not cover the stencil), and a
+        // column's (bf, al) is read only where its chord starts at L or ends
+        // at U; then a connecting hull in the stencil's inner part
         const uint64_t need = masks ? (mL | mU) : ~0ull;
+        const bool empty = L > U;
         float E1 = -DX_INF, S1 = DX_INF;
         for (int dy = -R; dy <= R; ++dy) {
             if (!__any(masks ? ((need >> (dy + R)) & 1ull) != 0 : true)) continue;
             const int w = wd[dy < 0 ? -dy : dy];
             const int ri = ci + dy * SW;
-            const float* hr = Hr + ro[dy < 0 ? -dy : dy];
-            sweep_row2(sab + ri, sba + ri, hr, w, [&](float2 v, float2 u, float hh) {
-                E1 = mx(E1, v.x - hh == L ? u.x + hh : -DX_INF);
-                S1 = mn(S1, v.y + hh == U ? u.y - hh : DX_INF);
-            });
+            const float* hr = Hr + ro[dy < 0 ? -dy : dy] + w;  // hr[dx]: H[dx^2 + dy^2]
+            const int yy = y + dy;
+            for (int dx = -w; dx <= w; ++dx) {
+                const float2 v = sab[ri + dx];
+                const float hh = hr[dx];
+                const bool eL = v.x - hh == L, eU = v.y + hh == U;
+                const int xx = x + dx;
+                if ((eL || eU) && v.x != DX_INF && xx >= 0 && xx < P.nx && yy >= 0 && yy < P.ny) {
+                    const float4 e4 = gld(&P.ends[(int64_t)yy * P.nx + xx]);
+                    E1 = eL ? mx(E1, e4.y + hh) : E1;
+                    S1 = eU ? mn(S1, e4.z - hh) : S1;
+                }
+            }
         }
         // (the inner disk's rows from the centre out, where the half-widths
         // are largest; the wave stops once no lane still looks for a hull)
+        // (a column whose chords span [E1, S1] is a hull if its largest-gap
+        // bound, read here, is within 2 hh)
         bool hull = false;
         for (int i = 0; i <= 2 * R; ++i) {
             const int dy = (i & 1) ? -((i + 1) >> 1) : (i >> 1);  // 0, -1, 1, -2, 2, ...
-            if (dy * dy > d2in || !__any(E1 < S1 && !hull)) break;
+            if (dy * dy > d2in || !__any(E1 < S1 && !hull && !empty)) break;
             const int wf = wd[dy < 0 ? -dy : dy];
             int w = wf;
             while (w * w + dy * dy > d2in) --w;
             const int ri = ci + dy * SW;
             const float* hr = Hr + ro[dy < 0 ? -dy : dy] + wf;  // hr[dx]: H[dx^2 + dy^2]
+            const int yy = y + dy;
             for (int dx = -w; dx <= w; ++dx) {
                 const float2 v = sab[ri + dx];
                 const float hh = hr[dx];
-                hull = hull || (sg[ri + dx] <= hh && v.x - hh <= E1 && v.y + hh >= S1);
+                const int xx = x + dx;
+                if (!hull && v.x - hh <= E1 && v.y + hh >= S1 && v.x != DX_INF && xx >= 0 && xx < P.nx &&
+                    yy >= 0 && yy < P.ny)
+                    hull = 0.5f * gld(&P.gap[(int64_t)yy * P.nx + xx]) <= hh;
             }
         }
         const bool live = x < P.nx;
         const int64_t c = (int64_t)y * P.nx + x;
-        const bool empty = L > U;
         const bool done = live && (empty || E1 >= S1 || hull);
         const int outn = (done && !empty) ? 1 : 0;
         int tot;
