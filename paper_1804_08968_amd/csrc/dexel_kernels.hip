@@ -362,8 +362,8 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
 }
 
 // K1: V0 = union over |dx| <= R of the chords [a - H[dx^2], b + H[dx^2]] of
-// the row's columns x + dx, nearest columns first (largest chords first).
-// Within a column the chord starts and the chord ends are both
+// the row's columns x + dx (the hull columns first, then the others in the
+// spread order below).  Within a column the chord starts and the chord ends are both
 // non-decreasing (disjoint sorted intervals, one half-width h), so:
 // * if no gap of the column exceeds 2h, its chords chain into the single
 //   interval [first start - h, last end + h] (rounding is monotone, so every
@@ -375,6 +375,8 @@ __device__ int merge_column(const OpParams& P, const L& U, int n, int64_t b, int
 // * otherwise the column's chords are merged with the list (in an erosion,
 //   a one-interval column against a union of two rays only moves the rays).
 // Visit v of a row window, nearest columns first: x, x-1, x+1, x-2, x+2, ...
+// (the order of the row offset's hull pass and slab replay, and of the direct
+// evaluation's rows)
 __device__ __forceinline__ int visit_col(int x, int v) {
     const int t = (v + 1) >> 1;
     return v == 0 ? x : ((v & 1) ? x - t : x + t);
@@ -3121,9 +3123,11 @@ __global__ void __launch_bounds__(THIN_T) k_thin_erode(Pass Q) {
 // their distance are as a rule: a hull missed there only sends the column on
 // to the exact evaluation.
 // k_solid_dilate evaluates these filters on LDS-staged tiles of
-// THIN_TX x SOLID_TY output columns ((af, bl), (bf, al) and half the
-// largest-gap bound of each neighbourhood column); every other column goes
-// to the row offset's lane replay (its V0 is needed) and then to k_solid_b.
+// THIN_TX x SOLID_TY output columns ((af, bl) of each neighbourhood column;
+// (bf, al) and the largest-gap bound come from the column summaries where
+// needed); every other column goes to the row offset's lane replay, which
+// settles most of them as soon as their partial row union spans [E1, S1],
+// and the rest, with V0, to k_solid_b.
 //
 // k_solid_b tests a column against V0(c) = [L0 .. U0], the union of the
 // chords of its own row: the union is [L, U] minus the points of the open
