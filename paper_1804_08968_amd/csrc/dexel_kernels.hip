@@ -3199,6 +3199,8 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         uint64_t mL = 0, mU = 0;
         const bool masks = 2 * R + 1 <= 64;
         for (int dy = -R; dy <= R; ++dy) {
+            // a row off the grid holds only empty cells (all lanes share y)
+            if (y + dy < 0 || y + dy >= P.ny) continue;
             const int w = wd[dy < 0 ? -dy : dy];
             const float* hr = Hr + ro[dy < 0 ? -dy : dy];
             float rL = DX_INF, rU = -DX_INF;
@@ -3221,6 +3223,7 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         const bool empty = L > U;
         float E1 = -DX_INF, S1 = DX_INF;
         for (int dy = -R; dy <= R; ++dy) {
+            if (y + dy < 0 || y + dy >= P.ny) continue;
             if (!__any(masks ? ((need >> (dy + R)) & 1ull) != 0 : true)) continue;
             const int w = wd[dy < 0 ? -dy : dy];
             const int ri = ci + dy * SW;
@@ -3246,6 +3249,7 @@ __global__ void __launch_bounds__(THIN_T) k_solid_dilate(Pass Q) {
         for (int i = 0; i <= 2 * R; ++i) {
             const int dy = (i & 1) ? -((i + 1) >> 1) : (i >> 1);  // 0, -1, 1, -2, 2, ...
             if (dy * dy > d2in || !__any(E1 < S1 && !hull && !empty)) break;
+            if (y + dy < 0 || y + dy >= P.ny) continue;
             const int wf = wd[dy < 0 ? -dy : dy];
             int w = wf;
             while (w * w + dy * dy > d2in) --w;
